@@ -1,0 +1,275 @@
+"""FP64 CPU oracle for the MPCD+MD solvent path -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The product package never
+imports it and shares no code with it.
+
+The arithmetic lives in ``rmp_oracle.c`` (plain C, FP64, contraction off);
+this module only marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+MAXC = 32
+PTABLE = 1024
+
+F_DISPLACEMENT, F_RATTLE, F_NONFINITE, F_INIT = 1, 2, 4, 8
+
+
+def build(verbose=False) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, OpenMP)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
+           os.path.join(_HERE, "rmp_oracle.c"), "-o", _SO + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("L", C.c_int32 * 3), ("rule", C.c_int32), ("n_solvent", C.c_int64),
+        ("kT", C.c_double), ("mass", C.c_double), ("dt", C.c_double),
+        ("alpha", C.c_double), ("skin", C.c_double), ("cat_prob", C.c_double),
+        ("bulk_rate", C.c_double), ("n_colloids", C.c_int32), ("n_bonds", C.c_int32),
+        ("cx", (C.c_double * 3) * MAXC), ("cmass", C.c_double * MAXC),
+        ("sigma", C.c_double * MAXC), ("epsA", C.c_double * MAXC),
+        ("epsB", C.c_double * MAXC), ("catalytic", C.c_int32 * MAXC),
+        ("ctype", C.c_int32 * MAXC), ("eps_cc", (C.c_double * 2) * 2),
+        ("bond_a", C.c_int32 * MAXC), ("bond_b", C.c_int32 * MAXC),
+        ("bond_d", C.c_double * MAXC),
+    ]
+
+
+class Obs(C.Structure):
+    _fields_ = [
+        ("momentum", C.c_double * 3), ("ke_solvent", C.c_double),
+        ("ke_colloid", C.c_double), ("potential", C.c_double),
+        ("temperature", C.c_double), ("e_rxn", C.c_double),
+        ("n_A", C.c_int64), ("n_B", C.c_int64), ("n_cat_flips", C.c_int64),
+        ("n_bulk_flips", C.c_int64), ("md_step", C.c_int64),
+        ("coll_step", C.c_int64), ("n_candidates", C.c_int64),
+        ("n_cells_T", C.c_int64), ("flags", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = C.CDLL(_SO)
+        P, D, I64, I32, U64 = C.c_void_p, C.c_double, C.c_int64, C.c_int32, C.c_uint64
+        L.orc_create.restype = P
+        L.orc_create.argtypes = [C.POINTER(Params), U64]
+        L.orc_destroy.argtypes = [P]
+        L.orc_init.argtypes = [P]
+        L.orc_set_state.argtypes = [P, P, P, P, P, P, P, I64, I64]
+        L.orc_get_state.argtypes = [P, P, P, P, P, P, P, P, P, P]
+        L.orc_run.argtypes = [P, I32, I32]
+        L.orc_interval.argtypes = [P, I32, I32]
+        L.orc_collide.argtypes = [P, I32]
+        L.orc_observables.argtypes = [P, C.POINTER(Obs)]
+        L.orc_candidates.restype = I64
+        L.orc_candidates.argtypes = [P, P, I64]
+        L.orc_forces.argtypes = [P, P]
+        L.orc_build_list.argtypes = [P, I32]
+        L.orc_forces_allpairs.argtypes = [P, P, P]
+        L.orc_cell_keys.argtypes = [P, P, P]
+        L.orc_shift.argtypes = [P, I64, P]
+        L.orc_last_cells.restype = I64
+        L.orc_last_cells.argtypes = [P, P, I64]
+        L.orc_philox.argtypes = [P, P, P]
+        L.orc_wca.argtypes = [D, D, D, C.POINTER(D), C.POINTER(D)]
+        L.orc_tree_sum.restype = D
+        L.orc_tree_sum.argtypes = [P, I64]
+        L.orc_marsaglia.argtypes = [U64, I64, I64, P]
+        L.orc_rotate.argtypes = [P, D, D, P, P]
+        L.orc_ptable.argtypes = [D, D, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def make_params(p: dict) -> Params:
+    q = Params()
+    for d in range(3):
+        q.L[d] = int(p["L"][d])
+    q.rule = {"srd": 0, "at": 1}[p.get("rule", "srd")]
+    q.n_solvent = int(p["n_solvent"])
+    q.kT, q.mass, q.dt = p["kT"], p["mass"], p["dt"]
+    q.alpha, q.skin = p["alpha"], p["skin"]
+    q.cat_prob, q.bulk_rate = p["cat_prob"], p["bulk_rate"]
+    cols = p["colloids"]
+    if len(cols) > MAXC:
+        raise ValueError("too many colloids")
+    q.n_colloids = len(cols)
+    for c, col in enumerate(cols):
+        for d in range(3):
+            q.cx[c][d] = col["x"][d]
+        q.cmass[c], q.sigma[c] = col["mass"], col["sigma"]
+        q.epsA[c], q.epsB[c] = col["eps_A"], col["eps_B"]
+        q.catalytic[c] = int(col["catalytic"])
+        q.ctype[c] = int(col["type"])
+    for a in range(2):
+        for b in range(2):
+            q.eps_cc[a][b] = p["eps_cc"][a][b]
+    q.n_bonds = len(p["bonds"])
+    for k, (a, b, dd) in enumerate(p["bonds"]):
+        q.bond_a[k], q.bond_b[k], q.bond_d[k] = a, b, dd
+    return q
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint64))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64))
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def wca(r2: float, sigma: float, eps: float):
+    coef, pot = C.c_double(), C.c_double()
+    lib().orc_wca(r2, sigma, eps, C.byref(coef), C.byref(pot))
+    return coef.value, pot.value
+
+
+def tree_sum(a) -> float:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return lib().orc_tree_sum(_ptr(a), a.size)
+
+
+def marsaglia(seed: int, coll_step: int, cell: int) -> np.ndarray:
+    n = np.zeros(3)
+    lib().orc_marsaglia(seed, coll_step, cell, _ptr(n))
+    return n
+
+
+def rotate(n, alpha: float, w) -> np.ndarray:
+    import math
+    n = np.ascontiguousarray(np.asarray(n, dtype=np.float64))
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    out = np.zeros(3)
+    lib().orc_rotate(_ptr(n), math.cos(alpha), math.sin(alpha), _ptr(w), _ptr(out))
+    return out
+
+
+def ptable(bulk_rate: float, tau: float) -> np.ndarray:
+    t = np.zeros(PTABLE)
+    lib().orc_ptable(bulk_rate, tau, _ptr(t))
+    return t
+
+
+class Oracle:
+    """One simulated system in the FP64 oracle."""
+
+    def __init__(self, params: dict, seed: int, init: bool = True):
+        self.params = params
+        self._p = make_params(params)
+        self.seed = int(seed)
+        self.h = lib().orc_create(C.byref(self._p), self.seed)
+        if not self.h:
+            raise ValueError("oracle rejected the parameters")
+        self.n = int(params["n_solvent"])
+        self.nc = len(params["colloids"])
+        if init:
+            lib().orc_init(self.h)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().orc_destroy(h)
+            self.h = None
+
+    def set_state(self, s: dict):
+        x = np.ascontiguousarray(s["x"], dtype=np.float64).reshape(3, self.n)
+        v = np.ascontiguousarray(s["v"], dtype=np.float64).reshape(3, self.n)
+        ids = np.ascontiguousarray(s["id"], dtype=np.uint32)
+        st = np.ascontiguousarray(s["state"], dtype=np.uint8)
+        X = np.ascontiguousarray(s["X"], dtype=np.float64).reshape(self.nc, 3) if self.nc else np.zeros((0, 3))
+        V = np.ascontiguousarray(s["V"], dtype=np.float64).reshape(self.nc, 3) if self.nc else np.zeros((0, 3))
+        X = np.ascontiguousarray(X)
+        V = np.ascontiguousarray(V)
+        lib().orc_set_state(self.h, _ptr(x), _ptr(v), _ptr(ids), _ptr(st), _ptr(X), _ptr(V),
+                            int(s.get("md_step", 0)), int(s.get("coll_step", 0)))
+
+    def get_state(self) -> dict:
+        x = np.zeros((3, self.n)); v = np.zeros((3, self.n))
+        ids = np.zeros(self.n, dtype=np.uint32); st = np.zeros(self.n, dtype=np.uint8)
+        X = np.zeros((self.nc, 3)); V = np.zeros((self.nc, 3)); F = np.zeros((self.nc, 3))
+        md, co = C.c_int64(), C.c_int64()
+        lib().orc_get_state(self.h, _ptr(x), _ptr(v), _ptr(ids), _ptr(st), _ptr(X), _ptr(V),
+                            _ptr(F), C.cast(C.pointer(md), C.c_void_p),
+                            C.cast(C.pointer(co), C.c_void_p))
+        return dict(x=x, v=v, id=ids, state=st, X=X, V=V, F=F,
+                    md_step=md.value, coll_step=co.value)
+
+    def run(self, n_md: int, n_collide: int):
+        if lib().orc_run(self.h, int(n_md), int(n_collide)) != 0:
+            raise ValueError("bad arguments")
+
+    def interval(self, n_md: int, collide: bool = True):
+        if lib().orc_interval(self.h, int(n_md), int(bool(collide))) != 0:
+            raise ValueError("bad arguments")
+
+    def collide(self, n_md: int):
+        if lib().orc_collide(self.h, int(n_md)) != 0:
+            raise ValueError("bad arguments")
+
+    def build_list(self, n_md: int):
+        lib().orc_build_list(self.h, int(n_md))
+
+    def observables(self) -> dict:
+        o = Obs()
+        lib().orc_observables(self.h, C.byref(o))
+        d = {k: getattr(o, k) for k, _ in Obs._fields_ if k != "pad"}
+        d["momentum"] = np.array(list(o.momentum))
+        return d
+
+    def candidates(self) -> np.ndarray:
+        n = lib().orc_candidates(self.h, None, 0)
+        idx = np.zeros(max(n, 1), dtype=np.int64)
+        lib().orc_candidates(self.h, _ptr(idx), n)
+        return idx[:n]
+
+    def forces(self) -> np.ndarray:
+        f = np.zeros((3, self.n))
+        lib().orc_forces(self.h, _ptr(f))
+        return f
+
+    def forces_allpairs(self):
+        f = np.zeros((3, self.n)); F = np.zeros((max(self.nc, 1), 3))
+        lib().orc_forces_allpairs(self.h, _ptr(f), _ptr(F))
+        return f, F[: self.nc]
+
+    def shift(self, coll_step: int) -> np.ndarray:
+        s = np.zeros(3)
+        lib().orc_shift(self.h, int(coll_step), _ptr(s))
+        return s
+
+    def cell_keys(self, shift) -> np.ndarray:
+        sh = np.ascontiguousarray(np.asarray(shift, dtype=np.float64))
+        k = np.zeros(self.n, dtype=np.uint32)
+        lib().orc_cell_keys(self.h, _ptr(sh), _ptr(k))
+        return k
+
+    def last_cells(self) -> np.ndarray:
+        m = lib().orc_last_cells(self.h, None, 0)
+        a = np.zeros(m, dtype=np.uint32)
+        lib().orc_last_cells(self.h, _ptr(a), m)
+        return a

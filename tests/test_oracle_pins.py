@@ -1,0 +1,618 @@
+"""Pins of the FP64 CPU oracle against facts fixed outside the oracle itself:
+a library implementation of the RNG, brute force on tiny inputs, a library
+stable sort, exact conservation laws of the collision, analytic special cases
+of rotations and ballistic motion, closed forms of MPCD transport theory and
+statistical laws of the reactions.
+
+Each test names the passage of the paper (section / equation) whose
+statement it pins.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ALPHA = math.radians(130.0)
+
+
+# --------------------------------------------------------------------------
+# Philox4x64-10 ("Algorithms": counter-based RNG) vs numpy's implementation.
+# numpy's generator increments the counter before producing a block, so its
+# first block for counter c-1 is the Philox function at counter c.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("ctr,key", [
+    ([1, 0, 0, 0], [0, 0]),
+    ([5, 17, 3, 0], [0x524D50434D44, 2]),
+    ([2**63 + 11, 2**40, 99, 7], [2**64 - 1, 12345]),
+    ([123456789, 2**32 - 1, 0, 0], [42, 7]),
+])
+def test_philox_matches_numpy(ctr, key):
+    c = list(ctr)
+    c[0] -= 1
+    ref = np.random.Philox(counter=np.array(c, dtype=np.uint64),
+                           key=np.array(key, dtype=np.uint64)).random_raw(4)
+    got = oracle.philox(ctr, key)
+    assert np.array_equal(np.asarray(ref, dtype=np.uint64), got)
+
+
+# --------------------------------------------------------------------------
+# WCA potential ("Algorithms", cut-off 12-6 LJ equation)
+# --------------------------------------------------------------------------
+def test_wca_known_values_and_cutoff():
+    for sigma, eps in [(1.0, 1.0), (2.0, 0.5), (4.0, 1.0)]:
+        coef, pot = oracle.wca(sigma * sigma, sigma, eps)
+        # at r = sigma: V = eps and |F| = 24 eps / sigma (textbook LJ values)
+        assert pot == pytest.approx(eps, rel=1e-15)
+        assert coef * sigma == pytest.approx(24.0 * eps / sigma, rel=1e-14)
+        rc = 2.0 ** (1.0 / 6.0) * sigma
+        coef, pot = oracle.wca(rc * rc, sigma, eps)
+        assert abs(pot) < 1e-13 * eps and abs(coef) < 1e-12 * eps
+
+
+def test_wca_force_is_minus_gradient():
+    sigma, eps = 4.0, 0.7
+    for r in np.linspace(3.2, 4.45, 17):
+        h = 1e-6
+        _, vp = oracle.wca((r + h) ** 2, sigma, eps)
+        _, vm = oracle.wca((r - h) ** 2, sigma, eps)
+        coef, _ = oracle.wca(r * r, sigma, eps)
+        dvdr = (vp - vm) / (2 * h)
+        assert coef * r == pytest.approx(-dvdr, rel=2e-6, abs=1e-8)
+
+
+# --------------------------------------------------------------------------
+# Fixed reduction tree (reading: pairwise over list positions, zero padded)
+# --------------------------------------------------------------------------
+def _tree_py(a):
+    a = list(a)
+    if not a:
+        return 0.0
+    p = 1
+    while p < len(a):
+        p *= 2
+    a += [0.0] * (p - len(a))
+    while len(a) > 1:
+        a = [a[2 * i] + a[2 * i + 1] for i in range(len(a) // 2)]
+    return a[0]
+
+
+def test_tree_sum_order():
+    rng = np.random.default_rng(3)
+    for n in [1, 2, 3, 5, 63, 64, 65, 1000]:
+        a = rng.normal(size=n) * 10.0 ** rng.integers(-8, 8, size=n)
+        assert oracle.tree_sum(a) == _tree_py(a)
+    # order matters: pairwise != sequential for this input
+    a = [1e16, 1.0, -1e16, 1.0]
+    assert oracle.tree_sum(a) == (1e16 + 1.0) + (-1e16 + 1.0)
+    assert oracle.tree_sum(a) != ((1e16 + 1.0) - 1e16) + 1.0
+    ints = rng.integers(-1000, 1000, size=777).astype(float)
+    assert oracle.tree_sum(ints) == math.fsum(ints)
+
+
+# --------------------------------------------------------------------------
+# Rotation and axis ("Algorithms": original MPCD collision rule)
+# --------------------------------------------------------------------------
+def test_marsaglia_axis_unit_and_isotropic():
+    ns = np.array([oracle.marsaglia(77, 3, c) for c in range(20000)])
+    assert np.allclose((ns ** 2).sum(1), 1.0, atol=4e-16)
+    assert np.all(np.abs(ns.mean(0)) < 0.02)
+    assert np.allclose((ns ** 2).mean(0), 1.0 / 3.0, atol=0.01)
+
+
+def test_rotation_properties():
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        n = rng.normal(size=3); n /= np.linalg.norm(n)
+        w = rng.normal(size=3)
+        rw = oracle.rotate(n, ALPHA, w)
+        assert np.linalg.norm(rw) == pytest.approx(np.linalg.norm(w), rel=1e-14)
+        assert np.dot(rw, n) == pytest.approx(np.dot(w, n), abs=1e-14 * np.linalg.norm(w))
+        wp = w - np.dot(w, n) * n
+        rp = rw - np.dot(rw, n) * n
+        # right-handed rotation by +alpha about n
+        ang = math.atan2(np.dot(np.cross(wp, rp), n), np.dot(wp, rp))
+        assert ang == pytest.approx(ALPHA, abs=1e-12)
+        assert np.allclose(oracle.rotate(n, ALPHA, n), n, atol=1e-15)
+        assert np.allclose(oracle.rotate(n, 0.0, w), w, rtol=0, atol=1e-15 * np.abs(w).max())
+        # alpha = pi: reflection through the axis
+        assert np.allclose(oracle.rotate(n, math.pi, w), 2 * np.dot(n, w) * n - w, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Binning and the stable counting sort ("Algorithms": sorting of solvent
+# particles in cells, shared by collision and cell lists; Table 1's
+# particle_system sorting routine)
+# --------------------------------------------------------------------------
+def _no_colloid(L=(6, 5, 4), rho=7, **kw):
+    p = W.base_params(L=L, rho=rho, dt=0.01, n_md=3, **kw)
+    return p
+
+
+def test_cell_keys_contain_particle():
+    p = _no_colloid()
+    o = oracle.Oracle(p, 11)
+    s = o.get_state()
+    L = np.array(p["L"], dtype=float)
+    for step in range(5):
+        sh = o.shift(step)
+        assert np.all((sh >= 0) & (sh < 1))
+        keys = o.cell_keys(sh)
+        cx = keys % p["L"][0]
+        cy = (keys // p["L"][0]) % p["L"][1]
+        cz = keys // (p["L"][0] * p["L"][1])
+        c = np.stack([cx, cy, cz]).astype(float)
+        rel = np.mod(s["x"] - sh[:, None] - c, L[:, None])
+        assert np.all((rel >= 0) & (rel < 1))
+
+
+def test_sort_is_stable_argsort():
+    p = _no_colloid()
+    o = oracle.Oracle(p, 12)
+    s0 = o.get_state()
+    sh = o.shift(0)
+    keys = o.cell_keys(sh)
+    o.collide(3)
+    s1 = o.get_state()
+    perm = np.argsort(keys, kind="stable")
+    assert np.array_equal(s1["id"], s0["id"][perm])
+    assert np.array_equal(s1["x"], s0["x"][:, perm])
+    start = o.last_cells()
+    ncell = int(np.prod(p["L"]))
+    assert np.array_equal(start, np.concatenate([[0], np.cumsum(np.bincount(keys, minlength=ncell))]))
+
+
+# --------------------------------------------------------------------------
+# Collision conservation laws and special cases
+# --------------------------------------------------------------------------
+def _cells_by_id(o, s_before):
+    s1 = o.get_state()
+    start = o.last_cells()
+    inv = np.empty_like(s_before["id"], dtype=np.int64)
+    inv[s_before["id"]] = np.arange(s_before["id"].size)
+    before_v = s_before["v"][:, inv[s1["id"]]]
+    return s1, start, before_v
+
+
+@pytest.mark.parametrize("rule", ["srd", "at"])
+def test_collision_conserves_cell_momentum_and_energy(rule):
+    p = _no_colloid(rule=rule)
+    o = oracle.Oracle(p, 13)
+    s0 = o.get_state()
+    o.collide(3)
+    s1, start, vb = _cells_by_id(o, s0)
+    va = s1["v"]
+    for c in range(start.size - 1):
+        b, e = start[c], start[c + 1]
+        if e - b == 0:
+            continue
+        scale = np.abs(vb[:, b:e]).sum() + 1.0
+        assert np.allclose(va[:, b:e].sum(1), vb[:, b:e].sum(1), atol=64 * 2.2e-16 * scale)
+        if rule == "srd":
+            assert (va[:, b:e] ** 2).sum() == pytest.approx((vb[:, b:e] ** 2).sum(), rel=1e-13)
+            u = vb[:, b:e].mean(1, keepdims=True)
+            assert np.allclose(np.linalg.norm(va[:, b:e] - u, axis=0),
+                               np.linalg.norm(vb[:, b:e] - u, axis=0), rtol=1e-12, atol=1e-13)
+
+
+def test_collision_single_particle_cells_unchanged_and_two_particle_rotation():
+    p = W.base_params(L=(3, 3, 3), rho=1, dt=0.01, n_md=1)
+    p["n_solvent"] = 3
+    o = oracle.Oracle(p, 14, init=False)
+    # two particles at the same point (same cell for any shift), one alone
+    x = np.array([[0.5, 0.5, 2.5], [0.5, 0.5, 2.5], [0.5, 0.5, 2.5]])
+    v = np.array([[1.0, -0.5, 0.3], [0.2, 0.7, -1.1], [0.0, 0.4, 2.0]])
+    o.set_state(dict(x=x, v=v, id=np.arange(3, dtype=np.uint32),
+                     state=np.zeros(3, np.uint8), X=np.zeros((0, 3)), V=np.zeros((0, 3))))
+    sh = o.shift(0)
+    keys = o.cell_keys(sh)
+    o.collide(1)
+    s = o.get_state()
+    order = np.argsort(s["id"])
+    va = s["v"][:, order]
+    assert np.array_equal(va[:, 2], v[:, 2])                 # alone: unchanged
+    n = oracle.marsaglia(14, 0, int(keys[0]))
+    rel_b = v[:, 0] - v[:, 1]
+    rel_a = va[:, 0] - va[:, 1]
+    assert np.linalg.norm(rel_a) == pytest.approx(np.linalg.norm(rel_b), rel=1e-14)
+    wp = rel_b - np.dot(rel_b, n) * n
+    rp = rel_a - np.dot(rel_a, n) * n
+    ang = math.atan2(np.dot(np.cross(wp, rp), n), np.dot(wp, rp))
+    assert ang == pytest.approx(ALPHA, abs=1e-12)
+    assert np.allclose(va[:, :2].sum(1), v[:, :2].sum(1), atol=1e-15)
+    obs = o.observables()
+    # T = (1/(3 N_c)) * sum |v - u|^2 / (N - 1) with one cell of two particles
+    assert obs["n_cells_T"] == 1
+    assert obs["temperature"] == pytest.approx(np.dot(rel_b, rel_b) / 2.0 / 3.0, rel=1e-14)
+
+
+def test_collision_alpha_zero_and_pi():
+    for alpha, check in [(0.0, "identity"), (math.pi, "reflect")]:
+        p = _no_colloid()
+        p["alpha"] = alpha
+        o = oracle.Oracle(p, 15)
+        s0 = o.get_state()
+        sh = o.shift(0)
+        keys0 = o.cell_keys(sh)
+        o.collide(3)
+        s1, start, vb = _cells_by_id(o, s0)
+        if check == "identity":
+            assert np.allclose(s1["v"], vb, rtol=0, atol=1e-14)
+        else:
+            inv = np.empty(s0["id"].size, np.int64)
+            inv[s0["id"]] = np.arange(s0["id"].size)
+            keys = keys0[inv[s1["id"]]]
+            for c in range(start.size - 1):
+                b, e = start[c], start[c + 1]
+                if e - b < 2:
+                    continue
+                n = oracle.marsaglia(15, 0, int(keys[b]))
+                u = vb[:, b:e].mean(1, keepdims=True)
+                w = vb[:, b:e] - u
+                ref = u + 2 * (n[:, None] * (n @ w)[None, :]) - w
+                assert np.allclose(s1["v"][:, b:e], ref, atol=1e-13)
+
+
+def test_collision_galilean_invariance():
+    p = _no_colloid()
+    o1 = oracle.Oracle(p, 16)
+    s = o1.get_state()
+    U = np.array([0.375, -1.25, 0.5])       # exactly representable boost
+    s2 = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in s.items()}
+    s2["v"] = s["v"] + U[:, None]
+    o2 = oracle.Oracle(p, 16, init=False)
+    o2.set_state(s2)
+    o1.collide(3); o2.collide(3)
+    a, b = o1.get_state(), o2.get_state()
+    assert np.array_equal(a["id"], b["id"])
+    assert np.allclose(b["v"] - U[:, None], a["v"], atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Colloid-solvent forces over the Verlet list vs brute force
+# --------------------------------------------------------------------------
+def _brute_forces(s, p):
+    L = np.array(p["L"], dtype=float)[:, None]
+    f = np.zeros_like(s["x"])
+    F = np.zeros((len(p["colloids"]), 3))
+    for c, col in enumerate(p["colloids"]):
+        Xw = np.mod(np.asarray(s["X"][c]), L[:, 0])[:, None]
+        d = s["x"] - Xw
+        d -= L * np.round(d / L)
+        r = np.sqrt((d * d).sum(0))
+        eps = np.where(s["state"] & 1, col["eps_B"], col["eps_A"])
+        sig = col["sigma"]
+        rc = 2 ** (1 / 6) * sig
+        inside = r < rc
+        # -dV/dr for V = 4 eps ((s/r)^12 - (s/r)^6 + 1/4)
+        mag = np.where(inside, 4 * eps * (12 * sig ** 12 / r ** 13 - 6 * sig ** 6 / r ** 7), 0.0)
+        g = mag * d / np.where(inside, r, 1.0)
+        f += g
+        F[c] -= g.sum(1)
+    return f, F
+
+
+@pytest.mark.parametrize("where", ["centre", "corner"])
+def test_forces_match_brute_force_and_list_is_sound(where):
+    p = W.dimer_system(L=16, rho=6, n_md=25, seed=3)
+    if where == "corner":
+        # dimer straddling the periodic boundary in every direction
+        # (unwrapped coordinates: the bond vector is unchanged)
+        for c in p["colloids"]:
+            c["x"] = tuple(np.asarray(c["x"]) - 7.7)
+    o = oracle.Oracle(p, 17)
+    s = W.random_state(p, 18, species_B_fraction=0.4)
+    o.set_state(s)
+    for it in range(4):
+        o.build_list(25)
+        st = o.get_state()
+        f = o.forces()
+        fb, Fb = _brute_forces(st, p)
+        scale = np.abs(fb).max()
+        assert np.allclose(f, fb, rtol=1e-11, atol=1e-12 * scale)
+        assert np.allclose(st["F"], Fb, rtol=1e-9, atol=1e-10 * np.abs(fb).sum())
+        # list soundness: every interaction during the interval is in the list
+        cand = set(o.candidates().tolist())
+        o.interval(25, collide=False)
+        fa, _ = o.forces_allpairs()
+        nonzero = np.nonzero(np.abs(fa).sum(0))[0]
+        assert set(nonzero.tolist()) <= cand
+        o.interval(25, collide=True)
+    assert o.observables()["flags"] == 0
+
+
+# --------------------------------------------------------------------------
+# Velocity-Verlet + exact RATTLE ("Algorithms": velocity-Verlet; RATTLE
+# exact for the dimer)
+# --------------------------------------------------------------------------
+def test_rattle_holds_bond_and_velocity_constraint():
+    p = W.dimer_system(L=16, rho=6, n_md=10, seed=4)
+    p["bulk_rate"] = 0.0
+    o = oracle.Oracle(p, 19)
+    d = p["bonds"][0][2]
+    for _ in range(30):
+        o.interval(10, collide=True)
+        s = o.get_state()
+        r = s["X"][0] - s["X"][1]
+        assert np.linalg.norm(r) == pytest.approx(d, rel=1e-13)
+        dv = s["V"][0] - s["V"][1]
+        assert abs(np.dot(dv, r)) < 1e-12 * np.linalg.norm(dv) * d + 1e-15
+
+
+def _energy(o):
+    ob = o.observables()
+    return ob["ke_solvent"] + ob["ke_colloid"] + ob["potential"]
+
+
+def test_velocity_verlet_energy_error_scales_dt2():
+    base = W.dimer_system(L=16, rho=6, n_md=1, seed=5, bulk_rate=0.0, cat_prob=0.0)
+    s0 = W.random_state(base, 20)
+    amps = []
+    for dt in (0.01, 0.005):
+        p = dict(base); p["dt"] = dt
+        o = oracle.Oracle(p, 21, init=False)
+        o.set_state(s0)
+        o.build_list(1)
+        e0 = _energy(o)
+        es = []
+        nsteps = int(round(1.0 / dt))
+        for _ in range(nsteps):
+            o.interval(1, collide=False)
+            es.append(_energy(o) - e0)
+        amps.append(np.abs(es).max())
+    ratio = amps[0] / amps[1]
+    assert 3.0 < ratio < 5.0
+
+
+@pytest.mark.parametrize("rule", ["srd", "at"])
+def test_total_momentum_conserved_and_energy_bounded(rule):
+    p = W.dimer_system(L=16, rho=6, n_md=20, seed=6, bulk_rate=0.0, cat_prob=0.0)
+    p["rule"] = rule
+    o = oracle.Oracle(p, 22)
+    o.build_list(20)
+    P0 = o.observables()["momentum"]
+    e0 = _energy(o)
+    for _ in range(20):
+        o.run(20, 1)
+    ob = o.observables()
+    scale = np.sqrt(2 * ob["ke_solvent"] * p["n_solvent"])
+    assert np.allclose(ob["momentum"], P0, atol=1e-11 * scale)
+    if rule == "srd":
+        assert abs(_energy(o) - e0) < 2e-4 * e0
+
+
+# --------------------------------------------------------------------------
+# Equilibrium and transport ("Implementation": validation by the velocity
+# distribution and the viscosity); closed forms of MPCD kinetic theory
+# (Kikuchi et al. 2003) for the rotation rule.
+# --------------------------------------------------------------------------
+def test_maxwell_boltzmann_from_non_gaussian_start():
+    from scipy import stats
+    p = _no_colloid(L=(10, 10, 10), rho=10)
+    o = oracle.Oracle(p, 23)
+    s = o.get_state()
+    rng = np.random.default_rng(1)
+    dirs = rng.normal(size=s["v"].shape)
+    dirs /= np.linalg.norm(dirs, axis=0)
+    s["v"] = dirs * math.sqrt(3.0)              # fixed speed, kT = 1
+    s["v"] -= s["v"].mean(1, keepdims=True)
+    o.set_state(s)
+    o.run(10, 30)
+    v = o.get_state()["v"]
+    T = (v ** 2).mean()
+    for d in range(3):
+        assert stats.kstest(v[d] / math.sqrt(T), "norm").pvalue > 1e-3
+    assert o.observables()["temperature"] == pytest.approx(T, rel=0.02)
+
+
+def _closed_forms(tau, M=10, alpha=ALPHA):
+    g = M - 1 + math.exp(-M)
+    ca, c2 = math.cos(alpha), math.cos(2 * alpha)
+    D = tau / 2 * (3 * M / ((1 - ca) * g) - 1)
+    nu = tau / 2 * (5 * M / (g * (2 - ca - c2)) - 1) + (1 / (18 * tau)) * (g / M) * (1 - ca)
+    return D, nu
+
+
+@pytest.mark.slow
+def test_self_diffusion_closed_form():
+    tau = 0.5
+    p = W.base_params(L=(10, 10, 10), rho=10, dt=tau, n_md=1)
+    o = oracle.Oracle(p, 24)
+    L = 10.0
+    prev = o.get_state()["x"][:, np.argsort(o.get_state()["id"])]
+    disp = np.zeros_like(prev)
+    msd = []
+    for _ in range(300):
+        o.run(1, 1)
+        s = o.get_state()
+        cur = s["x"][:, np.argsort(s["id"])]
+        d = cur - prev
+        d -= L * np.round(d / L)
+        disp += d
+        prev = cur
+        msd.append((disp ** 2).sum(0).mean())
+    t = tau * np.arange(1, 301)
+    slope = np.polyfit(t[100:], np.array(msd)[100:], 1)[0]
+    D, _ = _closed_forms(tau)
+    assert slope / 6 == pytest.approx(D, rel=0.05)
+
+
+@pytest.mark.slow
+def test_shear_viscosity_closed_form():
+    tau, Lz = 0.5, 16
+    k = 2 * math.pi / Lz
+    nus = []
+    for seed in range(6):
+        p = W.base_params(L=(24, 24, Lz), rho=10, dt=tau, n_md=1)
+        o = oracle.Oracle(p, 200 + seed)
+        s = o.get_state()
+        s["v"][0] += 0.5 * np.sin(k * s["x"][2])
+        o.set_state(s)
+        ts, amps = [], []
+        for c in range(50):
+            o.run(1, 1)
+            s = o.get_state()
+            amps.append(2 * np.mean(s["v"][0] * np.sin(k * s["x"][2])))
+            ts.append((c + 1) * tau)
+        ts, amps = np.array(ts), np.array(amps)
+        m = (amps > 0.04) & (ts > 2)
+        nus.append(-np.polyfit(ts[m], np.log(amps[m]), 1)[0] / k ** 2)
+    _, nu = _closed_forms(tau)
+    assert np.mean(nus) == pytest.approx(nu, rel=0.06)
+
+
+# --------------------------------------------------------------------------
+# Reactions: RMPCD bulk B->A (Overview: bulk kinetics) and catalytic A->B
+# ("Applications": dimer motor chemistry; configuration `probability`)
+# --------------------------------------------------------------------------
+def test_bulk_reaction_statistics():
+    p = _no_colloid(L=(12, 12, 12), rho=10)
+    p["bulk_rate"] = 0.05
+    n_md = 10
+    tau = n_md * p["dt"]
+    o = oracle.Oracle(p, 25)
+    s = o.get_state()
+    s["state"][:] = 1
+    o.set_state(s)
+    expected, var, got = 0.0, 0.0, 0
+    for step in range(40):
+        st = o.get_state()
+        keys = o.cell_keys(o.shift(st["coll_step"]))
+        nB = np.bincount(keys[(st["state"] & 1) == 1], minlength=int(np.prod(p["L"])))
+        P = -np.expm1(-p["bulk_rate"] * tau * nB)
+        expected += P.sum(); var += (P * (1 - P)).sum()
+        before = o.observables()["n_B"]
+        o.collide(n_md)
+        got += before - o.observables()["n_B"]
+    assert abs(got - expected) < 4 * math.sqrt(var)
+    assert o.observables()["n_bulk_flips"] == got
+    t = 40 * tau
+    # weak-reaction limit: N_B(t) ~ N_B(0) exp(-k t)
+    assert o.observables()["n_B"] / p["n_solvent"] == pytest.approx(math.exp(-p["bulk_rate"] * t), rel=0.02)
+    tab = oracle.ptable(p["bulk_rate"], tau)
+    assert np.allclose(tab[:50], 1 - np.exp(-p["bulk_rate"] * tau * np.arange(50)), rtol=1e-14, atol=1e-17)
+
+
+def test_catalysis_ballistic_exit_times():
+    """Frozen catalytic sphere with eps = 0 (no force): particles move on
+    straight lines; an A particle becomes B at the first MD step at which it is
+    outside the cut-off sphere after having been inside."""
+    L = 20
+    p = W.base_params(L=(L, L, L), rho=1, dt=0.01, n_md=1)
+    W.add_colloid(p, (10.0, 10.0, 10.0), sigma=3.0, eps_A=0.0, eps_B=0.0,
+                  catalytic=True, mass=1e30)
+    rng = np.random.default_rng(7)
+    n = 300
+    p["n_solvent"] = n
+    rc = 2 ** (1 / 6) * 3.0
+    dirs = rng.normal(size=(3, n)); dirs /= np.linalg.norm(dirs, axis=0)
+    r0 = rng.uniform(0.5 * rc, 1.6 * rc, size=n)
+    x = 10.0 + dirs * r0
+    v = rng.normal(size=(3, n))
+    st = np.zeros(n, np.uint8)
+    st[:20] = 1                               # some B: never converted
+    o = oracle.Oracle(p, 26, init=False)
+    o.set_state(dict(x=x, v=v, id=np.arange(n, dtype=np.uint32), state=st,
+                     X=np.array([[10.0, 10.0, 10.0]]), V=np.zeros((1, 3))))
+    nsteps = 400
+    flip_step = np.full(n, -1)
+    for k in range(nsteps):
+        o.interval(1, collide=False)
+        s = o.get_state()
+        newly = (s["state"] & 1 == 1) & (flip_step < 0) & (np.arange(n) >= 20)
+        flip_step[newly] = k
+    # analytic: positions after k+1 steps are x0 + (k+1) dt v (straight line)
+    t = (np.arange(nsteps) + 1) * p["dt"]
+    pos = x[:, :, None] + v[:, :, None] * t[None, None, :]
+    r = np.sqrt(((pos - 10.0) ** 2).sum(0))
+    inside = r < rc
+    for i in range(20, n):
+        exp_step = -1
+        was_in = False
+        for k in range(nsteps):
+            if inside[i, k]:
+                was_in = True
+            elif was_in:
+                exp_step = k
+                break
+        margin = np.abs(r[i] - rc).min()
+        if margin < 1e-9:
+            continue                           # rounding-ambiguous crossing
+        assert flip_step[i] == exp_step, i
+    assert np.all(o.get_state()["state"][:20] & 1 == 1)
+    assert (flip_step >= 0).sum() > 50
+
+
+def test_catalysis_probability():
+    L = 20
+    p = W.base_params(L=(L, L, L), rho=1, dt=0.01, n_md=1)
+    W.add_colloid(p, (10.0, 10.0, 10.0), sigma=3.0, eps_A=0.0, eps_B=0.0,
+                  catalytic=True, mass=1e30)
+    p["cat_prob"] = 0.3
+    n = 4000
+    p["n_solvent"] = n
+    rng = np.random.default_rng(8)
+    dirs = rng.normal(size=(3, n)); dirs /= np.linalg.norm(dirs, axis=0)
+    x = 10.0 + dirs * 3.0
+    v = dirs * 2.0                              # radially outward
+    o = oracle.Oracle(p, 27, init=False)
+    o.set_state(dict(x=x, v=v, id=np.arange(n, dtype=np.uint32),
+                     state=np.zeros(n, np.uint8), X=np.array([[10.0] * 3]), V=np.zeros((1, 3))))
+    for _ in range(60):
+        o.interval(1, collide=False)
+    s = o.get_state()
+    frac = (s["state"] & 1).mean()
+    assert frac == pytest.approx(0.3, abs=4 * math.sqrt(0.3 * 0.7 / n))
+    assert np.all((s["state"] & 2) == 0)
+
+
+# --------------------------------------------------------------------------
+# Initialisation, determinism, resume
+# --------------------------------------------------------------------------
+def test_init_state():
+    p = W.sphere10()
+    o = oracle.Oracle(p, 28)
+    s = o.get_state()
+    assert np.array_equal(s["id"], np.arange(p["n_solvent"], dtype=np.uint32))
+    assert np.all((s["x"] >= 0) & (s["x"] < 10))
+    d = s["x"] - 5.0
+    assert np.sqrt((d ** 2).sum(0)).min() >= 2.0
+    assert np.allclose(s["v"].mean(1), 0, atol=1e-15)
+    assert (s["v"] ** 2).mean() == pytest.approx(1.0, rel=0.03)
+    assert o.observables()["flags"] == 0
+
+
+def test_resume_is_bitwise():
+    p = W.dimer_system(L=16, rho=6, n_md=10, seed=9)
+    a = oracle.Oracle(p, 29)
+    a.run(10, 5)
+    b = oracle.Oracle(p, 29)
+    b.run(10, 2)
+    st = b.get_state()
+    c = oracle.Oracle(p, 29, init=False)
+    c.set_state(st)
+    c.run(10, 3)
+    sa, sc = a.get_state(), c.get_state()
+    for k in ("x", "v", "id", "state", "X", "V"):
+        assert np.array_equal(sa[k], sc[k]), k
+    d = oracle.Oracle(p, 30)
+    d.run(10, 5)
+    assert not np.array_equal(sa["v"], d.get_state()["v"])
+
+
+def test_paper_example_configuration_maps_to_params():
+    """The appendix configuration file of the paper, parsed into a parameter
+    set and run for a few steps (fixture: tests/golden/paper_example.parameters)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_example.parameters")
+    cfg = W.parse_parameters(open(path).read())
+    assert cfg["L"] == (32, 32, 32) and cfg["rho"] == 10 and cfg["N_MD"] == 100
+    assert cfg["sigma_N"] == 3.0 and cfg["d"] == 6.5
+    assert cfg["epsilon_N"] == (1.0, 0.2) and cfg["bulk_rmpcd"] is True
+    p = W.params_from_config(cfg, L_override=(12, 12, 12))
+    o = oracle.Oracle(p, 31)
+    o.run(5, 2)
+    s = o.get_state()
+    assert np.linalg.norm(s["X"][0] - s["X"][1]) == pytest.approx(6.5, rel=1e-13)
