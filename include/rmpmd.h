@@ -1,0 +1,209 @@
+/*
+ * rmpmd -- MI355X (gfx950) library for the solvent hot path of hybrid
+ * Reactive Multiparticle Collision Dynamics + Molecular Dynamics
+ * (RMPCDMD, de Buyl, Huang, Deprez, arXiv:1608.04904).
+ *
+ * One interval of the method = n_md velocity-Verlet MD steps of solvent and
+ * colloids ("Algorithms": velocity-Verlet; WCA colloid-solvent and
+ * colloid-colloid forces via Verlet and cell lists; exact RATTLE for the
+ * dimer; catalytic A->B conversion), followed by one MPCD collision on a
+ * randomly shifted grid ("Algorithms": original MPCD rule, grid shifting,
+ * Anderson thermostat; Overview: RMPCD bulk reactions) with the stable cell
+ * sort it shares with the cell lists.
+ *
+ * Conventions for every entry point:
+ *   - Device memory is owned by the caller: the library carves its arrays out
+ *     of a workspace the caller allocates (size from *_workspace_bytes) and
+ *     never frees it.  Host buffers are owned by the caller.  Handles are
+ *     owned by the library and released by the matching destroy call.
+ *   - `stream` is a hipStream_t passed as void*; all device work of a handle
+ *     is ordered on that stream.  Calls are asynchronous unless stated.
+ *   - Every call returns an rmp_status and never aborts or throws.  Device
+ *     side faults (list overflow, unsound Verlet list, barrier time-out,
+ *     non-finite force) are latched in a per-replica flag word and reported
+ *     by the next observables call as RMP_EDEVICE with `flags` filled in.
+ *   - Units are the paper's reduced units: cell size a = 1, energies in kT,
+ *     lengths in a, masses in the solvent mass.
+ *   - Arrays exchanged with the host are structure-of-arrays: x[3*N] holds
+ *     all x components, then all y, then all z.
+ */
+#ifndef RMPMD_H
+#define RMPMD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RMP_MAX_COLLOIDS 32
+#define RMP_PTABLE 1024
+
+typedef enum rmp_status {
+    RMP_OK = 0,
+    RMP_EINVAL = -1,   /* invalid argument or parameter set               */
+    RMP_ENOMEM = -2,   /* workspace smaller than *_workspace_bytes        */
+    RMP_EHIP = -3,     /* a HIP runtime call failed                       */
+    RMP_EDEVICE = -4,  /* a device-side flag is set (see rmp_observables) */
+    RMP_ESTATE = -5    /* call not valid in the handle's current state    */
+} rmp_status;
+
+/* device flag bits (rmp_observables.flags) */
+#define RMP_FLAG_DISPLACEMENT  1u  /* colloid moved >= skin/2 in one interval     */
+#define RMP_FLAG_RATTLE        2u  /* RATTLE quadratic had no real root           */
+#define RMP_FLAG_NONFINITE     4u  /* non-finite colloid force                    */
+#define RMP_FLAG_INIT          8u  /* init rejection sampling hit its cap         */
+#define RMP_FLAG_LIST_OVERFLOW 16u /* Verlet list longer than its capacity        */
+#define RMP_FLAG_BARRIER       32u /* inter-workgroup barrier timed out           */
+
+/*
+ * System parameters.  Names follow the paper's configuration file
+ * (appendix "Example configuration file": T -> kT, L, tau = n_md * dt,
+ * probability -> cat_prob, bulk_rate, sigma_*, epsilon_*, d -> bond_d).
+ * Colloid-solvent interaction: WCA with (sigma[c], eps_A[c] or eps_B[c] by
+ * solvent species).  Colloid-colloid: WCA with sigma_a + sigma_b and
+ * eps_cc[ctype[a]][ctype[b]], bonded pairs excluded.
+ */
+typedef struct rmp_params {
+    int32_t L[3];              /* box edge in cells, each >= 1                     */
+    int32_t precision;         /* 64: FP64 state; 32: FP32 state, FP64 cell sums   */
+    int64_t n_solvent;         /* N >= 0, N < 2^31                                 */
+    double  kT;                /* temperature for init and the thermostat          */
+    double  mass;              /* solvent particle mass m > 0                      */
+    double  dt;                /* MD time step > 0                                 */
+    double  alpha;             /* rotation angle in radians                        */
+    double  skin;              /* Verlet-list skin >= 0                            */
+    double  cat_prob;          /* probability of A->B on leaving a catalytic sphere */
+    double  bulk_rate;         /* bulk B->A rate k; 0 switches it off              */
+    int32_t rule;              /* 0: rotation (SRD) rule; 1: Anderson thermostat   */
+    int32_t n_colloids;        /* 0 .. RMP_MAX_COLLOIDS                            */
+    int32_t n_bonds;           /* rigid bonds (each colloid in at most one)        */
+    int32_t cand_capacity;     /* Verlet-list capacity; 0 = automatic              */
+    double  colloid_x[RMP_MAX_COLLOIDS][3];   /* initial positions (unwrapped)     */
+    double  colloid_mass[RMP_MAX_COLLOIDS];
+    double  sigma[RMP_MAX_COLLOIDS];
+    double  eps_A[RMP_MAX_COLLOIDS];
+    double  eps_B[RMP_MAX_COLLOIDS];
+    int32_t catalytic[RMP_MAX_COLLOIDS];      /* 1: converts A to B                */
+    int32_t ctype[RMP_MAX_COLLOIDS];          /* 0 or 1, index into eps_cc         */
+    double  eps_cc[2][2];
+    int32_t bond_a[RMP_MAX_COLLOIDS];
+    int32_t bond_b[RMP_MAX_COLLOIDS];
+    double  bond_d[RMP_MAX_COLLOIDS];
+} rmp_params;
+
+/* FP64 observables.  `potential` is the colloid-solvent plus colloid-colloid
+ * WCA energy at the last force evaluation; `temperature` is the cell-frame
+ * estimator ("Algorithms", temperature equation) of the last collision,
+ * averaged over the n_cells_T cells holding two or more particles. */
+typedef struct rmp_obs {
+    double   momentum[3];
+    double   ke_solvent, ke_colloid, potential, temperature, e_rxn;
+    int64_t  n_A, n_B, n_cat_flips, n_bulk_flips;
+    int64_t  md_step, coll_step, n_candidates, n_cells_T;
+    uint32_t flags;
+    int32_t  pad;
+    double   colloid_X[RMP_MAX_COLLOIDS][3];
+    double   colloid_V[RMP_MAX_COLLOIDS][3];
+} rmp_obs;
+
+/* Host-side state exchange, caller-owned buffers.  x, v: 3*N doubles (SoA;
+ * FP32 systems convert exactly on get and round on set); id: N; state: N
+ * bytes (bit 0 species B, bit 1 catalytic flag); X, V: 3*n_colloids
+ * doubles, row per colloid.  Any pointer may be NULL on get to skip it. */
+typedef struct rmp_host_state {
+    double*   x;
+    double*   v;
+    uint32_t* id;
+    uint8_t*  state;
+    double*   X;
+    double*   V;
+    int64_t   md_step;
+    int64_t   coll_step;
+} rmp_host_state;
+
+typedef struct rmp_system rmp_system;
+typedef struct rmp_batch rmp_batch;
+
+const char* rmp_status_string(rmp_status st);
+/* Text of the last HIP failure seen by the calling thread (RMP_EHIP). */
+const char* rmp_last_error(void);
+
+/* ---------------------------------------------------------------- single */
+
+/* Device bytes needed by one system with these parameters; 0 and *st set on
+ * invalid parameters.  Pure host function, used for HBM admission. */
+size_t rmp_workspace_bytes(const rmp_params* p, rmp_status* st);
+
+/* Validate p, carve d_workspace, and initialise the solvent on `stream`:
+ * positions uniform in the box, rejected inside colloid cores (r < sigma),
+ * velocities Maxwellian at kT with the mean removed, all species A, colloids
+ * at rest at colloid_x (Overview: N solvent particles with mass, position and
+ * velocity in a cuboid domain).  Randomness: Philox4x64-10 keyed by seed. */
+rmp_status rmp_init_system(const rmp_params* p, uint64_t seed, void* d_workspace,
+                           size_t workspace_bytes, void* stream, rmp_system** out);
+
+/* Advance n_collide intervals of (n_md MD steps, one collision); tau =
+ * n_md * dt.  Asynchronous.  n_md >= 1, n_collide >= 0. */
+rmp_status rmp_step(rmp_system* s, int32_t n_md, int32_t n_collide);
+
+/* FP64 reductions of the current state; synchronises the stream.  Returns
+ * RMP_EDEVICE (with out filled) if a device flag is set. */
+rmp_status rmp_observables(rmp_system* s, rmp_obs* out);
+
+/* Copy the state to / from caller-owned host buffers (synchronous).  After
+ * set_state the next interval rebuilds the Verlet list and forces. */
+rmp_status rmp_get_state(rmp_system* s, rmp_host_state* dst);
+rmp_status rmp_set_state(rmp_system* s, const rmp_host_state* src);
+
+/* Release the handle; the workspace is not freed. */
+rmp_status rmp_destroy(rmp_system* s);
+
+/* Per-kernel launch parameters (autotuning).  Values <= 0 keep the default.
+ * Applies to the next rmp_step / rmp_batch_step. */
+typedef struct rmp_tuning {
+    int32_t stream_block;      /* threads per workgroup, particle kernels       */
+    int32_t stream_ppt;        /* particles per thread in the streaming kernel  */
+    int32_t collide_cells;     /* cells per collision tile (power of two)       */
+    int32_t chain_k;           /* Verlet-list entries per thread (1, 2 or 4)    */
+    int32_t use_graph;         /* 1: replay a captured hipGraph per interval    */
+} rmp_tuning;
+rmp_status rmp_set_tuning(rmp_system* s, const rmp_tuning* t);
+rmp_status rmp_get_tuning(rmp_system* s, rmp_tuning* t);
+
+/* Average device time per launch of each hot kernel over the calls since
+ * the last reset, measured with HIP events on the handle's stream (enabled
+ * by rmp_profile(s, 1)).  names/ms/count hold up to cap entries. */
+rmp_status rmp_profile(rmp_system* s, int32_t enable);
+int32_t    rmp_profile_read(rmp_system* s, const char** names, double* ms_total,
+                            int64_t* count, int32_t cap);
+
+/* ----------------------------------------------------------------- batch */
+/* A batch advances many independent replicas together (uneven box sizes,
+ * per-replica seeds and n_md), one interval per replica per tick.  All
+ * replicas of a batch share the precision.  Each replica's state lives in a
+ * caller-provided workspace of rmp_workspace_bytes(params).  Slots can be
+ * filled and emptied between ticks (continuous batching). */
+size_t     rmp_batch_ctl_bytes(int32_t n_slots);
+rmp_status rmp_batch_create(int32_t n_slots, int32_t precision, void* d_ctl,
+                            size_t ctl_bytes, void* stream, rmp_batch** out);
+/* Admit a replica into an empty slot: validates, carves d_workspace and
+ * initialises the state (as rmp_init_system); it takes part from the next
+ * tick with its own n_md. */
+rmp_status rmp_batch_set_slot(rmp_batch* b, int32_t slot, const rmp_params* p,
+                              uint64_t seed, int32_t n_md, void* d_workspace,
+                              size_t workspace_bytes);
+/* Retire a slot; its workspace may then be reused by the caller. */
+rmp_status rmp_batch_clear_slot(rmp_batch* b, int32_t slot);
+/* n_ticks ticks: every occupied slot advances one interval per tick. */
+rmp_status rmp_batch_step(rmp_batch* b, int32_t n_ticks);
+rmp_status rmp_batch_slot_observables(rmp_batch* b, int32_t slot, rmp_obs* out);
+rmp_status rmp_batch_get_state(rmp_batch* b, int32_t slot, rmp_host_state* dst);
+rmp_status rmp_batch_set_state(rmp_batch* b, int32_t slot, const rmp_host_state* src);
+rmp_status rmp_batch_set_tuning(rmp_batch* b, const rmp_tuning* t);
+rmp_status rmp_batch_destroy(rmp_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RMPMD_H */

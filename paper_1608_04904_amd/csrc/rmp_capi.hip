@@ -1,0 +1,1081 @@
+// Host runtime and C ABI of the rmpmd library (include/rmpmd.h).
+//
+// A single system is a batch of one replica.  Each replica's arrays are
+// carved from a caller-owned workspace; the batch keeps a small control
+// block (descriptors and work-list prefixes) in device memory.  One tick
+// launches, for all occupied replicas at once:
+//
+//   [ k_chain  ||  k_stream_bin ]  (fork/join on a side stream)
+//   k_scan_blocks, k_scan_final, k_scatter, k_collide, k_chunk_scan,
+//   k_cand_write
+//
+// optionally replayed from a captured hipGraph.
+#include "rmp_kernels.hip"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace rmp;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t aup(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+// number of work items of each kind
+struct Sizes {
+    int64_t n, ncell;
+    int32_t n_chunks, n_tiles_max, n_scanblk, cand_cap, G;
+};
+
+constexpr int MIN_TILE_CELLS = 8;
+constexpr int MAX_G = 256;
+constexpr int K_MAX = 4;
+
+int64_t auto_capacity(const rmp_params* p)
+{
+    const double vol = (double)p->L[0] * p->L[1] * p->L[2];
+    const double rho = vol > 0 ? (double)p->n_solvent / vol : 0.0;
+    double cap = 4096.0;
+    for (int c = 0; c < p->n_colloids; ++c) {
+        double R = 0x1.1f59ac3c7d6c0p+0 * p->sigma[c] + p->skin + 2.5;
+        cap += 1.3 * rho * 4.0 / 3.0 * M_PI * R * R * R;
+    }
+    if (p->n_colloids == 0) cap = 1024.0;
+    int64_t c = (int64_t)cap;
+    if (c > p->n_solvent) c = p->n_solvent;
+    if (c < 1) c = 1;
+    return c;
+}
+
+rmp_status validate(const rmp_params* p)
+{
+    if (!p) return RMP_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (p->L[d] < 1 || p->L[d] > 65536) return RMP_EINVAL;
+    if (p->precision != 32 && p->precision != 64) return RMP_EINVAL;
+    const int64_t ncell = (int64_t)p->L[0] * p->L[1] * p->L[2];
+    if (ncell > (int64_t)1 << 31) return RMP_EINVAL;
+    if (p->n_solvent < 0 || p->n_solvent >= ((int64_t)1 << 31)) return RMP_EINVAL;
+    if (!(p->kT >= 0.0) || !(p->mass > 0.0) || !(p->dt > 0.0) || !(p->skin >= 0.0)) return RMP_EINVAL;
+    if (!std::isfinite(p->alpha) || !(p->cat_prob >= 0.0) || !(p->bulk_rate >= 0.0)) return RMP_EINVAL;
+    if (p->rule != 0 && p->rule != 1) return RMP_EINVAL;
+    if (p->n_colloids < 0 || p->n_colloids > RMP_MAX_COLLOIDS) return RMP_EINVAL;
+    if (p->n_bonds < 0 || p->n_bonds > RMP_MAX_COLLOIDS / 2) return RMP_EINVAL;
+    if (p->cand_capacity < 0) return RMP_EINVAL;
+    int used[RMP_MAX_COLLOIDS] = {0};
+    for (int c = 0; c < p->n_colloids; ++c) {
+        if (!(p->sigma[c] > 0.0) || !(p->colloid_mass[c] > 0.0)) return RMP_EINVAL;
+        if (!(p->eps_A[c] >= 0.0) || !(p->eps_B[c] >= 0.0)) return RMP_EINVAL;
+        if (p->ctype[c] < 0 || p->ctype[c] > 1) return RMP_EINVAL;
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(p->colloid_x[c][d])) return RMP_EINVAL;
+        // minimum image needs the interaction reach within half a box
+        double reach = 0x1.1f59ac3c7d6c0p+0 * p->sigma[c] + p->skin;
+        for (int d = 0; d < 3; ++d)
+            if (2.0 * reach > (double)p->L[d]) return RMP_EINVAL;
+    }
+    for (int b = 0; b < p->n_bonds; ++b) {
+        int a0 = p->bond_a[b], a1 = p->bond_b[b];
+        if (a0 < 0 || a1 < 0 || a0 >= p->n_colloids || a1 >= p->n_colloids || a0 == a1) return RMP_EINVAL;
+        if (used[a0] || used[a1]) return RMP_EINVAL;
+        used[a0] = used[a1] = 1;
+        if (!(p->bond_d[b] > 0.0)) return RMP_EINVAL;
+    }
+    return RMP_OK;
+}
+
+Sizes sizes_of(const rmp_params* p)
+{
+    Sizes s;
+    s.n = p->n_solvent;
+    s.ncell = (int64_t)p->L[0] * p->L[1] * p->L[2];
+    s.n_chunks = (int32_t)((s.n + CHUNK - 1) / CHUNK);
+    if (s.n_chunks < 1) s.n_chunks = 1;
+    s.n_tiles_max = (int32_t)((s.ncell + MIN_TILE_CELLS - 1) / MIN_TILE_CELLS);
+    s.n_scanblk = (int32_t)((s.ncell + SCAN_BLK - 1) / SCAN_BLK);
+    int64_t cap = p->cand_capacity > 0 ? p->cand_capacity : auto_capacity(p);
+    if (cap > (int64_t)MAX_G * CHAIN_BLOCK * K_MAX) cap = (int64_t)MAX_G * CHAIN_BLOCK * K_MAX;
+    s.cand_cap = (int32_t)cap;
+    s.G = (int32_t)((cap + CHAIN_BLOCK - 1) / CHAIN_BLOCK);   // enough for K = 1
+    if (s.G > MAX_G) s.G = MAX_G;
+    if (s.G < 1) s.G = 1;
+    return s;
+}
+
+// offsets of every array inside a replica workspace
+struct Layout {
+    size_t cp, rs, x[2], v[2], id[2], st[2], keyrank, perm, cflag, count, start, scanblk,
+        chunk_cnt, chunk_off, cand_idx, partials, epart, tpart, ptable, obs_part, mean, total;
+};
+
+Layout layout_of(const rmp_params* p)
+{
+    Sizes s = sizes_of(p);
+    const size_t tb = p->precision == 32 ? 4 : 8;
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = aup(o + (bytes ? bytes : 1)); return r; };
+    L.cp = take(sizeof(ColloidParams));
+    L.rs = take(sizeof(RepState));
+    for (int b = 0; b < 2; ++b) {
+        L.x[b] = take(3 * s.n * tb);
+        L.v[b] = take(3 * s.n * tb);
+        L.id[b] = take(4 * s.n);
+        L.st[b] = take(s.n);
+    }
+    L.keyrank = take(8 * s.n);
+    L.perm = take(4 * s.n);
+    L.cflag = take(s.n);
+    L.count = take(4 * s.ncell);
+    L.start = take(4 * (s.ncell + 1));
+    L.scanblk = take(4 * (size_t)s.n_scanblk);
+    L.chunk_cnt = take(4 * (size_t)s.n_chunks);
+    L.chunk_off = take(4 * (size_t)s.n_chunks);
+    L.cand_idx = take(4 * (size_t)s.cand_cap);
+    L.partials = take(2 * (size_t)s.G * NVAL_MAX * 8);
+    L.epart = take((size_t)s.G * 2 * 8);
+    L.tpart = take((size_t)s.n_tiles_max * 4 * 8);
+    L.ptable = take(RMP_PTABLE * 8);
+    L.obs_part = take((size_t)s.n_chunks * 8 * 8);
+    L.mean = take(4 * 8);
+    L.total = o;
+    return L;
+}
+
+size_t ctl_bytes_for(int32_t nslots)
+{
+    return aup(sizeof(RepDesc) * (size_t)nslots) + 6 * aup(4 * (size_t)(nslots + 1));
+}
+
+const char* KNAMES[] = {"stream_bin", "chain", "scan_blocks", "scan_final", "scatter",
+                        "collide", "chunk_scan", "cand_write", "list"};
+enum { KN_STREAM, KN_CHAIN, KN_SCANB, KN_SCANF, KN_SCATTER, KN_COLLIDE, KN_CHUNKSCAN,
+       KN_CANDW, KN_LIST, KN_COUNT };
+
+struct Replica {
+    bool used = false;
+    rmp_params p{};
+    uint64_t seed = 0;
+    int32_t n_md = 0;
+    char* ws = nullptr;
+    Layout lay{};
+    Sizes sz{};
+    RepDesc desc{};
+    bool list_valid = false;
+    int32_t list_nmd = -1;
+    std::vector<double> ptable;
+    int32_t ptable_nmd = -1;
+};
+
+}  // namespace
+
+struct rmp_batch {
+    int32_t nslots = 0;
+    int32_t precision = 64;
+    hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;
+    hipStream_t capture = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    char* ctl = nullptr;
+    RepDesc* d_desc = nullptr;
+    int32_t* d_prefix[6] = {};
+    std::vector<Replica> reps;
+    std::vector<RepDesc> hdesc;
+    std::vector<int32_t> hprefix[6];
+    int32_t totals[6] = {};
+    bool dirty = true;
+    bool have_rule[2] = {false, false};
+    bool multi_scan = false;
+    rmp_tuning tun{256, 4, 32, 2, 1};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_valid = false;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
+    double prof_ms[KN_COUNT] = {};
+    int64_t prof_cnt[KN_COUNT] = {};
+};
+
+struct rmp_system {
+    rmp_batch* b = nullptr;
+    rmp_batch storage;
+};
+
+namespace {
+
+enum { PF_CHUNK, PF_TILE, PF_SCAN, PF_CHAIN, PF_REP, PF_IDENT };
+
+thread_local char g_last_error[256] = "";
+
+void note_error(const char* what, hipError_t e)
+{
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(x)                                       \
+    do {                                                \
+        hipError_t e_ = (x);                            \
+        if (e_ != hipSuccess) {                         \
+            note_error(#x, e_);                         \
+            return RMP_EHIP;                            \
+        }                                               \
+    } while (0)
+
+rmp_status last_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        note_error(what, e);
+        return RMP_EHIP;
+    }
+    return RMP_OK;
+}
+
+int chain_k_of(const rmp_batch* b)
+{
+    int k = b->tun.chain_k;
+    return (k == 1 || k == 2 || k == 4) ? k : 2;
+}
+
+int tile_cells_of(const rmp_batch* b)
+{
+    int tc = b->tun.collide_cells;
+    if (tc < MIN_TILE_CELLS) tc = MIN_TILE_CELLS;
+    if (tc > COLL_TCMAX) tc = COLL_TCMAX;
+    int p2 = MIN_TILE_CELLS;
+    while (p2 * 2 <= tc) p2 *= 2;
+    return p2;
+}
+
+void fill_desc(rmp_batch* b, Replica& r)
+{
+    RepDesc& D = r.desc;
+    const rmp_params* p = &r.p;
+    char* w = r.ws;
+    const Layout& L = r.lay;
+    const Sizes& s = r.sz;
+    D = RepDesc{};
+    for (int d = 0; d < 3; ++d) {
+        D.L[d] = p->L[d];
+        D.Ld[d] = (double)p->L[d];
+        D.halfL[d] = 0.5 * D.Ld[d];
+    }
+    D.active = 1;
+    D.n = s.n;
+    D.ncell = s.ncell;
+    D.n_md = r.n_md;
+    D.rule = p->rule;
+    D.n_chunks = s.n_chunks;
+    D.tile_cells = tile_cells_of(b);
+    D.n_tiles = (int32_t)((s.ncell + D.tile_cells - 1) / D.tile_cells);
+    D.n_scanblk = s.n_scanblk;
+    D.cand_cap = s.cand_cap;
+    const int K = chain_k_of(b);
+    int G = (int)((s.cand_cap + CHAIN_BLOCK * K - 1) / (CHAIN_BLOCK * K));
+    if (G < 1) G = 1;
+    if (G > s.G) G = s.G;
+    D.G = G;
+    D.cand_cap = std::min<int64_t>(s.cand_cap, (int64_t)G * CHAIN_BLOCK * K);
+    D.chain_k = K;
+    D.dt = p->dt;
+    D.h = (0.5 * p->dt) / p->mass;
+    D.tau = (double)r.n_md * p->dt;
+    D.vscale = std::sqrt(p->kT / p->mass);
+    D.mass = p->mass;
+    D.ca = std::cos(p->alpha);
+    D.sa = std::sin(p->alpha);
+    D.cat_prob = p->cat_prob;
+    D.skin_half2 = (0.5 * p->skin) * (0.5 * p->skin);
+    D.bulk_on = p->bulk_rate > 0.0 ? 1 : 0;
+    D.seed = r.seed;
+    for (int q = 0; q < 2; ++q) {
+        D.x[q] = w + L.x[q];
+        D.v[q] = w + L.v[q];
+        D.id[q] = (uint32_t*)(w + L.id[q]);
+        D.st[q] = (uint8_t*)(w + L.st[q]);
+    }
+    D.keyrank = (uint64_t*)(w + L.keyrank);
+    D.perm = (uint32_t*)(w + L.perm);
+    D.cflag = (uint8_t*)(w + L.cflag);
+    D.count = (uint32_t*)(w + L.count);
+    D.start = (uint32_t*)(w + L.start);
+    D.scanblk = (uint32_t*)(w + L.scanblk);
+    D.chunk_cnt = (uint32_t*)(w + L.chunk_cnt);
+    D.chunk_off = (uint32_t*)(w + L.chunk_off);
+    D.cand_idx = (uint32_t*)(w + L.cand_idx);
+    D.partials = (double*)(w + L.partials);
+    D.epart = (double*)(w + L.epart);
+    D.tpart = (double*)(w + L.tpart);
+    D.ptable = (double*)(w + L.ptable);
+    D.obs_part = (double*)(w + L.obs_part);
+    D.cp = (ColloidParams*)(w + L.cp);
+    D.rs = (RepState*)(w + L.rs);
+}
+
+ColloidParams make_cp(const rmp_params* p)
+{
+    ColloidParams c{};
+    c.nc = p->n_colloids;
+    c.nbonds = p->n_bonds;
+    for (int i = 0; i < RMP_MAX_COLLOIDS; ++i) c.partner[i] = -1;
+    for (int i = 0; i < p->n_colloids; ++i) {
+        c.catalytic[i] = p->catalytic[i] ? 1 : 0;
+        c.ctype[i] = p->ctype[i];
+        c.sigma[i] = p->sigma[i];
+        c.sig2[i] = p->sigma[i] * p->sigma[i];
+        double rc = 0x1.1f59ac3c7d6c0p+0 * p->sigma[i];
+        c.rc2[i] = rc * rc;
+        c.reachR[i] = rc + p->skin;
+        c.epsA[i] = p->eps_A[i];
+        c.epsB[i] = p->eps_B[i];
+        c.mass[i] = p->colloid_mass[i];
+        c.imass[i] = 1.0 / p->colloid_mass[i];
+        c.hc[i] = (0.5 * p->dt) / p->colloid_mass[i];
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int q = 0; q < 2; ++q) c.eps_cc[a][q] = p->eps_cc[a][q];
+    for (int b = 0; b < p->n_bonds; ++b) {
+        c.bond_a[b] = p->bond_a[b];
+        c.bond_b[b] = p->bond_b[b];
+        c.bond_d[b] = p->bond_d[b];
+        c.partner[p->bond_a[b]] = p->bond_b[b];
+        c.partner[p->bond_b[b]] = p->bond_a[b];
+    }
+    return c;
+}
+
+void make_ptable(Replica& r)
+{
+    if (r.ptable_nmd == r.n_md && !r.ptable.empty()) return;
+    r.ptable.assign(RMP_PTABLE, 0.0);
+    const double kt = r.p.bulk_rate * ((double)r.n_md * r.p.dt);
+    for (int q = 0; q < RMP_PTABLE; ++q) r.ptable[q] = -std::expm1(-(kt * (double)q));
+    r.ptable_nmd = r.n_md;
+}
+
+// recompute the work-list prefixes and upload descriptors
+rmp_status sync_ctl(rmp_batch* b)
+{
+    if (!b->dirty) return RMP_OK;
+    const int S = b->nslots;
+    for (int k = 0; k < 6; ++k) b->hprefix[k].assign(S + 1, 0);
+    b->have_rule[0] = b->have_rule[1] = false;
+    b->multi_scan = false;
+    for (int r = 0; r < S; ++r) {
+        Replica& R = b->reps[r];
+        int items[6] = {0, 0, 0, 0, 1, 1};
+        if (R.used) {
+            fill_desc(b, R);
+            items[PF_CHUNK] = R.desc.n_chunks;
+            items[PF_TILE] = R.desc.n_tiles;
+            items[PF_SCAN] = R.desc.n_scanblk;
+            items[PF_CHAIN] = R.desc.G;
+            b->have_rule[R.p.rule] = true;
+            if (R.desc.n_scanblk > 1) b->multi_scan = true;
+            b->hdesc[r] = R.desc;
+        } else {
+            b->hdesc[r] = RepDesc{};
+            b->hdesc[r].active = 0;
+        }
+        for (int k = 0; k < 6; ++k) b->hprefix[k][r + 1] = b->hprefix[k][r] + items[k];
+    }
+    for (int k = 0; k < 6; ++k) b->totals[k] = b->hprefix[k][S];
+    HIPCHK(hipMemcpyAsync(b->d_desc, b->hdesc.data(), sizeof(RepDesc) * S, hipMemcpyHostToDevice, b->stream));
+    for (int k = 0; k < 6; ++k)
+        HIPCHK(hipMemcpyAsync(b->d_prefix[k], b->hprefix[k].data(), 4 * (S + 1), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->dirty = false;
+    b->graph_valid = false;
+    return RMP_OK;
+}
+
+Work work(const rmp_batch* b, int kind)
+{
+    Work w;
+    w.desc = b->d_desc;
+    w.prefix = b->d_prefix[kind];
+    w.nrep = b->nslots;
+    w.pad = 0;
+    return w;
+}
+
+// event-timed launch (profiling mode, no graph)
+struct Timer {
+    rmp_batch* b;
+    int kind;
+    hipStream_t s;
+    size_t i0;
+    Timer(rmp_batch* bb, int k, hipStream_t st) : b(bb), kind(k), s(st), i0(0)
+    {
+        if (!b->prof) return;
+        if (b->ev_used + 2 > b->ev.size()) {
+            size_t add = 512;
+            for (size_t q = 0; q < add; ++q) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                b->ev.push_back(e);
+                b->ev_kind.push_back(-1);
+            }
+        }
+        i0 = b->ev_used;
+        b->ev_used += 2;
+        b->ev_kind[i0] = kind;
+        (void)hipEventRecord(b->ev[i0], s);
+    }
+    ~Timer()
+    {
+        if (!b->prof) return;
+        (void)hipEventRecord(b->ev[i0 + 1], s);
+    }
+};
+
+rmp_status flush_profile(rmp_batch* b)
+{
+    if (!b->prof || b->ev_used == 0) return RMP_OK;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipStreamSynchronize(b->side));
+    for (size_t i = 0; i + 1 < b->ev_used; i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, b->ev[i], b->ev[i + 1]) == hipSuccess) {
+            b->prof_ms[b->ev_kind[i]] += ms;
+            b->prof_cnt[b->ev_kind[i]] += 1;
+        }
+    }
+    b->ev_used = 0;
+    return RMP_OK;
+}
+
+template <class T>
+rmp_status launch_chain(rmp_batch* b, hipStream_t s)
+{
+    Timer tm(b, KN_CHAIN, s);
+    const int K = chain_k_of(b);
+    dim3 g(b->totals[PF_CHAIN]), blk(CHAIN_BLOCK);
+    if (K == 1) hipLaunchKernelGGL((k_chain<T, 1>), g, blk, 0, s, work(b, PF_CHAIN));
+    else if (K == 2) hipLaunchKernelGGL((k_chain<T, 2>), g, blk, 0, s, work(b, PF_CHAIN));
+    else hipLaunchKernelGGL((k_chain<T, 4>), g, blk, 0, s, work(b, PF_CHAIN));
+    return last_launch("k_chain");
+}
+
+template <class T>
+rmp_status launch_list(rmp_batch* b)
+{
+    hipStream_t s = b->stream;
+    if (b->totals[PF_CHUNK] == 0) return RMP_OK;
+    {
+        Timer tm(b, KN_LIST, s);
+        hipLaunchKernelGGL((k_list<T>), dim3(b->totals[PF_CHUNK]), dim3(256), 0, s, work(b, PF_CHUNK));
+    }
+    {
+        Timer tm(b, KN_CHUNKSCAN, s);
+        hipLaunchKernelGGL(k_chunk_scan, dim3(b->nslots), dim3(1024), 0, s, work(b, PF_IDENT), 0);
+    }
+    {
+        Timer tm(b, KN_CANDW, s);
+        hipLaunchKernelGGL(k_cand_write, dim3(b->totals[PF_CHUNK]), dim3(256), 0, s, work(b, PF_CHUNK));
+    }
+    return last_launch("list build");
+}
+
+// one interval for every occupied replica
+template <class T>
+rmp_status launch_interval(rmp_batch* b, hipStream_t s)
+{
+    const int nch = b->totals[PF_CHUNK];
+    if (nch == 0) return RMP_OK;
+    // fork: the MD chain runs on the side stream next to the streaming kernel
+    HIPCHK(hipEventRecord(b->fork, s));
+    HIPCHK(hipStreamWaitEvent(b->side, b->fork, 0));
+    rmp_status st = launch_chain<T>(b, b->side);
+    if (st != RMP_OK) return st;
+    {
+        Timer tm(b, KN_STREAM, s);
+        int bs = b->tun.stream_block;
+        if (bs != 64 && bs != 128 && bs != 256) bs = 256;
+        hipLaunchKernelGGL((k_stream_bin<T>), dim3(nch), dim3(bs), 0, s, work(b, PF_CHUNK));
+    }
+    HIPCHK(hipEventRecord(b->join, b->side));
+    HIPCHK(hipStreamWaitEvent(s, b->join, 0));
+    if (b->multi_scan) {
+        Timer tm(b, KN_SCANB, s);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(b->totals[PF_SCAN]), dim3(1024), 0, s, work(b, PF_SCAN));
+    }
+    {
+        Timer tm(b, KN_SCANF, s);
+        hipLaunchKernelGGL(k_scan_final, dim3(b->totals[PF_SCAN]), dim3(1024), 0, s, work(b, PF_SCAN));
+    }
+    {
+        Timer tm(b, KN_SCATTER, s);
+        hipLaunchKernelGGL(k_scatter, dim3(nch), dim3(256), 0, s, work(b, PF_CHUNK));
+    }
+    {
+        Timer tm(b, KN_COLLIDE, s);
+        if (b->have_rule[0])
+            hipLaunchKernelGGL((k_collide<T, 0>), dim3(b->totals[PF_TILE]), dim3(COLL_NT), 0, s, work(b, PF_TILE));
+        if (b->have_rule[1])
+            hipLaunchKernelGGL((k_collide<T, 1>), dim3(b->totals[PF_TILE]), dim3(COLL_NT), 0, s, work(b, PF_TILE));
+    }
+    {
+        Timer tm(b, KN_CHUNKSCAN, s);
+        hipLaunchKernelGGL(k_chunk_scan, dim3(b->nslots), dim3(1024), 0, s, work(b, PF_IDENT), 1);
+    }
+    {
+        Timer tm(b, KN_CANDW, s);
+        hipLaunchKernelGGL(k_cand_write, dim3(nch), dim3(256), 0, s, work(b, PF_CHUNK));
+    }
+    return last_launch("interval");
+}
+
+rmp_status run_interval(rmp_batch* b, hipStream_t s)
+{
+    return b->precision == 32 ? launch_interval<float>(b, s) : launch_interval<double>(b, s);
+}
+
+rmp_status capture_graph(rmp_batch* b)
+{
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    // capture on the library's private stream (the caller's stream may be
+    // the legacy default stream, which cannot be captured); the graph is
+    // then launched on the caller's stream
+    HIPCHK(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    rmp_status st = run_interval(b, b->capture);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->capture, &g);
+    if (e != hipSuccess) note_error("hipStreamEndCapture", e);
+    if (st != RMP_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != RMP_OK ? st : RMP_EHIP;
+    }
+    b->graph = g;
+    HIPCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    b->graph_valid = true;
+    return RMP_OK;
+}
+
+// make every occupied replica's Verlet list valid for its current n_md
+rmp_status ensure_lists(rmp_batch* b)
+{
+    bool need = false;
+    for (int r = 0; r < b->nslots; ++r) {
+        Replica& R = b->reps[r];
+        if (R.used && (!R.list_valid || R.list_nmd != R.n_md)) need = true;
+    }
+    if (!need) return RMP_OK;
+    rmp_status st = b->precision == 32 ? launch_list<float>(b) : launch_list<double>(b);
+    if (st != RMP_OK) return st;
+    for (int r = 0; r < b->nslots; ++r) {
+        Replica& R = b->reps[r];
+        if (R.used) { R.list_valid = true; R.list_nmd = R.n_md; }
+    }
+    return RMP_OK;
+}
+
+rmp_status batch_ticks(rmp_batch* b, int32_t n)
+{
+    if (n < 0) return RMP_EINVAL;
+    rmp_status st = sync_ctl(b);
+    if (st != RMP_OK) return st;
+    st = ensure_lists(b);
+    if (st != RMP_OK) return st;
+    const bool use_graph = b->tun.use_graph > 0 && !b->prof;
+    for (int32_t k = 0; k < n; ++k) {
+        if (use_graph) {
+            if (!b->graph_valid) {
+                st = capture_graph(b);
+                if (st != RMP_OK) return st;
+            }
+            HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+        } else {
+            st = run_interval(b, b->stream);
+            if (st != RMP_OK) return st;
+        }
+        if (b->prof && b->ev_used > 3000) {
+            st = flush_profile(b);
+            if (st != RMP_OK) return st;
+        }
+    }
+    return RMP_OK;
+}
+
+// initialise one replica's state in its workspace
+rmp_status init_replica(rmp_batch* b, int slot)
+{
+    Replica& R = b->reps[slot];
+    hipStream_t s = b->stream;
+    HIPCHK(hipMemsetAsync(R.ws, 0, R.lay.total, s));
+    ColloidParams cp = make_cp(&R.p);
+    RepState rs{};
+    rs.list_nmd = -1;
+    for (int c = 0; c < R.p.n_colloids; ++c)
+        for (int d = 0; d < 3; ++d) rs.X[c][d] = R.p.colloid_x[c][d];
+    HIPCHK(hipMemcpyAsync(R.ws + R.lay.cp, &cp, sizeof(cp), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(R.ws + R.lay.rs, &rs, sizeof(rs), hipMemcpyHostToDevice, s));
+    make_ptable(R);
+    HIPCHK(hipMemcpyAsync(R.ws + R.lay.ptable, R.ptable.data(), RMP_PTABLE * 8, hipMemcpyHostToDevice, s));
+    b->dirty = true;
+    rmp_status st = sync_ctl(b);
+    if (st != RMP_OK) return st;
+    const RepDesc* dD = b->d_desc + slot;
+    double* mean = (double*)(R.ws + R.lay.mean);
+    const int nch = R.desc.n_chunks;
+    if (R.p.precision == 32) {
+        hipLaunchKernelGGL((k_init<float>), dim3(nch), dim3(256), 0, s, dD);
+        hipLaunchKernelGGL(k_init_mean, dim3(1), dim3(256), 0, s, dD, mean);
+        hipLaunchKernelGGL((k_init_sub<float>), dim3(nch), dim3(256), 0, s, dD, (const double*)mean);
+    } else {
+        hipLaunchKernelGGL((k_init<double>), dim3(nch), dim3(256), 0, s, dD);
+        hipLaunchKernelGGL(k_init_mean, dim3(1), dim3(256), 0, s, dD, mean);
+        hipLaunchKernelGGL((k_init_sub<double>), dim3(nch), dim3(256), 0, s, dD, (const double*)mean);
+    }
+    rmp_status le = last_launch("init");
+    if (le != RMP_OK) return le;
+    R.list_valid = false;
+    return RMP_OK;
+}
+
+rmp_status admit(rmp_batch* b, int slot, const rmp_params* p, uint64_t seed, int32_t n_md,
+                 void* ws, size_t bytes)
+{
+    rmp_status st = validate(p);
+    if (st != RMP_OK) return st;
+    if (p->precision != b->precision) return RMP_EINVAL;
+    if (n_md < 1) return RMP_EINVAL;
+    Layout L = layout_of(p);
+    if (!ws || bytes < L.total) return RMP_ENOMEM;
+    if (((uintptr_t)ws) % ALIGN) return RMP_EINVAL;
+    Replica& R = b->reps[slot];
+    R = Replica{};
+    R.used = true;
+    R.p = *p;
+    R.seed = seed;
+    R.n_md = n_md;
+    R.ws = (char*)ws;
+    R.lay = L;
+    R.sz = sizes_of(p);
+    return init_replica(b, slot);
+}
+
+rmp_status batch_init(rmp_batch* b, int32_t nslots, int32_t precision, void* ctl, size_t bytes,
+                      void* stream)
+{
+    if (nslots < 1 || nslots > 4096 || (precision != 32 && precision != 64)) return RMP_EINVAL;
+    if (!ctl || bytes < ctl_bytes_for(nslots)) return RMP_ENOMEM;
+    if (((uintptr_t)ctl) % ALIGN) return RMP_EINVAL;
+    b->nslots = nslots;
+    b->precision = precision;
+    b->stream = (hipStream_t)stream;
+    HIPCHK(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b->join, hipEventDisableTiming));
+    b->ctl = (char*)ctl;
+    size_t o = 0;
+    b->d_desc = (RepDesc*)(b->ctl + o);
+    o += aup(sizeof(RepDesc) * (size_t)nslots);
+    for (int k = 0; k < 6; ++k) {
+        b->d_prefix[k] = (int32_t*)(b->ctl + o);
+        o += aup(4 * (size_t)(nslots + 1));
+    }
+    b->reps.assign(nslots, Replica{});
+    b->hdesc.assign(nslots, RepDesc{});
+    b->dirty = true;
+    return RMP_OK;
+}
+
+void batch_release(rmp_batch* b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (auto e : b->ev) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    b->gexec = nullptr; b->graph = nullptr; b->fork = b->join = nullptr; b->side = nullptr;
+    b->capture = nullptr;
+    b->ev.clear();
+}
+
+template <class T>
+rmp_status observe(rmp_batch* b, int slot, rmp_obs* o)
+{
+    Replica& R = b->reps[slot];
+    hipStream_t s = b->stream;
+    rmp_status st = sync_ctl(b);
+    if (st != RMP_OK) return st;
+    // the observation kernel runs over this replica only: a one-replica work
+    // list whose prefix is the identity prefix (prefix[0] == 0)
+    const int cnt = R.desc.n_chunks;
+    Work w;
+    w.desc = b->d_desc + slot;
+    w.prefix = b->d_prefix[PF_REP];
+    w.nrep = 1;
+    w.pad = 0;
+    hipLaunchKernelGGL((k_observe<T>), dim3(cnt), dim3(256), 0, s, w);
+    st = last_launch("k_observe");
+    if (st != RMP_OK) return st;
+    std::vector<double> part((size_t)cnt * 8);
+    RepState rs;
+    HIPCHK(hipMemcpyAsync(part.data(), R.ws + R.lay.obs_part, part.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&rs, R.ws + R.lay.rs, sizeof(rs), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (b->prof) flush_profile(b);
+    std::memset(o, 0, sizeof(*o));
+    double P[3] = {0, 0, 0}, ke = 0, nb = 0;
+    for (int k = 0; k < cnt; ++k) {
+        for (int d = 0; d < 3; ++d) P[d] += part[(size_t)k * 8 + d];
+        ke += part[(size_t)k * 8 + 3];
+        nb += part[(size_t)k * 8 + 4];
+    }
+    double kec = 0.0;
+    for (int d = 0; d < 3; ++d) o->momentum[d] = R.p.mass * P[d];
+    for (int c = 0; c < R.p.n_colloids; ++c) {
+        double v2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            o->momentum[d] += R.p.colloid_mass[c] * rs.V[c][d];
+            v2 += rs.V[c][d] * rs.V[c][d];
+            o->colloid_X[c][d] = rs.X[c][d];
+            o->colloid_V[c][d] = rs.V[c][d];
+        }
+        kec += 0.5 * R.p.colloid_mass[c] * v2;
+    }
+    o->ke_solvent = 0.5 * R.p.mass * ke;
+    o->ke_colloid = kec;
+    o->potential = rs.U;
+    o->temperature = rs.T_cells > 0 ? rs.T_sum / (3.0 * rs.T_cells) : 0.0;
+    o->n_cells_T = (int64_t)rs.T_cells;
+    o->e_rxn = rs.e_rxn;
+    o->n_B = (int64_t)nb;
+    o->n_A = R.sz.n - o->n_B;
+    o->n_cat_flips = rs.n_cat;
+    o->n_bulk_flips = rs.n_bulk;
+    o->md_step = rs.md_step;
+    o->coll_step = rs.coll_step;
+    o->n_candidates = rs.n_cand_used;
+    o->flags = rs.flags;
+    return rs.flags ? RMP_EDEVICE : RMP_OK;
+}
+
+template <class T>
+rmp_status get_state_t(rmp_batch* b, int slot, rmp_host_state* dst)
+{
+    Replica& R = b->reps[slot];
+    hipStream_t s = b->stream;
+    HIPCHK(hipStreamSynchronize(s));
+    RepState rs;
+    HIPCHK(hipMemcpy(&rs, R.ws + R.lay.rs, sizeof(rs), hipMemcpyDeviceToHost));
+    const int cur = (int)(rs.coll_step & 1);
+    const int64_t n = R.sz.n;
+    if (dst->x || dst->v) {
+        std::vector<T> buf((size_t)3 * n);
+        if (dst->x) {
+            HIPCHK(hipMemcpy(buf.data(), R.ws + R.lay.x[cur], 3 * n * sizeof(T), hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < 3 * n; ++i) dst->x[i] = (double)buf[i];
+        }
+        if (dst->v) {
+            HIPCHK(hipMemcpy(buf.data(), R.ws + R.lay.v[cur], 3 * n * sizeof(T), hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < 3 * n; ++i) dst->v[i] = (double)buf[i];
+        }
+    }
+    if (dst->id) HIPCHK(hipMemcpy(dst->id, R.ws + R.lay.id[cur], 4 * n, hipMemcpyDeviceToHost));
+    if (dst->state) HIPCHK(hipMemcpy(dst->state, R.ws + R.lay.st[cur], n, hipMemcpyDeviceToHost));
+    for (int c = 0; c < R.p.n_colloids; ++c)
+        for (int d = 0; d < 3; ++d) {
+            if (dst->X) dst->X[3 * c + d] = rs.X[c][d];
+            if (dst->V) dst->V[3 * c + d] = rs.V[c][d];
+        }
+    dst->md_step = rs.md_step;
+    dst->coll_step = rs.coll_step;
+    return RMP_OK;
+}
+
+template <class T>
+rmp_status set_state_t(rmp_batch* b, int slot, const rmp_host_state* src)
+{
+    Replica& R = b->reps[slot];
+    if (!src->x || !src->v || !src->id || !src->state) return RMP_EINVAL;
+    if (R.p.n_colloids > 0 && (!src->X || !src->V)) return RMP_EINVAL;
+    if (src->md_step < 0 || src->coll_step < 0) return RMP_EINVAL;
+    hipStream_t s = b->stream;
+    HIPCHK(hipStreamSynchronize(s));
+    RepState rs;
+    HIPCHK(hipMemcpy(&rs, R.ws + R.lay.rs, sizeof(rs), hipMemcpyDeviceToHost));
+    const int64_t n = R.sz.n;
+    const int cur = (int)(src->coll_step & 1);
+    std::vector<T> buf((size_t)3 * n);
+    for (int d = 0; d < 3; ++d)
+        for (int64_t i = 0; i < n; ++i) {
+            double xv = src->x[d * n + i];
+            if (!(xv >= 0.0 && xv < (double)R.p.L[d])) return RMP_EINVAL;
+            T xt = (T)xv;
+            if ((double)xt >= (double)R.p.L[d]) xt = (T)0;
+            buf[d * n + i] = xt;
+        }
+    HIPCHK(hipMemcpy(R.ws + R.lay.x[cur], buf.data(), 3 * n * sizeof(T), hipMemcpyHostToDevice));
+    for (int64_t i = 0; i < 3 * n; ++i) buf[i] = (T)src->v[i];
+    HIPCHK(hipMemcpy(R.ws + R.lay.v[cur], buf.data(), 3 * n * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(R.ws + R.lay.id[cur], src->id, 4 * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(R.ws + R.lay.st[cur], src->state, n, hipMemcpyHostToDevice));
+    for (int c = 0; c < R.p.n_colloids; ++c)
+        for (int d = 0; d < 3; ++d) {
+            rs.X[c][d] = src->X[3 * c + d];
+            rs.V[c][d] = src->V[3 * c + d];
+            rs.F[c][d] = 0.0;
+        }
+    rs.md_step = src->md_step;
+    rs.coll_step = src->coll_step;
+    HIPCHK(hipMemcpy(R.ws + R.lay.rs, &rs, sizeof(rs), hipMemcpyHostToDevice));
+    R.list_valid = false;
+    return RMP_OK;
+}
+
+rmp_status slot_ok(rmp_batch* b, int32_t slot)
+{
+    if (!b) return RMP_EINVAL;
+    if (slot < 0 || slot >= b->nslots) return RMP_EINVAL;
+    if (!b->reps[slot].used) return RMP_ESTATE;
+    return RMP_OK;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+
+extern "C" {
+
+const char* rmp_last_error(void) { return g_last_error; }
+
+const char* rmp_status_string(rmp_status st)
+{
+    switch (st) {
+    case RMP_OK: return "ok";
+    case RMP_EINVAL: return "invalid argument";
+    case RMP_ENOMEM: return "workspace too small";
+    case RMP_EHIP: return "HIP runtime error";
+    case RMP_EDEVICE: return "device flag set";
+    case RMP_ESTATE: return "invalid state for this call";
+    }
+    return "unknown status";
+}
+
+size_t rmp_workspace_bytes(const rmp_params* p, rmp_status* st)
+{
+    rmp_status s = validate(p);
+    if (st) *st = s;
+    if (s != RMP_OK) return 0;
+    return aup(layout_of(p).total) + ctl_bytes_for(1);
+}
+
+rmp_status rmp_init_system(const rmp_params* p, uint64_t seed, void* d_workspace,
+                           size_t workspace_bytes, void* stream, rmp_system** out)
+{
+    if (!out) return RMP_EINVAL;
+    *out = nullptr;
+    rmp_status st = validate(p);
+    if (st != RMP_OK) return st;
+    const size_t rep_bytes = aup(layout_of(p).total);
+    if (!d_workspace || workspace_bytes < rep_bytes + ctl_bytes_for(1)) return RMP_ENOMEM;
+    if (((uintptr_t)d_workspace) % ALIGN) return RMP_EINVAL;
+    rmp_system* s = new (std::nothrow) rmp_system();
+    if (!s) return RMP_ENOMEM;
+    s->b = &s->storage;
+    st = batch_init(s->b, 1, p->precision, (char*)d_workspace + rep_bytes, ctl_bytes_for(1), stream);
+    if (st == RMP_OK) st = admit(s->b, 0, p, seed, 1, d_workspace, rep_bytes);
+    if (st != RMP_OK) {
+        batch_release(s->b);
+        delete s;
+        return st;
+    }
+    *out = s;
+    return RMP_OK;
+}
+
+rmp_status rmp_step(rmp_system* s, int32_t n_md, int32_t n_collide)
+{
+    if (!s || n_md < 1 || n_collide < 0) return RMP_EINVAL;
+    Replica& R = s->b->reps[0];
+    if (R.n_md != n_md) {
+        R.n_md = n_md;
+        make_ptable(R);
+        HIPCHK(hipMemcpyAsync(R.ws + R.lay.ptable, R.ptable.data(), RMP_PTABLE * 8,
+                              hipMemcpyHostToDevice, s->b->stream));
+        HIPCHK(hipStreamSynchronize(s->b->stream));
+        s->b->dirty = true;
+    }
+    return batch_ticks(s->b, n_collide);
+}
+
+rmp_status rmp_observables(rmp_system* s, rmp_obs* out)
+{
+    if (!s || !out) return RMP_EINVAL;
+    return s->b->precision == 32 ? observe<float>(s->b, 0, out) : observe<double>(s->b, 0, out);
+}
+
+rmp_status rmp_get_state(rmp_system* s, rmp_host_state* dst)
+{
+    if (!s || !dst) return RMP_EINVAL;
+    return s->b->precision == 32 ? get_state_t<float>(s->b, 0, dst) : get_state_t<double>(s->b, 0, dst);
+}
+
+rmp_status rmp_set_state(rmp_system* s, const rmp_host_state* src)
+{
+    if (!s || !src) return RMP_EINVAL;
+    return s->b->precision == 32 ? set_state_t<float>(s->b, 0, src) : set_state_t<double>(s->b, 0, src);
+}
+
+rmp_status rmp_destroy(rmp_system* s)
+{
+    if (!s) return RMP_EINVAL;
+    if (s->b->stream) (void)hipStreamSynchronize(s->b->stream);
+    batch_release(s->b);
+    delete s;
+    return RMP_OK;
+}
+
+rmp_status rmp_set_tuning(rmp_system* s, const rmp_tuning* t)
+{
+    if (!s) return RMP_EINVAL;
+    return rmp_batch_set_tuning(s->b, t);
+}
+
+rmp_status rmp_get_tuning(rmp_system* s, rmp_tuning* t)
+{
+    if (!s || !t) return RMP_EINVAL;
+    *t = s->b->tun;
+    return RMP_OK;
+}
+
+rmp_status rmp_profile(rmp_system* s, int32_t enable)
+{
+    if (!s) return RMP_EINVAL;
+    rmp_batch* b = s->b;
+    flush_profile(b);
+    b->prof = enable != 0;
+    for (int k = 0; k < KN_COUNT; ++k) { b->prof_ms[k] = 0.0; b->prof_cnt[k] = 0; }
+    return RMP_OK;
+}
+
+int32_t rmp_profile_read(rmp_system* s, const char** names, double* ms_total, int64_t* count, int32_t cap)
+{
+    if (!s) return 0;
+    flush_profile(s->b);
+    int32_t m = 0;
+    for (int k = 0; k < KN_COUNT && m < cap; ++k, ++m) {
+        if (names) names[m] = KNAMES[k];
+        if (ms_total) ms_total[m] = s->b->prof_ms[k];
+        if (count) count[m] = s->b->prof_cnt[k];
+    }
+    return m;
+}
+
+size_t rmp_batch_ctl_bytes(int32_t n_slots)
+{
+    if (n_slots < 1) return 0;
+    return ctl_bytes_for(n_slots);
+}
+
+rmp_status rmp_batch_create(int32_t n_slots, int32_t precision, void* d_ctl, size_t ctl_bytes,
+                            void* stream, rmp_batch** out)
+{
+    if (!out) return RMP_EINVAL;
+    *out = nullptr;
+    rmp_batch* b = new (std::nothrow) rmp_batch();
+    if (!b) return RMP_ENOMEM;
+    rmp_status st = batch_init(b, n_slots, precision, d_ctl, ctl_bytes, stream);
+    if (st != RMP_OK) {
+        batch_release(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return RMP_OK;
+}
+
+rmp_status rmp_batch_set_slot(rmp_batch* b, int32_t slot, const rmp_params* p, uint64_t seed,
+                              int32_t n_md, void* d_workspace, size_t workspace_bytes)
+{
+    if (!b || slot < 0 || slot >= b->nslots) return RMP_EINVAL;
+    if (b->reps[slot].used) return RMP_ESTATE;
+    rmp_status st = admit(b, slot, p, seed, n_md, d_workspace, workspace_bytes);
+    if (st != RMP_OK) b->reps[slot] = Replica{};
+    b->dirty = true;
+    return st;
+}
+
+rmp_status rmp_batch_clear_slot(rmp_batch* b, int32_t slot)
+{
+    rmp_status st = slot_ok(b, slot);
+    if (st != RMP_OK) return st;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->reps[slot] = Replica{};
+    b->dirty = true;
+    return RMP_OK;
+}
+
+rmp_status rmp_batch_step(rmp_batch* b, int32_t n_ticks)
+{
+    if (!b) return RMP_EINVAL;
+    return batch_ticks(b, n_ticks);
+}
+
+rmp_status rmp_batch_slot_observables(rmp_batch* b, int32_t slot, rmp_obs* out)
+{
+    rmp_status st = slot_ok(b, slot);
+    if (st != RMP_OK) return st;
+    if (!out) return RMP_EINVAL;
+    return b->precision == 32 ? observe<float>(b, slot, out) : observe<double>(b, slot, out);
+}
+
+rmp_status rmp_batch_get_state(rmp_batch* b, int32_t slot, rmp_host_state* dst)
+{
+    rmp_status st = slot_ok(b, slot);
+    if (st != RMP_OK) return st;
+    if (!dst) return RMP_EINVAL;
+    return b->precision == 32 ? get_state_t<float>(b, slot, dst) : get_state_t<double>(b, slot, dst);
+}
+
+rmp_status rmp_batch_set_state(rmp_batch* b, int32_t slot, const rmp_host_state* src)
+{
+    rmp_status st = slot_ok(b, slot);
+    if (st != RMP_OK) return st;
+    if (!src) return RMP_EINVAL;
+    return b->precision == 32 ? set_state_t<float>(b, slot, src) : set_state_t<double>(b, slot, src);
+}
+
+rmp_status rmp_batch_set_tuning(rmp_batch* b, const rmp_tuning* t)
+{
+    if (!b || !t) return RMP_EINVAL;
+    rmp_tuning n = b->tun;
+    if (t->stream_block > 0) n.stream_block = t->stream_block;
+    if (t->stream_ppt > 0) n.stream_ppt = t->stream_ppt;
+    if (t->collide_cells > 0) n.collide_cells = t->collide_cells;
+    if (t->chain_k > 0) n.chain_k = t->chain_k;
+    if (t->use_graph >= 0) n.use_graph = t->use_graph;
+    if (n.chain_k != 1 && n.chain_k != 2 && n.chain_k != 4) return RMP_EINVAL;
+    if (n.stream_block != 64 && n.stream_block != 128 && n.stream_block != 256) return RMP_EINVAL;
+    b->tun = n;
+    b->dirty = true;
+    b->graph_valid = false;
+    return RMP_OK;
+}
+
+rmp_status rmp_batch_destroy(rmp_batch* b)
+{
+    if (!b) return RMP_EINVAL;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_release(b);
+    delete b;
+    return RMP_OK;
+}
+
+}  // extern "C"

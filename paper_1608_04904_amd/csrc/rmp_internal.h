@@ -1,0 +1,95 @@
+// Internal layout shared by the host runtime and the gfx950 kernels of the
+// rmpmd library.  Not part of the public C ABI (include/rmpmd.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rmpmd.h"
+
+namespace rmp {
+
+constexpr int MAXC = RMP_MAX_COLLOIDS;
+constexpr int CHUNK = 1024;          // particles per chunk (list compaction, init, observables)
+constexpr int SCAN_BLK = 4096;       // cells per block of the multi-block cell scan
+constexpr int CHAIN_BLOCK = 256;     // threads per Verlet-list workgroup
+constexpr int NVAL_MAX = 3 * MAXC + 1;  // reduced values per MD step: F per colloid + U
+constexpr int TILE_CAP = 2048;       // particles per collision tile held in LDS
+
+// Philox stream tags (key word 1); key word 0 is the replica seed.
+enum : uint64_t {
+    TAG_SHIFT = 1, TAG_ROT = 2, TAG_BULK = 3, TAG_CAT = 4, TAG_THERMO = 5,
+    TAG_INIT_POS = 6, TAG_INIT_VEL = 7
+};
+
+// Per-replica colloid parameters with host-derived constants.
+struct ColloidParams {
+    int32_t nc, nbonds;
+    int32_t catalytic[MAXC], ctype[MAXC], partner[MAXC];
+    int32_t bond_a[MAXC], bond_b[MAXC];
+    double bond_d[MAXC];
+    double sigma[MAXC], sig2[MAXC], rc2[MAXC], reachR[MAXC];
+    double epsA[MAXC], epsB[MAXC];
+    double mass[MAXC], imass[MAXC], hc[MAXC];
+    double eps_cc[2][2];
+};
+
+// Per-replica mutable state, device resident.
+struct RepState {
+    int64_t md_step, coll_step;
+    int64_t n_cand;            // Verlet-list length for the coming interval
+    int64_t n_cand_used;       // ... of the last interval run
+    int64_t n_cat, n_bulk;
+    int64_t list_nmd;          // n_md the current Verlet list was built for (-1: none)
+    uint32_t flags;
+    uint32_t bar;              // inter-workgroup barrier counter of the MD chain
+    double U, e_rxn;
+    double T_sum, T_cells;     // temperature estimator of the last collision
+    double X[MAXC][3], V[MAXC][3], F[MAXC][3];
+};
+
+// Per-replica descriptor, written by the host.
+struct RepDesc {
+    int32_t L[3];
+    int32_t active;
+    int64_t n, ncell;
+    int32_t n_md, rule;
+    int32_t n_chunks, n_tiles, n_scanblk, tile_cells;
+    int32_t cand_cap, G;       // Verlet-list capacity, MD-chain workgroups
+    int32_t chain_k, pad0;
+    double Ld[3], halfL[3];
+    double dt, h, tau, vscale, mass, ca, sa, cat_prob, skin_half2;
+    int32_t bulk_on, pad1;
+    uint64_t seed;
+    void* x[2];                // [3][n] storage-type arrays, double-buffered
+    void* v[2];
+    uint32_t* id[2];
+    uint8_t* st[2];
+    uint64_t* keyrank;         // (key << 32) | rank
+    uint32_t* perm;
+    uint32_t* count;           // [ncell]
+    uint32_t* start;           // [ncell + 1]
+    uint32_t* scanblk;         // [n_scanblk]
+    uint8_t* cflag;            // [n] Verlet-list membership for the coming interval
+    uint32_t* chunk_cnt;       // [n_chunks]
+    uint32_t* chunk_off;       // [n_chunks]
+    uint32_t* cand_idx;        // [cand_cap]
+    double* partials;          // [2][G][NVAL_MAX]
+    double* epart;             // [G][2] reaction energy / flips of the interval
+    double* tpart;             // [n_tiles][2]
+    double* ptable;            // [RMP_PTABLE]
+    double* obs_part;          // [n_chunks][8]
+    ColloidParams* cp;
+    RepState* rs;
+};
+
+// Work lists: items of one kind (particle chunks, cell tiles, scan blocks,
+// chain workgroups) concatenated over replicas.  prefix[r] is the first item
+// of replica r, prefix[nrep] the total.
+struct Work {
+    const RepDesc* desc;
+    const int32_t* prefix;
+    int32_t nrep;
+    int32_t pad;
+};
+
+}  // namespace rmp

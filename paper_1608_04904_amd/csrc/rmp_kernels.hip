@@ -1,0 +1,1365 @@
+// gfx950 kernels of the MPCD+MD solvent path.
+//
+// One interval (paper, "Algorithms"): n_md velocity-Verlet steps with WCA
+// colloid-solvent forces over a Verlet list built from the cell sort, exact
+// RATTLE for dimers and catalytic conversion, then one MPCD collision on a
+// randomly shifted grid with the RMPCD bulk reaction.  Kernels of one
+// interval, in stream order:
+//
+//   k_stream_bin   particles outside the Verlet list: n_md drifts held in
+//                  registers, then the cell key of the next collision and an
+//                  atomic rank (HBM-bound, one pass over x, v)
+//   k_chain        Verlet-list particles and colloids: n_md MD steps in
+//                  persistent workgroups; colloid forces reduced with a fixed
+//                  binary tree over list positions; inter-workgroup barrier
+//                  per step when the list spans several workgroups
+//   k_scan_*       exclusive scan of the cell counts -> cell_start
+//   k_scatter      perm[cell_start[key] + rank] = i
+//   k_collide      per LDS tile of cells: restore the stable (old-index)
+//                  order inside each cell, gather, FP64 centre-of-mass sums,
+//                  rotation about a random axis (or Anderson thermostat),
+//                  bulk B->A reaction, Verlet-list flags for the next
+//                  interval, coalesced write of the cell-ordered arrays
+//   k_chunk_scan   list compaction offsets, per-interval bookkeeping
+//   k_cand_write   compacted Verlet list
+//
+// Data layout in HBM: structure-of-arrays, x[3][N] and v[3][N] in the
+// storage precision (double or float), double-buffered across collisions.
+#include "rmp_device.h"
+
+namespace rmp {
+
+// ------------------------------------------------------------------ utils
+
+// deterministic block sum: wave butterfly, then a pairwise tree over the
+// wave sums (xor butterfly over the first NT/64 lanes of wave 0)
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sbuf)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v = v + __shfl_xor(v, m, 64);
+    constexpr int NW = NT / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sbuf[wave] = v;
+    __syncthreads();
+    if (NW > 1) {
+        if (wave == 0) {
+            double a = lane < NW ? sbuf[lane] : 0.0;
+#pragma unroll
+            for (int m = 1; m < NW; m <<= 1) a = a + __shfl_xor(a, m, 64);
+            if (lane == 0) sbuf[NW] = a;
+        }
+        __syncthreads();
+    }
+    double r = sbuf[NW > 1 ? NW : 0];
+    __syncthreads();
+    return r;
+}
+
+template <int NT>
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* sbuf)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sbuf[wave] = v;
+    __syncthreads();
+    uint32_t r = 0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) r += sbuf[k];
+    __syncthreads();
+    return r;
+}
+
+// exclusive block scan of u32, returns the prefix of this thread; *total set
+template <int NT>
+__device__ __forceinline__ uint32_t block_exscan_u32(uint32_t v, uint32_t* sbuf, uint32_t* total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        uint32_t o = __shfl_up(inc, m, 64);
+        if (lane >= m) inc += o;
+    }
+    __syncthreads();
+    if (lane == 63) sbuf[wave] = inc;
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) {
+        if (k < wave) wpre += sbuf[k];
+        tot += sbuf[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return wpre + inc - v;
+}
+
+__device__ __forceinline__ void shift_of(uint64_t seed, int64_t coll, double s[3])
+{
+    uint64_t w[4];
+    philox((uint64_t)coll, 0, 0, seed, TAG_SHIFT, w);
+    s[0] = u01(w[0]);
+    s[1] = u01(w[1]);
+    s[2] = u01(w[2]);
+}
+
+__device__ __forceinline__ uint32_t cell_key(const RepDesc& D, double x0, double x1, double x2,
+                                             const double s[3])
+{
+    int64_t c[3];
+    const double xs[3] = {x0, x1, x2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double fq = floor(xs[d] - s[d]);
+        int64_t q = (fq >= -1.0 && fq < (double)D.L[d]) ? (int64_t)fq : 0;   // NaN-safe
+        if (q < 0) q += D.L[d];
+        c[d] = q;
+    }
+    return (uint32_t)(c[0] + (int64_t)D.L[0] * (c[1] + (int64_t)D.L[1] * c[2]));
+}
+
+// Verlet-list membership for the coming interval of length tau: flagged
+// particles, or r_ic^2 < (r_cut,c + skin + |v| tau)^2 for some colloid c.
+__device__ __forceinline__ bool is_candidate(const RepDesc& D, const ColloidParams* cp, int nc,
+                                             const double (*Xw)[3], uint8_t st,
+                                             double x0, double x1, double x2,
+                                             double v0, double v1, double v2)
+{
+    if (st & 2) return true;
+    if (nc == 0) return false;
+    double vv = dot3(v0, v1, v2, v0, v1, v2);
+    double reach = sqrt(vv) * D.tau;
+    for (int c = 0; c < nc; ++c) {
+        double dx = min_image(x0 - Xw[c][0], D.Ld[0], D.halfL[0]);
+        double dy = min_image(x1 - Xw[c][1], D.Ld[1], D.halfL[1]);
+        double dz = min_image(x2 - Xw[c][2], D.Ld[2], D.halfL[2]);
+        double r2 = dot3(dx, dy, dz, dx, dy, dz);
+        double tt = cp->reachR[c] + reach;
+        if (r2 < tt * tt) return true;
+    }
+    return false;
+}
+
+// potential change of a solvent particle whose species changes (bookkeeping)
+__device__ __forceinline__ double species_dU(const RepDesc& D, const ColloidParams* cp, int nc,
+                                             const double (*Xw)[3], double x0, double x1,
+                                             double x2, int from, int to)
+{
+    double du = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        double dx = min_image(x0 - Xw[c][0], D.Ld[0], D.halfL[0]);
+        double dy = min_image(x1 - Xw[c][1], D.Ld[1], D.halfL[1]);
+        double dz = min_image(x2 - Xw[c][2], D.Ld[2], D.halfL[2]);
+        double r2 = dot3(dx, dy, dz, dx, dy, dz);
+        if (r2 < cp->rc2[c]) {
+            double cf, p0, p1;
+            wca(r2, cp->sig2[c], from ? cp->epsB[c] : cp->epsA[c], cf, p0);
+            wca(r2, cp->sig2[c], to ? cp->epsB[c] : cp->epsA[c], cf, p1);
+            du += p1 - p0;
+        }
+    }
+    return du;
+}
+
+template <class T>
+__device__ __forceinline__ T* comp(void* base, int64_t n, int d)
+{
+    return reinterpret_cast<T*>(base) + (int64_t)d * n;
+}
+
+// ------------------------------------------------------------------- init
+
+// Solvent initial state: uniform positions rejected inside colloid cores,
+// Maxwellian velocities; per-chunk velocity sums for the mean removal.
+template <class T>
+__global__ __launch_bounds__(256) void k_init(const RepDesc* Dp)
+{
+    const RepDesc& D = *Dp;
+    const ColloidParams* cp = D.cp;
+    RepState* rs = D.rs;
+    __shared__ double sXw[MAXC][3];
+    __shared__ double sred[8];
+    const int nc = cp->nc;
+    const int t = threadIdx.x;
+    if (t < nc)
+        for (int d = 0; d < 3; ++d) sXw[t][d] = colloid_image(rs->X[t][d], D.Ld[d]);
+    __syncthreads();
+    const int64_t n = D.n;
+    const int64_t base = (int64_t)blockIdx.x * CHUNK;
+    double sum[3] = {0.0, 0.0, 0.0};
+    bool bad = false;
+    for (int j = t; j < CHUNK; j += 256) {
+        int64_t i = base + j;
+        if (i >= n) break;
+        double xi[3] = {0.0, 0.0, 0.0};
+        bool ok = false;
+        for (uint64_t att = 0; att < 4096 && !ok; ++att) {
+            uint64_t w[4];
+            philox(att, (uint64_t)i, 0, D.seed, TAG_INIT_POS, w);
+            for (int d = 0; d < 3; ++d) xi[d] = u01(w[d]) * D.Ld[d];
+            ok = true;
+            for (int c = 0; c < nc && ok; ++c) {
+                double dx = min_image(xi[0] - sXw[c][0], D.Ld[0], D.halfL[0]);
+                double dy = min_image(xi[1] - sXw[c][1], D.Ld[1], D.halfL[1]);
+                double dz = min_image(xi[2] - sXw[c][2], D.Ld[2], D.halfL[2]);
+                if (dot3(dx, dy, dz, dx, dy, dz) < cp->sig2[c]) ok = false;
+            }
+        }
+        bad |= !ok;
+        uint64_t w[4];
+        double z[3];
+        philox(0, (uint64_t)i, 0, D.seed, TAG_INIT_VEL, w);
+        normals3(w, z);
+        for (int d = 0; d < 3; ++d) {
+            T xv = (T)xi[d];
+            if (xv >= (T)D.Ld[d]) xv = (T)0;    // FP32 rounding up to L
+            comp<T>(D.x[0], n, d)[i] = xv;
+            T vv = (T)(D.vscale * z[d]);
+            comp<T>(D.v[0], n, d)[i] = vv;
+            sum[d] += (double)vv;
+        }
+        D.id[0][i] = (uint32_t)i;
+        D.st[0][i] = 0;
+    }
+    if (bad) atomicOr(&rs->flags, RMP_FLAG_INIT);
+    for (int d = 0; d < 3; ++d) {
+        double s = block_sum<256>(sum[d], sred);
+        if (t == 0) D.obs_part[(int64_t)blockIdx.x * 8 + d] = s;
+    }
+}
+
+// mean velocity from the chunk sums (one workgroup)
+__global__ __launch_bounds__(256) void k_init_mean(const RepDesc* Dp, double* mean_out)
+{
+    const RepDesc& D = *Dp;
+    __shared__ double sred[8];
+    for (int d = 0; d < 3; ++d) {
+        double s = 0.0;
+        for (int k = threadIdx.x; k < D.n_chunks; k += 256) s += D.obs_part[(int64_t)k * 8 + d];
+        s = block_sum<256>(s, sred);
+        if (threadIdx.x == 0) mean_out[d] = D.n > 0 ? s / (double)D.n : 0.0;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_init_sub(const RepDesc* Dp, const double* mean)
+{
+    const RepDesc& D = *Dp;
+    const int64_t n = D.n;
+    const int64_t base = (int64_t)blockIdx.x * CHUNK;
+    for (int j = threadIdx.x; j < CHUNK; j += 256) {
+        int64_t i = base + j;
+        if (i >= n) break;
+        for (int d = 0; d < 3; ++d) {
+            T* v = comp<T>(D.v[0], n, d);
+            v[i] = (T)((double)v[i] - mean[d]);
+        }
+    }
+}
+
+// ------------------------------------------------------- Verlet list build
+
+// Stand-alone list flags (first interval, or a change of n_md).
+template <class T>
+__global__ __launch_bounds__(256) void k_list(Work w)
+{
+    const int item = blockIdx.x;
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int chunk = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    if (!D.active) return;
+    const ColloidParams* cp = D.cp;
+    RepState* rs = D.rs;
+    __shared__ double sXw[MAXC][3];
+    __shared__ uint32_t sred[4];
+    const int nc = cp->nc;
+    const int t = threadIdx.x;
+    if (t < nc)
+        for (int d = 0; d < 3; ++d) sXw[t][d] = colloid_image(rs->X[t][d], D.Ld[d]);
+    __syncthreads();
+    const int cur = (int)(rs->coll_step & 1);
+    const int64_t n = D.n;
+    const int64_t base = (int64_t)chunk * CHUNK;
+    uint32_t cnt = 0;
+    for (int j = t; j < CHUNK; j += 256) {
+        int64_t i = base + j;
+        if (i >= n) break;
+        double x0 = comp<T>(D.x[cur], n, 0)[i], x1 = comp<T>(D.x[cur], n, 1)[i],
+               x2 = comp<T>(D.x[cur], n, 2)[i];
+        double v0 = comp<T>(D.v[cur], n, 0)[i], v1 = comp<T>(D.v[cur], n, 1)[i],
+               v2 = comp<T>(D.v[cur], n, 2)[i];
+        bool c = is_candidate(D, cp, nc, sXw, D.st[cur][i], x0, x1, x2, v0, v1, v2);
+        D.cflag[i] = c ? 1 : 0;
+        cnt += c ? 1u : 0u;
+    }
+    uint32_t tot = block_sum_u32<256>(cnt, sred);
+    if (t == 0) D.chunk_cnt[chunk] = tot;
+}
+
+// Per replica (one workgroup each): exclusive scan of the chunk counts of
+// Verlet-list members, list length and capacity check, barrier reset.  When
+// `after_collision` is set it also closes the interval: collision-step
+// counter, temperature of the collision, reaction bookkeeping.
+__global__ __launch_bounds__(1024) void k_chunk_scan(Work w, int after_collision)
+{
+    const int rep = blockIdx.x;
+    const RepDesc& D = w.desc[rep];
+    if (!D.active) return;
+    RepState* rs = D.rs;
+    __shared__ uint32_t sbuf[16];
+    __shared__ double dbuf[32];
+    const int t = threadIdx.x;
+    const int nch = D.n_chunks;
+    const int per = (nch + 1023) / 1024;
+    uint32_t local = 0;
+    for (int k = 0; k < per; ++k) {
+        int q = t * per + k;
+        if (q < nch) local += D.chunk_cnt[q];
+    }
+    uint32_t total;
+    uint32_t pre = block_exscan_u32<1024>(local, sbuf, &total);
+    for (int k = 0; k < per; ++k) {
+        int q = t * per + k;
+        if (q < nch) {
+            D.chunk_off[q] = pre;
+            pre += D.chunk_cnt[q];
+        }
+    }
+    if (after_collision) {
+        double ts = 0.0, tc = 0.0, du = 0.0, nb = 0.0;
+        for (int k = t; k < D.n_tiles; k += 1024) {
+            ts += D.tpart[(int64_t)k * 4 + 0];
+            tc += D.tpart[(int64_t)k * 4 + 1];
+            du += D.tpart[(int64_t)k * 4 + 2];
+            nb += D.tpart[(int64_t)k * 4 + 3];
+        }
+        double eu = 0.0, ef = 0.0;
+        for (int k = t; k < D.G; k += 1024) {
+            eu += D.epart[(int64_t)k * 2 + 0];
+            ef += D.epart[(int64_t)k * 2 + 1];
+            D.epart[(int64_t)k * 2 + 0] = 0.0;
+            D.epart[(int64_t)k * 2 + 1] = 0.0;
+        }
+        ts = block_sum<1024>(ts, dbuf);
+        tc = block_sum<1024>(tc, dbuf);
+        du = block_sum<1024>(du, dbuf);
+        nb = block_sum<1024>(nb, dbuf);
+        eu = block_sum<1024>(eu, dbuf);
+        ef = block_sum<1024>(ef, dbuf);
+        if (t == 0) {
+            rs->T_sum = ts;
+            rs->T_cells = tc;
+            rs->e_rxn += du + eu;
+            rs->n_bulk += (int64_t)nb;
+            rs->n_cat += (int64_t)ef;
+            rs->coll_step += 1;
+        }
+    }
+    if (t == 0) {
+        rs->n_cand = total;
+        if ((int64_t)total > (int64_t)D.cand_cap) rs->flags |= RMP_FLAG_LIST_OVERFLOW;
+        rs->bar = 0;
+        rs->list_nmd = D.n_md;
+    }
+}
+
+// Compacted Verlet list in array order.
+__global__ __launch_bounds__(256) void k_cand_write(Work w)
+{
+    const int item = blockIdx.x;
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int chunk = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    if (!D.active) return;
+    __shared__ uint32_t sbuf[4];
+    const int64_t n = D.n;
+    const int64_t base = (int64_t)chunk * CHUNK;
+    constexpr int PER = CHUNK / 256;
+    const int t = threadIdx.x;
+    uint32_t f[PER];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        int64_t i = base + (int64_t)t * PER + k;
+        f[k] = (i < n) ? (uint32_t)D.cflag[i] : 0u;
+        cnt += f[k];
+    }
+    uint32_t total;
+    uint32_t pre = block_exscan_u32<256>(cnt, sbuf, &total) + D.chunk_off[chunk];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (f[k]) {
+            const int64_t i = base + (int64_t)t * PER + k;
+            if ((int64_t)pre < (int64_t)D.cand_cap) {
+                D.cand_idx[pre] = (uint32_t)i;
+            } else {
+                // beyond the list capacity (RMP_FLAG_LIST_OVERFLOW is set):
+                // the particle is streamed freely so that every particle is
+                // still binned exactly once
+                D.cflag[i] = 0;
+            }
+            pre++;
+        }
+    }
+    if (t == 0) D.chunk_cnt[chunk] = 0;
+}
+
+// ------------------------------------------------- free streaming + binning
+
+// Particles outside the Verlet list feel no force during the interval: n_md
+// drifts x <- fma(dt, v, x) with a periodic wrap after each.  The drift of a
+// coordinate is monotone, so if its final value is still inside the box no
+// wrap occurred and the per-step wrap can be skipped; otherwise the drifts
+// are replayed with the wrap.  Then the key of the shifted cell of the coming
+// collision and an atomic rank within the cell.
+template <class T>
+__global__ __launch_bounds__(256) void k_stream_bin(Work w)
+{
+    const int item = blockIdx.x;
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int chunk = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    if (!D.active) return;
+    RepState* rs = D.rs;
+    __shared__ double sshift[3];
+    const int64_t coll = rs->coll_step;
+    if (threadIdx.x == 0) shift_of(D.seed, coll, sshift);
+    __syncthreads();
+    const double s[3] = {sshift[0], sshift[1], sshift[2]};
+    const int cur = (int)(coll & 1);
+    const int64_t n = D.n;
+    const int nmd = D.n_md;
+    const T dt = (T)D.dt;
+    const T Lt[3] = {(T)D.Ld[0], (T)D.Ld[1], (T)D.Ld[2]};
+    T* xs[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
+    const T* vs[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
+    const int64_t base = (int64_t)chunk * CHUNK;
+    for (int j = threadIdx.x; j < CHUNK; j += blockDim.x) {
+        int64_t i = base + j;
+        if (i >= n) break;
+        if (D.cflag[i]) continue;
+        T x[3], v[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) { x[d] = xs[d][i]; v[d] = vs[d][i]; }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            T y = x[d];
+            for (int k = 0; k < nmd; ++k) y = tfma(dt, v[d], y);
+            bool inside = (v[d] >= (T)0) ? (y < Lt[d]) : (y >= (T)0);
+            if (!inside) {
+                y = x[d];
+                for (int k = 0; k < nmd; ++k) y = wrap_coord<T>(tfma(dt, v[d], y), Lt[d]);
+            }
+            x[d] = y;
+            xs[d][i] = y;
+        }
+        uint32_t key = cell_key(D, (double)x[0], (double)x[1], (double)x[2], s);
+        uint32_t rank = atomicAdd(&D.count[key], 1u);
+        D.keyrank[i] = ((uint64_t)key << 32) | rank;
+    }
+}
+
+// ------------------------------------------------------------- MD chain
+
+// inter-workgroup barrier of one replica's chain (bounded spin)
+__device__ __forceinline__ void chain_barrier(uint32_t* bar, uint32_t target, uint32_t* sflags)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __atomic_thread_fence(__ATOMIC_RELEASE);
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1u << 21)) {
+                *sflags |= RMP_FLAG_BARRIER;
+                break;
+            }
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void store_agent(double* p, double v)
+{
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p)
+{
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Chain workgroup g of a replica holds Verlet-list positions
+// [g*B, (g+1)*B), B = 256*K, K consecutive positions per thread, in
+// registers for the whole interval.
+template <class T, int K>
+struct ChainCtx {
+    double sX[MAXC][3], sV[MAXC][3], sF[MAXC][3], sXw[MAXC][3], sX0[MAXC][3], sXold[MAXC][3];
+    double sRed[CHAIN_BLOCK / 64][NVAL_MAX];
+    double sNode[NVAL_MAX];
+    double sU;
+    uint32_t sflags;
+};
+
+// Forces on this workgroup's list entries from all colloids, per-colloid
+// force sums and the potential reduced over list positions with the fixed
+// binary tree (within thread over K, wave butterfly, waves, workgroups).
+// On return sF holds the colloid forces (solvent part plus colloid-colloid),
+// sU the potential.
+template <class T, int K>
+__device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D, const ColloidParams* cp,
+                             int nc, const bool* valid, const T (*x)[3], const uint8_t* st,
+                             double (*f)[3], bool* inside, int g, int Gact, int Gpad,
+                             uint32_t& nbar, uint32_t* bar)
+{
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double u[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        f[j][0] = 0.0; f[j][1] = 0.0; f[j][2] = 0.0;
+        u[j] = 0.0;
+        inside[j] = false;
+    }
+    for (int c = 0; c < nc; ++c) {
+        const double Xc0 = S.sXw[c][0], Xc1 = S.sXw[c][1], Xc2 = S.sXw[c][2];
+        const double rc2 = cp->rc2[c], sig2 = cp->sig2[c];
+        const double eA = cp->epsA[c], eB = cp->epsB[c];
+        const bool cat = cp->catalytic[c] != 0;
+        double gx[K], gy[K], gz[K];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            gx[j] = 0.0; gy[j] = 0.0; gz[j] = 0.0;
+            if (valid[j]) {
+                double dx = min_image((double)x[j][0] - Xc0, D.Ld[0], D.halfL[0]);
+                double dy = min_image((double)x[j][1] - Xc1, D.Ld[1], D.halfL[1]);
+                double dz = min_image((double)x[j][2] - Xc2, D.Ld[2], D.halfL[2]);
+                double r2 = dot3(dx, dy, dz, dx, dy, dz);
+                if (r2 < rc2) {
+                    double coef, pot;
+                    wca(r2, sig2, (st[j] & 1) ? eB : eA, coef, pot);
+                    gx[j] = coef * dx; gy[j] = coef * dy; gz[j] = coef * dz;
+                    f[j][0] = f[j][0] + gx[j];
+                    f[j][1] = f[j][1] + gy[j];
+                    f[j][2] = f[j][2] + gz[j];
+                    u[j] = u[j] + pot;
+                    if (cat) inside[j] = true;
+                    any = true;
+                }
+            }
+        }
+        // reduce the three components over list positions
+        const bool wave_any = __ballot(any) != 0;
+        double r[3];
+        {
+            double a0[K], a1[K], a2[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) { a0[j] = gx[j]; a1[j] = gy[j]; a2[j] = gz[j]; }
+#pragma unroll
+            for (int s = 1; s < K; s <<= 1)
+#pragma unroll
+                for (int j = 0; j + s < K; j += 2 * s) {
+                    a0[j] = a0[j] + a0[j + s];
+                    a1[j] = a1[j] + a1[j + s];
+                    a2[j] = a2[j] + a2[j + s];
+                }
+            r[0] = a0[0]; r[1] = a1[0]; r[2] = a2[0];
+        }
+        if (wave_any) {
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) {
+                r[0] = r[0] + __shfl_xor(r[0], m, 64);
+                r[1] = r[1] + __shfl_xor(r[1], m, 64);
+                r[2] = r[2] + __shfl_xor(r[2], m, 64);
+            }
+        } else {
+            r[0] = 0.0; r[1] = 0.0; r[2] = 0.0;
+        }
+        if (lane == 0) {
+            S.sRed[wave][3 * c + 0] = r[0];
+            S.sRed[wave][3 * c + 1] = r[1];
+            S.sRed[wave][3 * c + 2] = r[2];
+        }
+    }
+    {
+        double a[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) a[j] = u[j];
+#pragma unroll
+        for (int s = 1; s < K; s <<= 1)
+#pragma unroll
+            for (int j = 0; j + s < K; j += 2 * s) a[j] = a[j] + a[j + s];
+        double r = a[0];
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) r = r + __shfl_xor(r, m, 64);
+        if (lane == 0) S.sRed[wave][3 * nc] = r;
+    }
+    __syncthreads();
+    const int nv = 3 * nc + 1;
+    constexpr int NW = CHAIN_BLOCK / 64;
+    if (t < nv) {
+        double a[NW];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) a[k] = S.sRed[k][t];
+#pragma unroll
+        for (int s = 1; s < NW; s <<= 1)
+#pragma unroll
+            for (int k = 0; k + s < NW; k += 2 * s) a[k] = a[k] + a[k + s];
+        S.sNode[t] = a[0];
+    }
+    if (Gact > 1) {
+        const int parity = (int)(nbar & 1);
+        double* part = D.partials + (int64_t)parity * D.G * NVAL_MAX;
+        if (t < nv) {
+            store_agent(&part[(int64_t)g * NVAL_MAX + t], S.sNode[t]);
+            __atomic_thread_fence(__ATOMIC_RELEASE);
+        }
+        nbar++;
+        chain_barrier(bar, nbar * (uint32_t)Gact, &S.sflags);
+        // tree over workgroups, padded with zeros to Gpad (a power of two);
+        // lane l holds workgroups [l*Q, l*Q+Q), Q = max(1, Gpad/64) <= 4
+        const int Q = Gpad > 64 ? Gpad / 64 : 1;
+        for (int v = wave; v < nv; v += NW) {
+            double b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                int gg = lane * Q + q;
+                b[q] = (q < Q && gg < Gact) ? load_agent(&part[(int64_t)gg * NVAL_MAX + v]) : 0.0;
+            }
+            double a = (Q == 1) ? b[0] : (Q == 2) ? (b[0] + b[1]) : ((b[0] + b[1]) + (b[2] + b[3]));
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) a = a + __shfl_xor(a, m, 64);
+            if (lane == 0) S.sNode[v] = a;
+        }
+        __syncthreads();
+    } else {
+        __syncthreads();
+    }
+    // colloid forces: solvent part, then colloid-colloid pairs in (a<b) order
+    if (t < nc) {
+        const int c = t;
+        double F[3] = {-S.sNode[3 * c + 0], -S.sNode[3 * c + 1], -S.sNode[3 * c + 2]};
+        for (int a = 0; a < nc; ++a) {
+            if (a == c || cp->partner[c] == a) continue;
+            const int lo = a < c ? a : c, hi = a < c ? c : a;
+            double dx = min_image(S.sXw[lo][0] - S.sXw[hi][0], D.Ld[0], D.halfL[0]);
+            double dy = min_image(S.sXw[lo][1] - S.sXw[hi][1], D.Ld[1], D.halfL[1]);
+            double dz = min_image(S.sXw[lo][2] - S.sXw[hi][2], D.Ld[2], D.halfL[2]);
+            double r2 = dot3(dx, dy, dz, dx, dy, dz);
+            double sab = cp->sigma[lo] + cp->sigma[hi];
+            double rc = 0x1.1f59ac3c7d6c0p+0 * sab;
+            if (r2 < rc * rc) {
+                double coef, pot;
+                wca(r2, sab * sab, cp->eps_cc[cp->ctype[lo]][cp->ctype[hi]], coef, pot);
+                double g3[3] = {coef * dx, coef * dy, coef * dz};
+                for (int d = 0; d < 3; ++d) F[d] = (c == lo) ? F[d] + g3[d] : F[d] - g3[d];
+            }
+        }
+        for (int d = 0; d < 3; ++d) S.sF[c][d] = F[d];
+    }
+    if (t == 0) {
+        double ucc = 0.0;
+        for (int a = 0; a < nc; ++a)
+            for (int b = a + 1; b < nc; ++b) {
+                if (cp->partner[a] == b) continue;
+                double dx = min_image(S.sXw[a][0] - S.sXw[b][0], D.Ld[0], D.halfL[0]);
+                double dy = min_image(S.sXw[a][1] - S.sXw[b][1], D.Ld[1], D.halfL[1]);
+                double dz = min_image(S.sXw[a][2] - S.sXw[b][2], D.Ld[2], D.halfL[2]);
+                double r2 = dot3(dx, dy, dz, dx, dy, dz);
+                double sab = cp->sigma[a] + cp->sigma[b];
+                double rc = 0x1.1f59ac3c7d6c0p+0 * sab;
+                if (r2 < rc * rc) {
+                    double coef, pot;
+                    wca(r2, sab * sab, cp->eps_cc[cp->ctype[a]][cp->ctype[b]], coef, pot);
+                    ucc = ucc + pot;
+                }
+            }
+        S.sU = S.sNode[3 * nc] + ucc;
+    }
+    __syncthreads();
+}
+
+template <class T, int K>
+__global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
+{
+    const int item = blockIdx.x;
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int g = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    if (!D.active) return;
+    RepState* rs = D.rs;
+    const ColloidParams* cp = D.cp;
+    const int nc = cp->nc;
+    constexpr int B = CHAIN_BLOCK * K;
+    int64_t ncand = rs->n_cand;
+    if (ncand > D.cand_cap) ncand = D.cand_cap;
+    int Gact = (int)((ncand + B - 1) / B);
+    if (Gact < 1) Gact = 1;
+    if (Gact > D.G) Gact = D.G;
+    if (g >= Gact) return;
+    int Gpad = 1;
+    while (Gpad < Gact) Gpad <<= 1;
+
+    __shared__ ChainCtx<T, K> S;
+    const int t = threadIdx.x;
+    if (t == 0) S.sflags = 0;
+    if (t < nc) {
+        for (int d = 0; d < 3; ++d) {
+            S.sX[t][d] = rs->X[t][d];
+            S.sV[t][d] = rs->V[t][d];
+            S.sX0[t][d] = S.sX[t][d];
+            S.sXw[t][d] = colloid_image(S.sX[t][d], D.Ld[d]);
+        }
+    }
+    const int64_t coll = rs->coll_step;
+    const int cur = (int)(coll & 1);
+    const int64_t md0 = rs->md_step;
+    const int nmd = D.n_md;
+    const int64_t n = D.n;
+    T* xb[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
+    T* vb[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
+    uint8_t* stb = D.st[cur];
+    const uint32_t* idb = D.id[cur];
+
+    bool valid[K];
+    int64_t idx[K];
+    T x[K][3], v[K][3];
+    double f[K][3];
+    uint8_t st[K];
+    uint32_t pid[K];
+    bool inside[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        int64_t pos = (int64_t)g * B + (int64_t)t * K + j;
+        valid[j] = pos < ncand;
+        idx[j] = valid[j] ? (int64_t)D.cand_idx[pos] : 0;
+        for (int d = 0; d < 3; ++d) {
+            x[j][d] = valid[j] ? xb[d][idx[j]] : (T)0;
+            v[j][d] = valid[j] ? vb[d][idx[j]] : (T)0;
+        }
+        st[j] = valid[j] ? stb[idx[j]] : 0;
+        pid[j] = valid[j] ? idb[idx[j]] : 0;
+    }
+    __syncthreads();
+    uint32_t nbar = 0;
+    uint32_t* bar = &rs->bar;
+    chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, bar);
+
+    const double dt = D.dt;
+    const T dtT = (T)dt, hT = (T)D.h;
+    const T Lt[3] = {(T)D.Ld[0], (T)D.Ld[1], (T)D.Ld[2]};
+    double eu = 0.0, ef = 0.0;
+    for (int step = 0; step < nmd; ++step) {
+        const int64_t md = md0 + step;
+        // colloids: half kick, drift, RATTLE position stage
+        if (t < nc) {
+            const int c = t;
+            for (int d = 0; d < 3; ++d) {
+                S.sV[c][d] = fma(cp->hc[c], S.sF[c][d], S.sV[c][d]);
+                S.sXold[c][d] = S.sX[c][d];
+                S.sX[c][d] = fma(dt, S.sV[c][d], S.sX[c][d]);
+            }
+        }
+        __syncthreads();
+        if (t < cp->nbonds) {
+            const int a = cp->bond_a[t], b = cp->bond_b[t];
+            const double dd = cp->bond_d[t];
+            double r0[3], sv[3];
+            for (int d = 0; d < 3; ++d) {
+                r0[d] = S.sXold[a][d] - S.sXold[b][d];
+                sv[d] = S.sX[a][d] - S.sX[b][d];
+            }
+            double mu = cp->imass[a] + cp->imass[b];
+            double r0r0 = dot3(r0[0], r0[1], r0[2], r0[0], r0[1], r0[2]);
+            double sr0 = dot3(sv[0], sv[1], sv[2], r0[0], r0[1], r0[2]);
+            double ss = dot3(sv[0], sv[1], sv[2], sv[0], sv[1], sv[2]);
+            double A = (mu * mu) * r0r0;
+            double Bh = mu * sr0;
+            double C = ss - (dd * dd);
+            double disc = (Bh * Bh) - (A * C);
+            if (disc < 0.0) {
+                atomicOr(&S.sflags, RMP_FLAG_RATTLE);
+                disc = 0.0;
+            }
+            double gq = C / (Bh + sqrt(disc));
+            double ga = gq * cp->imass[a], gb = gq * cp->imass[b];
+            double gad = ga / dt, gbd = gb / dt;
+            for (int d = 0; d < 3; ++d) {
+                S.sX[a][d] = S.sX[a][d] - (ga * r0[d]);
+                S.sX[b][d] = S.sX[b][d] + (gb * r0[d]);
+                S.sV[a][d] = S.sV[a][d] - (gad * r0[d]);
+                S.sV[b][d] = S.sV[b][d] + (gbd * r0[d]);
+            }
+        }
+        __syncthreads();
+        if (t < nc)
+            for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(S.sX[t][d], D.Ld[d]);
+        // solvent list entries: half kick, drift, wrap
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (!valid[j]) continue;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                v[j][d] = tfma(hT, (T)f[j][d], v[j][d]);
+                x[j][d] = wrap_coord<T>(tfma(dtT, v[j][d], x[j][d]), Lt[d]);
+            }
+        }
+        __syncthreads();
+        chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, bar);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (!valid[j]) continue;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) v[j][d] = tfma(hT, (T)f[j][d], v[j][d]);
+        }
+        // colloids: second half kick, RATTLE velocity stage
+        if (t < nc)
+            for (int d = 0; d < 3; ++d) S.sV[t][d] = fma(cp->hc[t], S.sF[t][d], S.sV[t][d]);
+        __syncthreads();
+        if (t < cp->nbonds) {
+            const int a = cp->bond_a[t], b = cp->bond_b[t];
+            double r[3], vr[3];
+            for (int d = 0; d < 3; ++d) {
+                r[d] = S.sX[a][d] - S.sX[b][d];
+                vr[d] = S.sV[a][d] - S.sV[b][d];
+            }
+            double mu = cp->imass[a] + cp->imass[b];
+            double rr = dot3(r[0], r[1], r[2], r[0], r[1], r[2]);
+            double vrr = dot3(vr[0], vr[1], vr[2], r[0], r[1], r[2]);
+            double k = vrr / (mu * rr);
+            double ka = k * cp->imass[a], kb = k * cp->imass[b];
+            for (int d = 0; d < 3; ++d) {
+                S.sV[a][d] = S.sV[a][d] - (ka * r[d]);
+                S.sV[b][d] = S.sV[b][d] + (kb * r[d]);
+            }
+        }
+        // catalysis: A inside a catalytic sphere is flagged; a flagged A
+        // outside all of them converts to B with probability cat_prob
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (!valid[j]) continue;
+            uint8_t s = st[j];
+            if (s & 1) continue;
+            if (inside[j]) {
+                st[j] = (uint8_t)(s | 2);
+            } else if (s & 2) {
+                bool flip = true;
+                if (D.cat_prob < 1.0) {
+                    uint64_t wv[4];
+                    philox((uint64_t)md, pid[j], 0, D.seed, TAG_CAT, wv);
+                    flip = u01(wv[0]) < D.cat_prob;
+                }
+                if (flip) {
+                    st[j] = 1;
+                    ef += 1.0;
+                    eu += species_dU(D, cp, nc, S.sXw, (double)x[j][0], (double)x[j][1],
+                                     (double)x[j][2], 0, 1);
+                } else {
+                    st[j] = 0;
+                }
+            }
+        }
+        // Verlet-list soundness: colloid displacement within the interval
+        if (t < nc) {
+            double dx = S.sX[t][0] - S.sX0[t][0], dy = S.sX[t][1] - S.sX0[t][1],
+                   dz = S.sX[t][2] - S.sX0[t][2];
+            if (dot3(dx, dy, dz, dx, dy, dz) >= D.skin_half2) atomicOr(&S.sflags, RMP_FLAG_DISPLACEMENT);
+        }
+        __syncthreads();
+    }
+    // write back list entries and bin them for the coming collision
+    double s3[3];
+    shift_of(D.seed, coll, s3);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (!valid[j]) continue;
+        const int64_t i = idx[j];
+        for (int d = 0; d < 3; ++d) {
+            xb[d][i] = x[j][d];
+            vb[d][i] = v[j][d];
+        }
+        stb[i] = st[j];
+        uint32_t key = cell_key(D, (double)x[j][0], (double)x[j][1], (double)x[j][2], s3);
+        uint32_t rank = atomicAdd(&D.count[key], 1u);
+        D.keyrank[i] = ((uint64_t)key << 32) | rank;
+    }
+    // reaction bookkeeping of this workgroup (combined after the collision)
+    __shared__ double sred[CHAIN_BLOCK / 64 + 1];
+    eu = block_sum<CHAIN_BLOCK>(eu, sred);
+    ef = block_sum<CHAIN_BLOCK>(ef, sred);
+    if (t == 0) {
+        D.epart[(int64_t)g * 2 + 0] = eu;
+        D.epart[(int64_t)g * 2 + 1] = ef;
+        if (S.sflags) atomicOr(&rs->flags, S.sflags);
+    }
+    if (g == 0) {
+        if (t < nc)
+            for (int d = 0; d < 3; ++d) {
+                rs->X[t][d] = S.sX[t][d];
+                rs->V[t][d] = S.sV[t][d];
+                rs->F[t][d] = S.sF[t][d];
+            }
+        if (t == 0) {
+            rs->U = S.sU;
+            rs->md_step = md0 + nmd;
+            rs->n_cand_used = ncand;
+            for (int c = 0; c < nc; ++c)
+                for (int d = 0; d < 3; ++d)
+                    if (!isfinite(S.sF[c][d])) atomicOr(&rs->flags, RMP_FLAG_NONFINITE);
+        }
+    }
+}
+
+// ------------------------------------------------------------- cell scan
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(Work w)
+{
+    const int item = blockIdx.x;
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int blk = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    if (!D.active) return;
+    __shared__ uint32_t sbuf[16];
+    const int64_t c0 = (int64_t)blk * SCAN_BLK;
+    uint32_t s = 0;
+    for (int k = 0; k < SCAN_BLK / 1024; ++k) {
+        int64_t c = c0 + (int64_t)threadIdx.x * (SCAN_BLK / 1024) + k;
+        if (c < D.ncell) s += D.count[c];
+    }
+    uint32_t tot = block_sum_u32<1024>(s, sbuf);
+    if (threadIdx.x == 0) D.scanblk[blk] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_final(Work w)
+{
+    const int item = blockIdx.x;
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int blk = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    if (!D.active) return;
+    __shared__ uint32_t sbuf[16];
+    uint32_t pre = 0;
+    for (int k = threadIdx.x; k < blk; k += 1024) pre += D.scanblk[k];
+    pre = block_sum_u32<1024>(pre, sbuf);
+    constexpr int PER = SCAN_BLK / 1024;
+    const int64_t c0 = (int64_t)blk * SCAN_BLK + (int64_t)threadIdx.x * PER;
+    uint32_t cnt[PER];
+    uint32_t loc = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        int64_t c = c0 + k;
+        cnt[k] = c < D.ncell ? D.count[c] : 0u;
+        loc += cnt[k];
+    }
+    uint32_t total;
+    uint32_t p = block_exscan_u32<1024>(loc, sbuf, &total) + pre;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        int64_t c = c0 + k;
+        if (c < D.ncell) {
+            D.start[c] = p;
+            D.count[c] = 0;
+            p += cnt[k];
+        }
+    }
+    if (blk == D.n_scanblk - 1 && threadIdx.x == 0) D.start[D.ncell] = pre + total;
+}
+
+__global__ __launch_bounds__(256) void k_scatter(Work w)
+{
+    const int item = blockIdx.x;
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int chunk = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    if (!D.active) return;
+    const int64_t base = (int64_t)chunk * CHUNK;
+    for (int j = threadIdx.x; j < CHUNK; j += 256) {
+        int64_t i = base + j;
+        if (i >= D.n) break;
+        uint64_t kr = D.keyrank[i];
+        uint32_t key = (uint32_t)(kr >> 32), rank = (uint32_t)kr;
+        D.perm[D.start[key] + rank] = (uint32_t)i;
+    }
+}
+
+// ------------------------------------------------------------- collision
+
+constexpr int COLL_NT = 256;
+constexpr int COLL_CAP = 1024;       // particles per LDS group
+constexpr int COLL_TCMAX = 64;       // cells per tile at most
+
+// MPCD collision on one tile of cells of the shifted grid.  Cells of the
+// tile are processed in groups whose particles fit in LDS; a cell larger
+// than the group capacity is handled by a serial fallback.
+template <class T, int RULE>
+__global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
+{
+    const int item = blockIdx.x;
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int tile = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    if (!D.active || D.rule != RULE) return;
+    RepState* rs = D.rs;
+    const ColloidParams* cp = D.cp;
+    const int nc = cp->nc;
+    const int t = threadIdx.x;
+
+    __shared__ uint32_t s_start[COLL_TCMAX + 1];
+    __shared__ uint32_t s_perm[COLL_CAP], s_src[COLL_CAP];
+    __shared__ double s_v[3][COLL_CAP];
+    __shared__ double s_g[3][RULE ? COLL_CAP : 1];
+    __shared__ uint8_t s_st[COLL_CAP];
+    __shared__ uint8_t s_cell[COLL_CAP];
+    __shared__ double s_u[COLL_TCMAX][3], s_n[COLL_TCMAX][3];
+    __shared__ int32_t s_flip[COLL_TCMAX], s_nn[COLL_TCMAX];
+    __shared__ double s_Xw[MAXC][3];
+    __shared__ int32_t s_group[2];
+    __shared__ double sred[COLL_NT / 64 + 1];
+
+    const int64_t coll = rs->coll_step;
+    const int cur = (int)(coll & 1), nxt = cur ^ 1;
+    const int64_t n = D.n;
+    const int TC = D.tile_cells;
+    const int64_t c0 = (int64_t)tile * TC;
+    const int64_t c1 = (c0 + TC < D.ncell) ? c0 + TC : D.ncell;
+    const int ncl = (int)(c1 - c0);
+    for (int k = t; k <= ncl; k += COLL_NT) s_start[k] = D.start[c0 + k];
+    if (t < nc)
+        for (int d = 0; d < 3; ++d) s_Xw[t][d] = colloid_image(rs->X[t][d], D.Ld[d]);
+    __syncthreads();
+
+    const T* xo[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
+    const T* vo[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
+    T* xn[3] = {comp<T>(D.x[nxt], n, 0), comp<T>(D.x[nxt], n, 1), comp<T>(D.x[nxt], n, 2)};
+    T* vn[3] = {comp<T>(D.v[nxt], n, 0), comp<T>(D.v[nxt], n, 1), comp<T>(D.v[nxt], n, 2)};
+    const uint32_t* ido = D.id[cur];
+    const uint8_t* sto = D.st[cur];
+    uint32_t* idn = D.id[nxt];
+    uint8_t* stn = D.st[nxt];
+    const double ca = D.ca, sa = D.sa, oma = 1.0 - D.ca;
+
+    double t_sum = 0.0, t_cells = 0.0, du_sum = 0.0, n_flip = 0.0;
+    int ga = 0;
+    while (ga < ncl) {
+        if (t == 0) {
+            int gb = ga + 1;
+            while (gb < ncl && s_start[gb + 1] - s_start[ga] <= (uint32_t)COLL_CAP) gb++;
+            s_group[0] = gb;
+        }
+        __syncthreads();
+        const int gb = s_group[0];
+        const uint32_t q0 = s_start[ga], q1 = s_start[gb];
+        const int ns = (int)(q1 - q0);
+        if (ns > COLL_CAP) {
+            // One cell larger than an LDS group (the group is this cell
+            // alone).  Stable order by counting ranks into scratch: the
+            // key/rank array is dead after the scatter and is reused here.
+            const int64_t cell = c0 + ga;
+            const int nn = ns;
+            uint32_t* srt = reinterpret_cast<uint32_t*>(D.keyrank);
+            for (int j = t; j < nn; j += COLL_NT) {
+                const uint32_t p = D.perm[q0 + j];
+                int r = 0;
+                for (int q = 0; q < nn; ++q) r += D.perm[q0 + q] < p ? 1 : 0;
+                srt[q0 + r] = p < (uint32_t)n ? p : 0u;
+            }
+            __syncthreads();
+            // ordered per-cell quantities by one thread (FP64, stable order)
+            if (t == 0) {
+                double S0 = 0.0, S1 = 0.0, S2 = 0.0;
+                for (int k = 0; k < nn; ++k) {
+                    const uint32_t p = srt[q0 + k] < (uint32_t)n ? srt[q0 + k] : 0u;
+                    S0 = S0 + (double)vo[0][p];
+                    S1 = S1 + (double)vo[1][p];
+                    S2 = S2 + (double)vo[2][p];
+                }
+                const double u0 = S0 / (double)nn, u1 = S1 / (double)nn, u2 = S2 / (double)nn;
+                double tsum = 0.0, G0 = 0.0, G1 = 0.0, G2 = 0.0;
+                int nB = 0;
+                for (int k = 0; k < nn; ++k) {
+                    const uint32_t p = srt[q0 + k] < (uint32_t)n ? srt[q0 + k] : 0u;
+                    double w0 = (double)vo[0][p] - u0, w1 = (double)vo[1][p] - u1,
+                           w2 = (double)vo[2][p] - u2;
+                    tsum = tsum + dot3(w0, w1, w2, w0, w1, w2);
+                    nB += sto[p] & 1;
+                    if constexpr (RULE == 1) {
+                        uint64_t wv[4]; double z[3];
+                        philox((uint64_t)coll, ido[p], 0, D.seed, TAG_THERMO, wv);
+                        normals3(wv, z);
+                        G0 = G0 + (D.vscale * z[0]);
+                        G1 = G1 + (D.vscale * z[1]);
+                        G2 = G2 + (D.vscale * z[2]);
+                    }
+                }
+                t_sum += (D.mass * tsum) / (double)(nn - 1);
+                t_cells += 1.0;
+                s_u[0][0] = u0; s_u[0][1] = u1; s_u[0][2] = u2;
+                if constexpr (RULE == 0) {
+                    double nax[3];
+                    marsaglia_axis(D.seed, (uint64_t)coll, (uint64_t)cell, nax);
+                    s_n[0][0] = nax[0]; s_n[0][1] = nax[1]; s_n[0][2] = nax[2];
+                } else {
+                    s_n[0][0] = G0 / (double)nn; s_n[0][1] = G1 / (double)nn; s_n[0][2] = G2 / (double)nn;
+                }
+                int flipk = -1;
+                if (D.bulk_on && nB > 0) {
+                    uint64_t wv[4];
+                    philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
+                    double P = D.ptable[nB < RMP_PTABLE ? nB : RMP_PTABLE - 1];
+                    if (u01(wv[0]) < P) {
+                        int jb = (int)(u01(wv[1]) * (double)nB);
+                        if (jb >= nB) jb = nB - 1;
+                        for (int k = 0; k < nn; ++k)
+                            if (sto[srt[q0 + k] < (uint32_t)n ? srt[q0 + k] : 0u] & 1) {
+                                if (jb == 0) { flipk = k; break; }
+                                jb--;
+                            }
+                    }
+                }
+                s_flip[0] = flipk;
+            }
+            __syncthreads();
+            const double u0 = s_u[0][0], u1 = s_u[0][1], u2 = s_u[0][2];
+            for (int k = t; k < nn; k += COLL_NT) {
+                const uint32_t p = srt[q0 + k] < (uint32_t)n ? srt[q0 + k] : 0u;
+                const double vv0 = (double)vo[0][p], vv1 = (double)vo[1][p], vv2 = (double)vo[2][p];
+                double v3[3];
+                if constexpr (RULE == 0) {
+                    const double nax[3] = {s_n[0][0], s_n[0][1], s_n[0][2]};
+                    double rw[3];
+                    rotate(nax, ca, sa, oma, vv0 - u0, vv1 - u1, vv2 - u2, rw);
+                    v3[0] = u0 + rw[0]; v3[1] = u1 + rw[1]; v3[2] = u2 + rw[2];
+                } else {
+                    uint64_t wv[4]; double z[3];
+                    philox((uint64_t)coll, ido[p], 0, D.seed, TAG_THERMO, wv);
+                    normals3(wv, z);
+                    v3[0] = u0 + ((D.vscale * z[0]) - s_n[0][0]);
+                    v3[1] = u1 + ((D.vscale * z[1]) - s_n[0][1]);
+                    v3[2] = u2 + ((D.vscale * z[2]) - s_n[0][2]);
+                }
+                uint8_t s = sto[p];
+                const T xt[3] = {xo[0][p], xo[1][p], xo[2][p]};
+                if (k == s_flip[0]) {
+                    du_sum += species_dU(D, cp, nc, s_Xw, (double)xt[0], (double)xt[1], (double)xt[2], 1, 0);
+                    n_flip += 1.0;
+                    s = 0;
+                }
+                const int64_t o = (int64_t)q0 + k;
+                const T vt[3] = {(T)v3[0], (T)v3[1], (T)v3[2]};
+                for (int d = 0; d < 3; ++d) { xn[d][o] = xt[d]; vn[d][o] = vt[d]; }
+                idn[o] = ido[p];
+                stn[o] = s;
+                bool cnd = is_candidate(D, cp, nc, s_Xw, s, (double)xt[0], (double)xt[1], (double)xt[2],
+                                        (double)vt[0], (double)vt[1], (double)vt[2]);
+                D.cflag[o] = cnd ? 1 : 0;
+                if (cnd) atomicAdd(&D.chunk_cnt[o / CHUNK], 1u);
+            }
+            __syncthreads();
+            ga = gb;
+            continue;
+        }
+        // 1. permutation entries and local cell of each slot
+        for (int j = t; j < ns; j += COLL_NT) {
+            s_perm[j] = D.perm[q0 + j];
+            const uint32_t q = q0 + j;
+            int lo = ga, hi = gb - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (s_start[mid] <= q) lo = mid; else hi = mid - 1;
+            }
+            s_cell[j] = (uint8_t)(lo - ga);
+        }
+        __syncthreads();
+        // 2. stable order inside each cell: rank by old index
+        for (int j = t; j < ns; j += COLL_NT) {
+            const int cl = ga + s_cell[j];
+            const int cb = (int)(s_start[cl] - q0), ce = (int)(s_start[cl + 1] - q0);
+            const uint32_t p = s_perm[j];
+            int r = 0;
+            for (int q = cb; q < ce; ++q) r += s_perm[q] < p ? 1 : 0;
+            s_src[cb + r] = p;
+        }
+        __syncthreads();
+        // 3. gather velocities and species in the stable order
+        for (int j = t; j < ns; j += COLL_NT) {
+            uint32_t p = s_src[j];
+            if (p >= (uint32_t)n) { p = 0; s_src[j] = 0; }   // memory safety only
+            s_v[0][j] = (double)vo[0][p];
+            s_v[1][j] = (double)vo[1][p];
+            s_v[2][j] = (double)vo[2][p];
+            s_st[j] = sto[p];
+            if constexpr (RULE == 1) {
+                uint64_t wv[4]; double z[3];
+                philox((uint64_t)coll, ido[p], 0, D.seed, TAG_THERMO, wv);
+                normals3(wv, z);
+                s_g[0][j] = D.vscale * z[0];
+                s_g[1][j] = D.vscale * z[1];
+                s_g[2][j] = D.vscale * z[2];
+            }
+        }
+        __syncthreads();
+        // 4. per cell: centre-of-mass velocity (sequential FP64 sum in the
+        //    stable order), temperature term, axis, bulk reaction
+        for (int lc = t; lc < gb - ga; lc += COLL_NT) {
+            const int cl = ga + lc;
+            const int64_t cell = c0 + cl;
+            const int cb = (int)(s_start[cl] - q0), ce = (int)(s_start[cl + 1] - q0);
+            const int nn = ce - cb;
+            s_nn[lc] = nn;
+            s_flip[lc] = -1;
+            if (nn >= 2) {
+                double S0 = 0.0, S1 = 0.0, S2 = 0.0;
+                for (int q = cb; q < ce; ++q) {
+                    S0 = S0 + s_v[0][q];
+                    S1 = S1 + s_v[1][q];
+                    S2 = S2 + s_v[2][q];
+                }
+                const double u0 = S0 / (double)nn, u1 = S1 / (double)nn, u2 = S2 / (double)nn;
+                double tsum = 0.0;
+                for (int q = cb; q < ce; ++q) {
+                    double w0 = s_v[0][q] - u0, w1 = s_v[1][q] - u1, w2 = s_v[2][q] - u2;
+                    tsum = tsum + dot3(w0, w1, w2, w0, w1, w2);
+                }
+                t_sum += (D.mass * tsum) / (double)(nn - 1);
+                t_cells += 1.0;
+                s_u[lc][0] = u0; s_u[lc][1] = u1; s_u[lc][2] = u2;
+                if constexpr (RULE == 0) {
+                    double nax[3];
+                    marsaglia_axis(D.seed, (uint64_t)coll, (uint64_t)cell, nax);
+                    s_n[lc][0] = nax[0]; s_n[lc][1] = nax[1]; s_n[lc][2] = nax[2];
+                } else {
+                    double G0 = 0.0, G1 = 0.0, G2 = 0.0;
+                    for (int q = cb; q < ce; ++q) {
+                        G0 = G0 + s_g[0][q];
+                        G1 = G1 + s_g[1][q];
+                        G2 = G2 + s_g[2][q];
+                    }
+                    s_n[lc][0] = G0 / (double)nn; s_n[lc][1] = G1 / (double)nn; s_n[lc][2] = G2 / (double)nn;
+                }
+            }
+            if (D.bulk_on && nn > 0) {
+                int nB = 0;
+                for (int q = cb; q < ce; ++q) nB += s_st[q] & 1;
+                if (nB > 0) {
+                    uint64_t wv[4];
+                    philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
+                    double P = D.ptable[nB < RMP_PTABLE ? nB : RMP_PTABLE - 1];
+                    if (u01(wv[0]) < P) {
+                        int jb = (int)(u01(wv[1]) * (double)nB);
+                        if (jb >= nB) jb = nB - 1;
+                        for (int q = cb; q < ce; ++q)
+                            if (s_st[q] & 1) {
+                                if (jb == 0) { s_flip[lc] = q; break; }
+                                jb--;
+                            }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // 5. rotate, react, flag for the next Verlet list, write in cell order
+        for (int j = t; j < ns; j += COLL_NT) {
+            const int lc = s_cell[j];
+            const uint32_t p = s_src[j];
+            double v3[3] = {s_v[0][j], s_v[1][j], s_v[2][j]};
+            if (s_nn[lc] >= 2) {
+                const double u0 = s_u[lc][0], u1 = s_u[lc][1], u2 = s_u[lc][2];
+                if constexpr (RULE == 0) {
+                    const double nax[3] = {s_n[lc][0], s_n[lc][1], s_n[lc][2]};
+                    double rw[3];
+                    rotate(nax, ca, sa, oma, v3[0] - u0, v3[1] - u1, v3[2] - u2, rw);
+                    v3[0] = u0 + rw[0]; v3[1] = u1 + rw[1]; v3[2] = u2 + rw[2];
+                } else {
+                    v3[0] = u0 + (s_g[0][j] - s_n[lc][0]);
+                    v3[1] = u1 + (s_g[1][j] - s_n[lc][1]);
+                    v3[2] = u2 + (s_g[2][j] - s_n[lc][2]);
+                }
+            }
+            uint8_t s = s_st[j];
+            const T xt[3] = {xo[0][p], xo[1][p], xo[2][p]};
+            if (s_flip[lc] == j) {
+                du_sum += species_dU(D, cp, nc, s_Xw, (double)xt[0], (double)xt[1], (double)xt[2], 1, 0);
+                n_flip += 1.0;
+                s = 0;
+            }
+            const int64_t o = (int64_t)q0 + j;
+            const T vt[3] = {(T)v3[0], (T)v3[1], (T)v3[2]};
+            for (int d = 0; d < 3; ++d) { xn[d][o] = xt[d]; vn[d][o] = vt[d]; }
+            idn[o] = ido[p];
+            stn[o] = s;
+            bool cnd = is_candidate(D, cp, nc, s_Xw, s, (double)xt[0], (double)xt[1], (double)xt[2],
+                                    (double)vt[0], (double)vt[1], (double)vt[2]);
+            D.cflag[o] = cnd ? 1 : 0;
+            if (cnd) atomicAdd(&D.chunk_cnt[o / CHUNK], 1u);
+        }
+        __syncthreads();
+        ga = gb;
+    }
+    t_sum = block_sum<COLL_NT>(t_sum, sred);
+    t_cells = block_sum<COLL_NT>(t_cells, sred);
+    du_sum = block_sum<COLL_NT>(du_sum, sred);
+    n_flip = block_sum<COLL_NT>(n_flip, sred);
+    if (t == 0) {
+        D.tpart[(int64_t)tile * 4 + 0] = t_sum;
+        D.tpart[(int64_t)tile * 4 + 1] = t_cells;
+        D.tpart[(int64_t)tile * 4 + 2] = du_sum;
+        D.tpart[(int64_t)tile * 4 + 3] = n_flip;
+    }
+}
+
+// ---------------------------------------------------------- observables
+
+template <class T>
+__global__ __launch_bounds__(256) void k_observe(Work w)
+{
+    const int item = blockIdx.x;
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int chunk = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    if (!D.active) return;
+    __shared__ double sred[8];
+    const int cur = (int)(D.rs->coll_step & 1);
+    const int64_t n = D.n;
+    const int64_t base = (int64_t)chunk * CHUNK;
+    double P0 = 0.0, P1 = 0.0, P2 = 0.0, ke = 0.0, nb = 0.0;
+    for (int j = threadIdx.x; j < CHUNK; j += 256) {
+        int64_t i = base + j;
+        if (i >= n) break;
+        double v0 = comp<T>(D.v[cur], n, 0)[i], v1 = comp<T>(D.v[cur], n, 1)[i],
+               v2 = comp<T>(D.v[cur], n, 2)[i];
+        P0 += v0; P1 += v1; P2 += v2;
+        ke += dot3(v0, v1, v2, v0, v1, v2);
+        nb += (double)(D.st[cur][i] & 1);
+    }
+    double r[5] = {P0, P1, P2, ke, nb};
+    for (int k = 0; k < 5; ++k) {
+        double s = block_sum<256>(r[k], sred);
+        if (threadIdx.x == 0) D.obs_part[(int64_t)chunk * 8 + k] = s;
+    }
+}
+
+// ----------------------------------------------------- explicit instances
+
+#define RMP_INST(T)                                                              \
+    template __global__ void k_init<T>(const RepDesc*);                          \
+    template __global__ void k_init_sub<T>(const RepDesc*, const double*);       \
+    template __global__ void k_list<T>(Work);                                    \
+    template __global__ void k_stream_bin<T>(Work);                              \
+    template __global__ void k_chain<T, 1>(Work);                                \
+    template __global__ void k_chain<T, 2>(Work);                                \
+    template __global__ void k_chain<T, 4>(Work);                                \
+    template __global__ void k_collide<T, 0>(Work);                              \
+    template __global__ void k_collide<T, 1>(Work);                              \
+    template __global__ void k_observe<T>(Work);
+
+RMP_INST(double)
+RMP_INST(float)
+
+}  // namespace rmp

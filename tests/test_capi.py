@@ -1,0 +1,92 @@
+"""The C-ABI library loads, exports every entry point include/rmpmd.h
+declares, and the ctypes mirrors of its structs match the header's layout
+(checked against the header compiled by gcc).  No compute calls: no GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rmpmd.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(rmp_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1608_04904_amd import _capi
+    lib = _capi.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(_capi.SIGNATURES), set(declared) ^ set(_capi.SIGNATURES)
+
+
+def test_struct_layout_matches_header():
+    from paper_1608_04904_amd import _capi
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "rmpmd.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(rmp_params), sizeof(rmp_obs), sizeof(rmp_host_state), sizeof(rmp_tuning));
+  printf("%zu %zu %zu %zu\n", offsetof(rmp_params, colloid_x), offsetof(rmp_params, bond_d),
+         offsetof(rmp_obs, flags), offsetof(rmp_obs, colloid_V));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "t")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split()
+    sizes = list(map(int, out))
+    assert sizes[0] == C.sizeof(_capi.Params)
+    assert sizes[1] == C.sizeof(_capi.Obs)
+    assert sizes[2] == C.sizeof(_capi.HostState)
+    assert sizes[3] == C.sizeof(_capi.Tuning)
+    assert sizes[4] == _capi.Params.colloid_x.offset
+    assert sizes[5] == _capi.Params.bond_d.offset
+    assert sizes[6] == _capi.Obs.flags.offset
+    assert sizes[7] == _capi.Obs.colloid_V.offset
+
+
+def test_workspace_bytes_and_validation_on_host():
+    """rmp_workspace_bytes is a pure host function: usable without a GPU."""
+    import workloads as W
+    from paper_1608_04904_amd import _capi, workspace_bytes
+    p = W.dimer32()
+    n64 = workspace_bytes(p)
+    p32 = dict(p); p32["precision"] = 32
+    n32 = workspace_bytes(p32)
+    assert 100 * p["n_solvent"] < n64 < 160 * p["n_solvent"]
+    assert n32 < n64
+    bad = dict(p); bad["L"] = (0, 32, 32)
+    with pytest.raises(_capi.RmpError):
+        workspace_bytes(bad)
+    bad = dict(p); bad["precision"] = 16
+    with pytest.raises(_capi.RmpError):
+        workspace_bytes(bad)
+    small = W.base_params(L=(6, 6, 6), rho=5)
+    W.add_colloid(small, (3, 3, 3), sigma=4.0)      # reach beyond half the box
+    with pytest.raises(_capi.RmpError):
+        workspace_bytes(small)
+
+
+def test_product_package_has_no_oracle_dependency():
+    pkg = os.path.join(ROOT, "paper_1608_04904_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "liboracle" not in text, f
+                assert "rmp_oracle" not in text, f

@@ -1,0 +1,294 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+FP64 state: trajectories from identical uploaded states are compared element
+by element and must be bit-identical (positions, velocities, ids, species and
+flags, colloid positions and velocities), because both sides evaluate the
+same defined sequence of IEEE operations (contraction off, explicit fma, the
+same Philox streams, the same fixed reduction tree).  Observables that are
+sums in a different order are compared to 1e-12 relative.  The Anderson
+thermostat uses transcendental functions (log, cos, sin) whose last bits
+differ between the GPU math library and glibc: compared to 1e-12.  FP32
+state is compared with the FP64 oracle to 1e-5 (relative to the field's
+scale), matched by particle id.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _rm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1608_04904_amd as rm
+    return rm
+
+
+def _run_both(p, state, seed, n_md, n_coll, tuning=None, per_call=None):
+    rm = _rm()
+    print(f"[parity] L={p['L']} N={p['n_solvent']} nc={len(p['colloids'])} n_md={n_md} "
+          f"n_coll={n_coll} tuning={tuning}", flush=True)
+    g = rm.System(p, seed)
+    if tuning:
+        g.set_tuning(**tuning)
+    g.set_state(state)
+    o = oracle.Oracle(p, seed, init=False)
+    o.set_state(state)
+    calls = per_call or [n_coll]
+    for k in calls:
+        g.step(n_md, k)
+        o.run(n_md, k)
+    return g, o
+
+
+def _assert_bitwise(gs, os_, what=""):
+    for k in ("id", "state", "x", "v", "X", "V"):
+        a, b = np.asarray(gs[k]), np.asarray(os_[k])
+        if not np.array_equal(a, b):
+            if a.dtype.kind == "f":
+                bad = np.argwhere(a != b)
+                diff = np.abs(a - b).max()
+                raise AssertionError(f"{what}: {k} differs at {len(bad)} entries, first {bad[:3].tolist()}, "
+                                     f"max abs diff {diff}")
+            bad = np.argwhere(a != b)
+            raise AssertionError(f"{what}: {k} differs at {len(bad)} entries, first {bad[:5].tolist()}")
+    assert gs["md_step"] == os_["md_step"] and gs["coll_step"] == os_["coll_step"]
+
+
+def _assert_obs(go, oo, rtol=1e-12):
+    for k in ("ke_solvent", "ke_colloid", "potential", "temperature"):
+        assert go[k] == pytest.approx(oo[k], rel=rtol, abs=1e-12), k
+    for k in ("n_A", "n_B", "n_cat_flips", "n_bulk_flips", "md_step", "coll_step",
+              "n_candidates", "n_cells_T"):
+        assert go[k] == oo[k], k
+    assert go["e_rxn"] == pytest.approx(oo["e_rxn"], rel=1e-9, abs=1e-9)
+    scale = math.sqrt(2 * oo["ke_solvent"] + 1.0)
+    assert np.allclose(go["momentum"], oo["momentum"], atol=1e-11 * scale)
+
+
+# ---------------------------------------------------------------- FP64 ---
+
+CASES = {
+    "sphere_small": lambda: W.scaled(W.sphere10(), L=(10, 10, 10), rho=4),
+    "dimer_react": lambda: W.dimer_system(L=16, rho=5, n_md=20, seed=3, bulk_rate=0.05),
+    "dimer_p05": lambda: W.dimer_system(L=14, rho=6, n_md=10, seed=4, bulk_rate=0.02, cat_prob=0.5),
+    "free_ragged": lambda: W.base_params(L=(7, 5, 9), rho=6, n_md=5),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_fp64_trajectory_bitwise(case):
+    p = CASES[case]()
+    s0 = W.random_state(p, 101, species_B_fraction=0.3, flag_fraction=0.05)
+    n_md = p["n_md"]
+    g, o = _run_both(p, s0, 5150, n_md, 4)
+    _assert_bitwise(g.get_state(), o.get_state(), case)
+    _assert_obs(g.observables(), o.observables())
+
+
+def test_fp64_gpu_init_matches_oracle_init():
+    rm = _rm()
+    p = W.sphere10()
+    g = rm.System(p, 77)
+    o = oracle.Oracle(p, 77)
+    gs, os_ = g.get_state(), o.get_state()
+    assert np.array_equal(gs["id"], os_["id"])
+    assert np.array_equal(gs["x"], os_["x"])           # u01 * L: exact on both sides
+    # Box-Muller uses log/cos/sin: last-bit differences, then the mean removal
+    assert np.allclose(gs["v"], os_["v"], rtol=0, atol=1e-13)
+    assert g.observables()["flags"] == 0
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(chain_k=1, collide_cells=8, stream_block=64, use_graph=0),
+    dict(chain_k=2, collide_cells=16, stream_block=128, use_graph=1),
+    dict(chain_k=4, collide_cells=64, stream_block=256, use_graph=1),
+])
+def test_fp64_launch_configuration_does_not_change_results(tuning):
+    """Different tile sizes, list blockings (and hence numbers of chain
+    workgroups and inter-workgroup barriers) and graph replay give the
+    oracle's bits."""
+    p = W.dimer_system(L=18, rho=8, n_md=12, seed=5, bulk_rate=0.03)
+    s0 = W.random_state(p, 102, species_B_fraction=0.2)
+    g, o = _run_both(p, s0, 99, 12, 3, tuning=tuning)
+    _assert_bitwise(g.get_state(), o.get_state(), str(tuning))
+
+
+def test_fp64_change_of_n_md_between_calls():
+    p = W.dimer_system(L=14, rho=5, n_md=10, seed=6, bulk_rate=0.05)
+    s0 = W.random_state(p, 103)
+    rm = _rm()
+    g = rm.System(p, 3)
+    g.set_state(s0)
+    o = oracle.Oracle(p, 3, init=False)
+    o.set_state(s0)
+    for n_md, k in [(10, 2), (7, 1), (13, 2), (10, 1)]:
+        g.step(n_md, k)
+        o.run(n_md, k)
+    _assert_bitwise(g.get_state(), o.get_state())
+
+
+def test_fp64_crowded_cells_and_oversized_cell():
+    """A cell holding 1500 particles (beyond one LDS group: serial path) and
+    one holding 300 (several groups per tile)."""
+    p = W.base_params(L=(8, 8, 8), rho=6, n_md=3)
+    s0 = W.random_state(p, 104)
+    rng = np.random.default_rng(5)
+    for d in range(3):
+        s0["x"][d, :1500] = 2.0 + rng.uniform(0.3, 0.7, 1500)
+        s0["x"][d, 1500:1800] = 5.0 + rng.uniform(0.3, 0.7, 300)
+    g, o = _run_both(p, s0, 11, 3, 2)
+    _assert_bitwise(g.get_state(), o.get_state(), "crowded")
+    _assert_obs(g.observables(), o.observables())
+
+
+def test_fp64_tiny_and_empty_systems():
+    for L, n in [((1, 1, 1), 5), ((3, 2, 1), 0), ((2, 2, 2), 1)]:
+        p = W.base_params(L=L, rho=1, n_md=2)
+        p["n_solvent"] = n
+        s0 = W.random_state(p, 105)
+        g, o = _run_both(p, s0, 12, 2, 3)
+        _assert_bitwise(g.get_state(), o.get_state(), f"L={L} n={n}")
+
+
+def test_fp64_anderson_thermostat():
+    p = W.dimer_system(L=14, rho=6, n_md=10, seed=7, bulk_rate=0.0)
+    p["rule"] = "at"
+    s0 = W.random_state(p, 106)
+    g, o = _run_both(p, s0, 13, 10, 1)
+    gs, os_ = g.get_state(), o.get_state()
+    assert np.array_equal(gs["id"], os_["id"])
+    assert np.allclose(gs["v"], os_["v"], rtol=0, atol=1e-12)
+    assert np.allclose(gs["x"], os_["x"], rtol=0, atol=1e-12)
+
+
+def test_fp64_many_list_workgroups():
+    """Large colloids and K=1: the Verlet list spans many workgroups (the
+    inter-workgroup barrier and the tree over workgroups are exercised)."""
+    p = W.base_params(L=(24, 24, 24), rho=10, n_md=8)
+    W.add_colloid(p, (12.0, 12.0, 12.0), sigma=6.0, eps_A=1.0, eps_B=0.7, catalytic=True)
+    W.add_colloid(p, (12.0, 12.0, 1.0), sigma=3.0)
+    s0 = W.random_state(p, 107, species_B_fraction=0.5)
+    g, o = _run_both(p, s0, 14, 8, 3, tuning=dict(chain_k=1))
+    ob = g.observables()
+    assert ob["n_candidates"] > 8 * 256, ob["n_candidates"]
+    _assert_bitwise(g.get_state(), o.get_state(), "many workgroups")
+    _assert_obs(ob, o.observables())
+
+
+def test_fp64_resume_and_determinism():
+    rm = _rm()
+    p = W.dimer_system(L=14, rho=6, n_md=10, seed=8, bulk_rate=0.05)
+    a = rm.System(p, 21)
+    a.step(10, 5)
+    b = rm.System(p, 21)
+    b.step(10, 2)
+    st = b.get_state()
+    c = rm.System(p, 21)
+    c.set_state(st)
+    c.step(10, 3)
+    sa, sc = a.get_state(), c.get_state()
+    _assert_bitwise(sa, sc, "resume")
+    d = rm.System(p, 21)
+    d.step(10, 5)
+    _assert_bitwise(sa, d.get_state(), "determinism")
+
+
+def test_fp64_full_size_dimer32_one_interval():
+    """The benchmark workload at full size (32^3 cells, 327,680 particles,
+    N_MD = 50), in the launch configuration the benchmark times."""
+    rm = _rm()
+    p = W.dimer32()
+    g = rm.System(p, W.BASE_SEED + 2)
+    s0 = g.get_state()
+    o = oracle.Oracle(p, W.BASE_SEED + 2, init=False)
+    o.set_state(s0)
+    g.step(50, 1)
+    o.run(50, 1)
+    _assert_bitwise(g.get_state(), o.get_state(), "dimer32")
+    _assert_obs(g.observables(), o.observables())
+
+
+# ---------------------------------------------------------------- errors ---
+
+def test_errors_are_reported():
+    rm = _rm()
+    p = W.dimer_system(L=14, rho=6, n_md=10, seed=9)
+    g = rm.System(p, 1)
+    s = g.get_state()
+    bad = dict(s)
+    bad["x"] = s["x"].copy()
+    bad["x"][0, 0] = 14.0                              # outside [0, L)
+    with pytest.raises(rm.RmpError):
+        g.set_state(bad)
+    with pytest.raises(rm.RmpError):
+        g.step(0, 1)
+    q = dict(p)
+    q["cand_capacity"] = 16                            # far too small
+    h = rm.System(q, 1)
+    h.step(10, 1)
+    with pytest.raises(rm.RmpError) as e:
+        h.observables()
+    assert e.value.flags & 16
+
+
+# ----------------------------------------------------------------- FP32 ---
+
+def test_fp32_one_interval_close_to_fp64_oracle():
+    p = W.dimer_system(L=16, rho=6, n_md=20, seed=10, bulk_rate=0.0, precision=32)
+    s0 = W.random_state(p, 108, float32=True)
+    g, o = _run_both(p, s0, 15, 20, 1)
+    gs, os_ = g.get_state(), o.get_state()
+    gi, oi = np.argsort(gs["id"]), np.argsort(os_["id"])
+    L = np.array(p["L"], dtype=float)[:, None]
+    dx = gs["x"][:, gi] - os_["x"][:, oi]
+    dx -= L * np.round(dx / L)
+    assert np.abs(dx).max() <= 1e-5 * L.max()
+    dv = gs["v"][:, gi] - os_["v"][:, oi]
+    assert np.abs(dv).max() <= 1e-5 * np.abs(os_["v"]).max()
+    assert np.allclose(gs["X"], os_["X"], rtol=1e-6, atol=1e-6)
+
+
+# ---------------------------------------------------------------- batch ---
+
+def test_batch_replicas_match_alone_and_oracle():
+    rm = _rm()
+    ps = [W.dimer_system(L=L, rho=5, n_md=nmd, seed=20 + i, bulk_rate=0.03)
+          for i, (L, nmd) in enumerate([(14, 10), (16, 7), (12, 10), (18, 5)])]
+    ps.append(W.base_params(L=(9, 7, 5), rho=6, n_md=4))
+    seeds = [31, 32, 33, 34, 35]
+    b = rm.Batch(len(ps), precision=64)
+    states = []
+    for i, p in enumerate(ps):
+        b.set_slot(i, p, seeds[i], p["n_md"])
+        s0 = W.random_state(p, 200 + i, species_B_fraction=0.2)
+        b.set_state(i, s0)
+        states.append(s0)
+    b.step(3)
+    for i, p in enumerate(ps):
+        o = oracle.Oracle(p, seeds[i], init=False)
+        o.set_state(states[i])
+        o.run(p["n_md"], 3)
+        _assert_bitwise(b.get_state(i), o.get_state(), f"replica {i}")
+        _assert_obs(b.observables(i), o.observables())
+    # retire one, admit another, keep stepping: the others are unaffected
+    b.clear_slot(1)
+    q = W.dimer_system(L=15, rho=5, n_md=9, seed=40, bulk_rate=0.03)
+    b.set_slot(1, q, 41, 9)
+    sq = W.random_state(q, 300)
+    b.set_state(1, sq)
+    b.step(2)
+    o = oracle.Oracle(q, 41, init=False)
+    o.set_state(sq)
+    o.run(9, 2)
+    _assert_bitwise(b.get_state(1), o.get_state(), "admitted")
+    o0 = oracle.Oracle(ps[0], seeds[0], init=False)
+    o0.set_state(states[0])
+    o0.run(ps[0]["n_md"], 5)
+    _assert_bitwise(b.get_state(0), o0.get_state(), "replica 0 after 5 ticks")
