@@ -1,0 +1,198 @@
+"""Benchmark of the MPCD+MD solvent hot path on one MI355X.
+
+Workload (default): chemically powered dimer nanomotor, periodic 32^3 cells,
+10 solvent particles per cell = 327,680 particles, catalytic C and
+non-catalytic N spheres (sigma 4, bond 6.7), eps_B = 0.5 on N, catalytic
+conversion with probability 1, bulk B->A rate 0.01, dt = 0.01,
+tau = 0.5 (50 MD steps per collision), FP64 state.  Synthetic seeded input:
+the library's own initialisation (uniform positions outside the colloids,
+Maxwellian velocities at kT = 1).
+
+One benchmark step = one interval of the method: 50 velocity-Verlet MD steps
+of all solvent particles and the dimer, then one MPCD collision with the
+bulk reaction.  value = solvent particle-steps per second
+= N * 50 * steps / wall time, inputs resident in HBM.
+
+The roofline object reports the dominant kernel: its average launch
+duration is measured with HIP events recorded by the library on the stream
+that kernel runs on, over a second pass of the same workload; achieved =
+algorithmic bytes per launch / that duration.  cpu_baseline times the FP64
+CPU oracle on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solvent particle-steps/s + % HBM peak; batched FP32 vs FP64; p50/p99 job latency"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def algorithmic_bytes(kernel: str, n: int, ncell: int, tb: int, n_cand: int) -> float:
+    """Bytes the method must move per launch (not counting re-reads):
+    stream_bin  per free particle: read x, v (6 tb) + list flag (1), write x
+                (3 tb) + key/rank (8); cell counters 8 B per cell.
+    collide     per particle: read perm (4), x, v (6 tb), id (4), state (1);
+                write x, v (6 tb), id (4), state (1), list flag (1); cell
+                starts 4 B per cell.
+    scatter     per particle: read key/rank (8), write perm (4); starts 4/cell.
+    scan_final  per cell: read count (4), write start (4), clear count (4).
+    chain       per list entry: read and write x, v, state (12 tb + 2)."""
+    nf = max(n - n_cand, 0)
+    if kernel == "stream_bin":
+        return nf * (9 * tb + 9) + 8 * ncell
+    if kernel == "collide":
+        return n * (12 * tb + 15) + 4 * ncell
+    if kernel == "scatter":
+        return n * 12 + 4 * ncell
+    if kernel == "scan_final":
+        return 12 * ncell
+    if kernel == "chain":
+        return n_cand * (12 * tb + 2)
+    if kernel in ("chunk_scan", "cand_write"):
+        return n * 1 + 8 * math.ceil(n / 1024)
+    return 0.0
+
+
+def workload(name: str, precision: int):
+    import workloads as W
+    if name == "dimer32":
+        p = W.dimer32(precision=precision)
+        return p, 50, W.BASE_SEED + 2, "dimer32: 32^3 cells, rho 10, N=327,680, 1 dimer (C+N, sigma 4, d 6.7), tau 0.5 (50 MD steps/collision)"
+    if name == "sphere10":
+        p = W.sphere10(precision=precision)
+        return p, 10, W.BASE_SEED + 1, "sphere10: 10^3 cells, rho 10, N=10,000, 1 WCA sphere sigma 2, tau 0.1 (10 MD steps/collision)"
+    if name == "large128":
+        p = W.large128(precision=precision)
+        return p, 50, W.BASE_SEED + 3, "large128: 128^3 cells, rho 10, N=20,971,520, 8 dimers, tau 0.5 (50 MD steps/collision)"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(p, n_md, seed, budget_s: float):
+    """Time the FP64 oracle on a bounded sample: whole intervals of the same
+    workload until about budget_s seconds of work."""
+    import oracle
+    o = oracle.Oracle(p, seed)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o.run(n_md, 1)                                 # warm-up interval
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        o.run(n_md, 1)
+        k += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=p["n_solvent"] * n_md * k / dt, unit="particle-steps/s", cores=threads,
+                kind="oracle",
+                sample=f"{k} intervals x {n_md} MD steps of the same workload "
+                       f"({p['n_solvent']} particles), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="dimer32")
+    ap.add_argument("--precision", type=int, default=64)
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--collide-cells", type=int, default=0)
+    ap.add_argument("--chain-k", type=int, default=0)
+    ap.add_argument("--stream-block", type=int, default=0)
+    ap.add_argument("--stream-ppt", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(each replica or job is independent; see the design notes for how a "
+              "single large system would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1608_04904_amd as rm
+
+    p, n_md, seed, desc = workload(args.workload, args.precision)
+    n = p["n_solvent"]
+    ncell = p["L"][0] * p["L"][1] * p["L"][2]
+    tb = 8 if args.precision == 64 else 4
+
+    print(f"[bench] workload {args.workload} N={n} n_md={n_md} precision={args.precision}",
+          file=sys.stderr, flush=True)
+    s = rm.System(p, seed)
+    tun = dict(use_graph=args.graph)
+    for k in ("collide_cells", "chain_k", "stream_block", "stream_ppt"):
+        if getattr(args, k) > 0:
+            tun[k] = getattr(args, k)
+    s.set_tuning(**tun)
+    s.step(n_md, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(n_md, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    value = n * n_md * args.steps / wall
+    ob = s.observables(raise_on_flags=False)
+    print(f"[bench] timed {args.steps} steps in {wall:.3f} s, flags={ob['flags']}",
+          file=sys.stderr, flush=True)
+
+    # per-kernel device time over a second pass (HIP events on each kernel's stream)
+    s.profile(True)
+    s.step(n_md, args.profile_steps)
+    prof = s.profile_read()
+    s.profile(False)
+    n_cand = ob["n_candidates"]
+    kern = {k: (ms / c, c) for k, (ms, c) in prof.items() if c > 0}
+    dom = max(kern, key=lambda k: kern[k][0] * kern[k][1])
+    avg_ms = kern[dom][0]
+    if dom == "chain":
+        # latency-bound chain of n_md small steps: report FP64 work against the
+        # vector FP64 peak (about 120 flops per list entry per MD step)
+        flops = 120.0 * n_cand * n_md
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=achieved / FP64_PEAK_TFLOPS, traffic=None, kernel=dom,
+                    avg_launch_ms=avg_ms)
+    else:
+        byts = algorithmic_bytes(dom, n, ncell, tb, n_cand)
+        achieved = byts / (avg_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=None, kernel=dom,
+                    avg_launch_ms=avg_ms)
+    kernels = {k: dict(avg_ms=round(v[0], 5), launches=v[1],
+                       algorithmic_GBps=round(algorithmic_bytes(k, n, ncell, tb, n_cand)
+                                              / (v[0] * 1e-3) / 1e9, 1))
+               for k, v in kern.items()}
+    print(f"[bench] kernels {json.dumps(kernels)}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(p, n_md, seed, args.cpu_seconds)
+
+    line = dict(
+        metric=METRIC, value=value, unit="particle-steps/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=1e3 * wall / args.steps, higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f64" if args.precision == 64 else "f32",
+        data="synthetic",
+        config=dict(workload=desc, n_solvent=n, n_md=n_md, precision=args.precision,
+                    n_candidates=n_cand, tuning=s.get_tuning()),
+        roofline=roof, cpu_baseline=cpu, kernels=kernels)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

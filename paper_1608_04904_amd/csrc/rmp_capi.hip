@@ -138,7 +138,7 @@ Layout layout_of(const rmp_params* p)
     L.chunk_cnt = take(4 * (size_t)s.n_chunks);
     L.chunk_off = take(4 * (size_t)s.n_chunks);
     L.cand_idx = take(4 * (size_t)s.cand_cap);
-    L.partials = take(2 * (size_t)s.G * NVAL_MAX * 8);
+    L.partials = take(2 * (size_t)s.G * NVAL_MAX * 2 * 8);
     L.epart = take((size_t)s.G * 2 * 8);
     L.tpart = take((size_t)s.n_tiles_max * 4 * 8);
     L.ptable = take(RMP_PTABLE * 8);
@@ -192,7 +192,7 @@ struct rmp_batch {
     bool dirty = true;
     bool have_rule[2] = {false, false};
     bool multi_scan = false;
-    rmp_tuning tun{256, 4, 32, 2, 1};
+    rmp_tuning tun{256, 1, 32, 1, 1};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
@@ -501,7 +501,12 @@ rmp_status launch_interval(rmp_batch* b, hipStream_t s)
         Timer tm(b, KN_STREAM, s);
         int bs = b->tun.stream_block;
         if (bs != 64 && bs != 128 && bs != 256) bs = 256;
-        hipLaunchKernelGGL((k_stream_bin<T>), dim3(nch), dim3(bs), 0, s, work(b, PF_CHUNK));
+        int ppt = b->tun.stream_ppt;
+        if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) ppt = 1;
+        int span = bs * ppt;
+        if (span > CHUNK) span = CHUNK;
+        const int wpc = CHUNK / span;
+        hipLaunchKernelGGL((k_stream_bin<T>), dim3(nch * wpc), dim3(bs), 0, s, work(b, PF_CHUNK), wpc);
     }
     HIPCHK(hipEventRecord(b->join, b->side));
     HIPCHK(hipStreamWaitEvent(s, b->join, 0));

@@ -73,7 +73,7 @@ struct RepDesc {
     uint32_t* chunk_cnt;       // [n_chunks]
     uint32_t* chunk_off;       // [n_chunks]
     uint32_t* cand_idx;        // [cand_cap]
-    double* partials;          // [2][G][NVAL_MAX]
+    double* partials;          // [2][G][NVAL_MAX][2] 64-bit exchange words of the MD chain
     double* epart;             // [G][2] reaction energy / flips of the interval
     double* tpart;             // [n_tiles][2]
     double* ptable;            // [RMP_PTABLE]

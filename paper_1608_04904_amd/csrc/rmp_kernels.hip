@@ -31,13 +31,41 @@ namespace rmp {
 
 // ------------------------------------------------------------------ utils
 
+// Pairwise binary tree over the 64 lanes of a wave with DPP moves:
+// xor 1 and xor 2 (quad permutes), 4-blocks (half-row mirror), 8-blocks (row
+// mirror), 16-blocks (row broadcast of lane 15 into rows 1 and 3), and the
+// two 32-blocks combined from lanes 31 and 63.  Each level adds the value of
+// the adjacent block of the same size, so the result is the tree
+// node(l, j) = node(l-1, 2j) + node(l-1, 2j+1) over lanes; it is returned in
+// every lane.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_tree_sum(double v)
+{
+    v = v + dpp_d<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+    v = v + dpp_d<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+    v = v + dpp_d<0x141, 0xF>(v);    // row_half_mirror
+    v = v + dpp_d<0x140, 0xF>(v);    // row_mirror
+    v = v + dpp_d<0x142, 0xA>(v);    // row_bcast15 into rows 1 and 3
+    const double a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 31),
+                                      __builtin_amdgcn_readlane(__double2loint(v), 31));
+    const double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                                      __builtin_amdgcn_readlane(__double2loint(v), 63));
+    return a + b;
+}
+
 // deterministic block sum: wave butterfly, then a pairwise tree over the
 // wave sums (xor butterfly over the first NT/64 lanes of wave 0)
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sbuf)
 {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v = v + __shfl_xor(v, m, 64);
+    v = wave_tree_sum(v);
     constexpr int NW = NT / 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __syncthreads();
@@ -359,6 +387,13 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(Work w, int after_collision
             rs->coll_step += 1;
         }
     }
+    if (!after_collision) {
+        // a stand-alone list build follows init or set_state, where the step
+        // counters may have moved backwards: clear the exchange words so no
+        // stale epoch can match
+        uint64_t* part = reinterpret_cast<uint64_t*>(D.partials);
+        for (int64_t k = t; k < (int64_t)2 * D.G * NVAL_MAX * 2; k += 1024) part[k] = 0ull;
+    }
     if (t == 0) {
         rs->n_cand = total;
         if ((int64_t)total > (int64_t)D.cand_cap) rs->flags |= RMP_FLAG_LIST_OVERFLOW;
@@ -410,16 +445,38 @@ __global__ __launch_bounds__(256) void k_cand_write(Work w)
 
 // ------------------------------------------------- free streaming + binning
 
+// Rank of this lane's particle within its cell, with one atomic per run of
+// equal keys in consecutive lanes (particles arrive sorted by the previous
+// collision's cells, so runs are common).  All 64 lanes must call it.
+__device__ __forceinline__ uint32_t wave_rank(uint32_t* count, uint32_t key, bool valid)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t k = valid ? key : 0xffffffffu;
+    const uint32_t prev = __shfl_up(k, 1, 64);
+    const bool head = (lane == 0) || (k != prev);
+    const uint64_t H = __ballot(head);
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int h = 63 - __clzll(H & upto);
+    const uint64_t above = (h == 63) ? 0ull : (H & (~0ull << (h + 1)));
+    const int nexth = above ? (__ffsll((long long)above) - 1) : 64;
+    uint32_t base = 0;
+    if (head && valid) base = atomicAdd(&count[key], (uint32_t)(nexth - h));
+    base = __shfl(base, h, 64);
+    return base + (uint32_t)(lane - h);
+}
+
 // Particles outside the Verlet list feel no force during the interval: n_md
 // drifts x <- fma(dt, v, x) with a periodic wrap after each.  The drift of a
 // coordinate is monotone, so if its final value is still inside the box no
 // wrap occurred and the per-step wrap can be skipped; otherwise the drifts
 // are replayed with the wrap.  Then the key of the shifted cell of the coming
-// collision and an atomic rank within the cell.
+// collision and a rank within the cell.  Workgroup `sub` of a chunk covers
+// particles [sub*span, (sub+1)*span) of it, span = blockDim.x * ppt.
 template <class T>
-__global__ __launch_bounds__(256) void k_stream_bin(Work w)
+__global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
 {
-    const int item = blockIdx.x;
+    const int item = blockIdx.x / wg_per_chunk;
+    const int sub = blockIdx.x - item * wg_per_chunk;
     const int rep = find_rep(w.prefix, w.nrep, item);
     const int chunk = item - w.prefix[rep];
     const RepDesc& D = w.desc[rep];
@@ -437,64 +494,37 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w)
     const T Lt[3] = {(T)D.Ld[0], (T)D.Ld[1], (T)D.Ld[2]};
     T* xs[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
     const T* vs[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
-    const int64_t base = (int64_t)chunk * CHUNK;
-    for (int j = threadIdx.x; j < CHUNK; j += blockDim.x) {
-        int64_t i = base + j;
-        if (i >= n) break;
-        if (D.cflag[i]) continue;
-        T x[3], v[3];
+    const int span = CHUNK / wg_per_chunk;
+    const int64_t base = (int64_t)chunk * CHUNK + (int64_t)sub * span;
+    for (int j0 = 0; j0 < span; j0 += blockDim.x) {
+        const int64_t i = base + j0 + threadIdx.x;
+        bool valid = (j0 + (int)threadIdx.x < span) && (i < n);
+        if (valid) valid = D.cflag[i] == 0;
+        uint32_t key = 0;
+        if (valid) {
+            T x[3], v[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) { x[d] = xs[d][i]; v[d] = vs[d][i]; }
+            for (int d = 0; d < 3; ++d) { x[d] = xs[d][i]; v[d] = vs[d][i]; }
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            T y = x[d];
-            for (int k = 0; k < nmd; ++k) y = tfma(dt, v[d], y);
-            bool inside = (v[d] >= (T)0) ? (y < Lt[d]) : (y >= (T)0);
-            if (!inside) {
-                y = x[d];
-                for (int k = 0; k < nmd; ++k) y = wrap_coord<T>(tfma(dt, v[d], y), Lt[d]);
+            for (int d = 0; d < 3; ++d) {
+                T y = x[d];
+                for (int k = 0; k < nmd; ++k) y = tfma(dt, v[d], y);
+                const bool inside = (v[d] >= (T)0) ? (y < Lt[d]) : (y >= (T)0);
+                if (!inside) {
+                    y = x[d];
+                    for (int k = 0; k < nmd; ++k) y = wrap_coord<T>(tfma(dt, v[d], y), Lt[d]);
+                }
+                x[d] = y;
+                xs[d][i] = y;
             }
-            x[d] = y;
-            xs[d][i] = y;
+            key = cell_key(D, (double)x[0], (double)x[1], (double)x[2], s);
         }
-        uint32_t key = cell_key(D, (double)x[0], (double)x[1], (double)x[2], s);
-        uint32_t rank = atomicAdd(&D.count[key], 1u);
-        D.keyrank[i] = ((uint64_t)key << 32) | rank;
+        const uint32_t rank = wave_rank(D.count, key, valid);
+        if (valid) D.keyrank[i] = ((uint64_t)key << 32) | rank;
     }
 }
 
 // ------------------------------------------------------------- MD chain
-
-// inter-workgroup barrier of one replica's chain (bounded spin)
-__device__ __forceinline__ void chain_barrier(uint32_t* bar, uint32_t target, uint32_t* sflags)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __atomic_thread_fence(__ATOMIC_RELEASE);
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > (1u << 21)) {
-                *sflags |= RMP_FLAG_BARRIER;
-                break;
-            }
-        }
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ void store_agent(double* p, double v)
-{
-    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __double_as_longlong(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_agent(const double* p)
-{
-    return __longlong_as_double((long long)__hip_atomic_load(
-        reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
 
 // Chain workgroup g of a replica holds Verlet-list positions
 // [g*B, (g+1)*B), B = 256*K, K consecutive positions per thread, in
@@ -517,7 +547,7 @@ template <class T, int K>
 __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D, const ColloidParams* cp,
                              int nc, const bool* valid, const T (*x)[3], const uint8_t* st,
                              double (*f)[3], bool* inside, int g, int Gact, int Gpad,
-                             uint32_t& nbar, uint32_t* bar)
+                             uint32_t& nbar, uint32_t epoch0)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double u[K];
@@ -534,26 +564,28 @@ __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D
         const bool cat = cp->catalytic[c] != 0;
         double gx[K], gy[K], gz[K];
         bool any = false;
+        // branch-free over the K entries (selects instead of divergent
+        // branches, so the entries' dependency chains interleave); the
+        // untaken case evaluates the potential at the cut-off and discards it
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            gx[j] = 0.0; gy[j] = 0.0; gz[j] = 0.0;
-            if (valid[j]) {
-                double dx = min_image((double)x[j][0] - Xc0, D.Ld[0], D.halfL[0]);
-                double dy = min_image((double)x[j][1] - Xc1, D.Ld[1], D.halfL[1]);
-                double dz = min_image((double)x[j][2] - Xc2, D.Ld[2], D.halfL[2]);
-                double r2 = dot3(dx, dy, dz, dx, dy, dz);
-                if (r2 < rc2) {
-                    double coef, pot;
-                    wca(r2, sig2, (st[j] & 1) ? eB : eA, coef, pot);
-                    gx[j] = coef * dx; gy[j] = coef * dy; gz[j] = coef * dz;
-                    f[j][0] = f[j][0] + gx[j];
-                    f[j][1] = f[j][1] + gy[j];
-                    f[j][2] = f[j][2] + gz[j];
-                    u[j] = u[j] + pot;
-                    if (cat) inside[j] = true;
-                    any = true;
-                }
-            }
+            const double dx = min_image((double)x[j][0] - Xc0, D.Ld[0], D.halfL[0]);
+            const double dy = min_image((double)x[j][1] - Xc1, D.Ld[1], D.halfL[1]);
+            const double dz = min_image((double)x[j][2] - Xc2, D.Ld[2], D.halfL[2]);
+            const double r2 = dot3(dx, dy, dz, dx, dy, dz);
+            const bool hit = valid[j] && (r2 < rc2);
+            double coef, pot;
+            wca(hit ? r2 : rc2, sig2, (st[j] & 1) ? eB : eA, coef, pot);
+            const double ax = coef * dx, ay = coef * dy, az = coef * dz;
+            gx[j] = hit ? ax : 0.0;
+            gy[j] = hit ? ay : 0.0;
+            gz[j] = hit ? az : 0.0;
+            f[j][0] = hit ? f[j][0] + ax : f[j][0];
+            f[j][1] = hit ? f[j][1] + ay : f[j][1];
+            f[j][2] = hit ? f[j][2] + az : f[j][2];
+            u[j] = hit ? u[j] + pot : u[j];
+            inside[j] = inside[j] || (hit && cat);
+            any = any || hit;
         }
         // reduce the three components over list positions
         const bool wave_any = __ballot(any) != 0;
@@ -573,12 +605,9 @@ __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D
             r[0] = a0[0]; r[1] = a1[0]; r[2] = a2[0];
         }
         if (wave_any) {
-#pragma unroll
-            for (int m = 1; m < 64; m <<= 1) {
-                r[0] = r[0] + __shfl_xor(r[0], m, 64);
-                r[1] = r[1] + __shfl_xor(r[1], m, 64);
-                r[2] = r[2] + __shfl_xor(r[2], m, 64);
-            }
+            r[0] = wave_tree_sum(r[0]);
+            r[1] = wave_tree_sum(r[1]);
+            r[2] = wave_tree_sum(r[2]);
         } else {
             r[0] = 0.0; r[1] = 0.0; r[2] = 0.0;
         }
@@ -596,9 +625,7 @@ __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D
         for (int s = 1; s < K; s <<= 1)
 #pragma unroll
             for (int j = 0; j + s < K; j += 2 * s) a[j] = a[j] + a[j + s];
-        double r = a[0];
-#pragma unroll
-        for (int m = 1; m < 64; m <<= 1) r = r + __shfl_xor(r, m, 64);
+        const double r = wave_tree_sum(a[0]);
         if (lane == 0) S.sRed[wave][3 * nc] = r;
     }
     __syncthreads();
@@ -615,28 +642,51 @@ __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D
         S.sNode[t] = a[0];
     }
     if (Gact > 1) {
-        const int parity = (int)(nbar & 1);
-        double* part = D.partials + (int64_t)parity * D.G * NVAL_MAX;
-        if (t < nv) {
-            store_agent(&part[(int64_t)g * NVAL_MAX + t], S.sNode[t]);
-            __atomic_thread_fence(__ATOMIC_RELEASE);
-        }
+        // Exchange of the workgroup nodes: value v of workgroup g is
+        // published as two 64-bit words (low and high half of the double,
+        // each with the barrier's epoch in its low 32 bits).  A reader
+        // accepts a word only when its epoch matches, so no separate flag,
+        // fence or counter is needed.  Epochs are unique per barrier of the
+        // replica; the two buffers alternate between barriers.
         nbar++;
-        chain_barrier(bar, nbar * (uint32_t)Gact, &S.sflags);
+        const uint32_t epoch = epoch0 + nbar;
+        uint64_t* part = reinterpret_cast<uint64_t*>(D.partials) +
+                         (int64_t)(nbar & 1) * D.G * NVAL_MAX * 2;
+        if (t < nv) {
+            const double val = S.sNode[t];
+            const uint64_t lo = ((uint64_t)(uint32_t)__double2loint(val) << 32) | epoch;
+            const uint64_t hi = ((uint64_t)(uint32_t)__double2hiint(val) << 32) | epoch;
+            __hip_atomic_store(&part[((int64_t)g * NVAL_MAX + t) * 2 + 0], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&part[((int64_t)g * NVAL_MAX + t) * 2 + 1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         // tree over workgroups, padded with zeros to Gpad (a power of two);
         // lane l holds workgroups [l*Q, l*Q+Q), Q = max(1, Gpad/64) <= 4
         const int Q = Gpad > 64 ? Gpad / 64 : 1;
         for (int v = wave; v < nv; v += NW) {
-            double b[4];
+            double b4[4] = {0.0, 0.0, 0.0, 0.0};
+            uint32_t spins = 0;
+            while (true) {
+                bool ok = true;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                int gg = lane * Q + q;
-                b[q] = (q < Q && gg < Gact) ? load_agent(&part[(int64_t)gg * NVAL_MAX + v]) : 0.0;
+                for (int q = 0; q < 4; ++q) {
+                    const int gg = lane * Q + q;
+                    if (q < Q && gg < Gact) {
+                        const int64_t o = ((int64_t)gg * NVAL_MAX + v) * 2;
+                        const uint64_t lo = __hip_atomic_load(&part[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const uint64_t hi = __hip_atomic_load(&part[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = ok && ((uint32_t)lo == epoch) && ((uint32_t)hi == epoch);
+                        b4[q] = __hiloint2double((int)(hi >> 32), (int)(lo >> 32));
+                    }
+                }
+                if (__ballot(!ok) == 0) break;
+                if (++spins > (1u << 22)) {
+                    if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
+                    break;
+                }
             }
-            double a = (Q == 1) ? b[0] : (Q == 2) ? (b[0] + b[1]) : ((b[0] + b[1]) + (b[2] + b[3]));
-#pragma unroll
-            for (int m = 1; m < 64; m <<= 1) a = a + __shfl_xor(a, m, 64);
-            if (lane == 0) S.sNode[v] = a;
+            double a2 = (Q == 1) ? b4[0] : (Q == 2) ? (b4[0] + b4[1]) : ((b4[0] + b4[1]) + (b4[2] + b4[3]));
+            a2 = wave_tree_sum(a2);
+            if (lane == 0) S.sNode[v] = a2;
         }
         __syncthreads();
     } else {
@@ -749,8 +799,10 @@ __global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
     }
     __syncthreads();
     uint32_t nbar = 0;
-    uint32_t* bar = &rs->bar;
-    chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, bar);
+    // barrier epochs: unique per barrier of the replica between list
+    // rebuilds (md_step + coll_step grows by n_md + 1 per interval)
+    const uint32_t epoch0 = (uint32_t)(md0 + coll);
+    chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, epoch0);
 
     const double dt = D.dt;
     const T dtT = (T)dt, hT = (T)D.h;
@@ -801,10 +853,10 @@ __global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
         __syncthreads();
         if (t < nc)
             for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(S.sX[t][d], D.Ld[d]);
-        // solvent list entries: half kick, drift, wrap
+        // solvent list entries: half kick, drift, wrap (entries past the end
+        // of the list hold dummies that are never written back)
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            if (!valid[j]) continue;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 v[j][d] = tfma(hT, (T)f[j][d], v[j][d]);
@@ -812,10 +864,9 @@ __global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
             }
         }
         __syncthreads();
-        chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, bar);
+        chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, epoch0);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            if (!valid[j]) continue;
 #pragma unroll
             for (int d = 0; d < 3; ++d) v[j][d] = tfma(hT, (T)f[j][d], v[j][d]);
         }
@@ -1351,7 +1402,7 @@ __global__ __launch_bounds__(256) void k_observe(Work w)
     template __global__ void k_init<T>(const RepDesc*);                          \
     template __global__ void k_init_sub<T>(const RepDesc*, const double*);       \
     template __global__ void k_list<T>(Work);                                    \
-    template __global__ void k_stream_bin<T>(Work);                              \
+    template __global__ void k_stream_bin<T>(Work, int);                         \
     template __global__ void k_chain<T, 1>(Work);                                \
     template __global__ void k_chain<T, 2>(Work);                                \
     template __global__ void k_chain<T, 4>(Work);                                \
