@@ -62,6 +62,31 @@ def algorithmic_bytes(kernel: str, n: int, ncell: int, tb: int, n_cand: int) -> 
     return 0.0
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources: counter-derived traffic is only reported for
+    the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1608_04904_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name: str, precision: int, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if the
+    kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload_name}_fp{precision}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else 1e6 * (k["fetch_MB"] + k["write_MB"])
+
+
 def workload(name: str, precision: int):
     import workloads as W
     if name == "dimer32":
@@ -112,6 +137,8 @@ def main():
     ap.add_argument("--chain-k", type=int, default=0)
     ap.add_argument("--stream-block", type=int, default=0)
     ap.add_argument("--stream-ppt", type=int, default=0)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB copied by one plain device copy before the run (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -123,6 +150,16 @@ def main():
 
     import torch
     import paper_1608_04904_amd as rm
+
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {nbytes} bytes done", file=sys.stderr, flush=True)
+        del src, dst
 
     p, n_md, seed, desc = workload(args.workload, args.precision)
     n = p["n_solvent"]
@@ -164,13 +201,15 @@ def main():
         flops = 120.0 * n_cand * n_md
         achieved = flops / (avg_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP64_PEAK_TFLOPS, traffic=None, kernel=dom,
+                    frac=achieved / FP64_PEAK_TFLOPS,
+                    traffic=measured_traffic(args.workload, args.precision, dom), kernel=dom,
                     avg_launch_ms=avg_ms)
     else:
         byts = algorithmic_bytes(dom, n, ncell, tb, n_cand)
         achieved = byts / (avg_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None, kernel=dom,
+                    frac=achieved / HBM_PEAK_GBS,
+                    traffic=measured_traffic(args.workload, args.precision, dom), kernel=dom,
                     avg_launch_ms=avg_ms)
     kernels = {k: dict(avg_ms=round(v[0], 5), launches=v[1],
                        algorithmic_GBps=round(algorithmic_bytes(k, n, ncell, tb, n_cand)
