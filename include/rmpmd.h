@@ -201,6 +201,10 @@ rmp_status rmp_batch_slot_observables(rmp_batch* b, int32_t slot, rmp_obs* out);
 rmp_status rmp_batch_get_state(rmp_batch* b, int32_t slot, rmp_host_state* dst);
 rmp_status rmp_batch_set_state(rmp_batch* b, int32_t slot, const rmp_host_state* src);
 rmp_status rmp_batch_set_tuning(rmp_batch* b, const rmp_tuning* t);
+/* Per-replica override of the collision tile size (t->collide_cells; the
+ * other fields are batch-wide and ignored here); <= 0 restores the batch
+ * value.  Used to apply a per-box-class autotuned tile size. */
+rmp_status rmp_batch_set_slot_tuning(rmp_batch* b, int32_t slot, const rmp_tuning* t);
 rmp_status rmp_batch_destroy(rmp_batch* b);
 
 #ifdef __cplusplus

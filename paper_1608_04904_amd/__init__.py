@@ -241,3 +241,8 @@ class Batch:
         for k, v in kw.items():
             setattr(t, k, int(v))
         check(_capi.lib().rmp_batch_set_tuning(self.h, C.byref(t)), "rmp_batch_set_tuning")
+
+    def set_slot_tuning(self, slot: int, collide_cells: int):
+        t = _capi.Tuning(-1, -1, int(collide_cells), -1, -1)
+        check(_capi.lib().rmp_batch_set_slot_tuning(self.h, int(slot), C.byref(t)),
+              "rmp_batch_set_slot_tuning")

@@ -89,6 +89,7 @@ SIGNATURES = {
     "rmp_batch_get_state": (I32, [P, I32, C.POINTER(HostState)]),
     "rmp_batch_set_state": (I32, [P, I32, C.POINTER(HostState)]),
     "rmp_batch_set_tuning": (I32, [P, C.POINTER(Tuning)]),
+    "rmp_batch_set_slot_tuning": (I32, [P, I32, C.POINTER(Tuning)]),
     "rmp_batch_destroy": (I32, [P]),
 }
 

@@ -171,6 +171,7 @@ struct Replica {
     int32_t list_nmd = -1;
     std::vector<double> ptable;
     int32_t ptable_nmd = -1;
+    int32_t tile_cells = 0;    // per-replica override of the collision tile size
 };
 
 }  // namespace
@@ -246,9 +247,9 @@ int chain_k_of(const rmp_batch* b)
     return (k == 1 || k == 2 || k == 4) ? k : 2;
 }
 
-int tile_cells_of(const rmp_batch* b)
+int tile_cells_of(const rmp_batch* b, int override_cells = 0)
 {
-    int tc = b->tun.collide_cells;
+    int tc = override_cells > 0 ? override_cells : b->tun.collide_cells;
     if (tc < MIN_TILE_CELLS) tc = MIN_TILE_CELLS;
     if (tc > COLL_TCMAX) tc = COLL_TCMAX;
     int p2 = MIN_TILE_CELLS;
@@ -275,7 +276,7 @@ void fill_desc(rmp_batch* b, Replica& r)
     D.n_md = r.n_md;
     D.rule = p->rule;
     D.n_chunks = s.n_chunks;
-    D.tile_cells = tile_cells_of(b);
+    D.tile_cells = tile_cells_of(b, r.tile_cells);
     D.n_tiles = (int32_t)((s.ncell + D.tile_cells - 1) / D.tile_cells);
     D.n_scanblk = s.n_scanblk;
     D.cand_cap = s.cand_cap;
@@ -1069,6 +1070,17 @@ rmp_status rmp_batch_set_tuning(rmp_batch* b, const rmp_tuning* t)
     if (n.chain_k != 1 && n.chain_k != 2 && n.chain_k != 4) return RMP_EINVAL;
     if (n.stream_block != 64 && n.stream_block != 128 && n.stream_block != 256) return RMP_EINVAL;
     b->tun = n;
+    b->dirty = true;
+    b->graph_valid = false;
+    return RMP_OK;
+}
+
+rmp_status rmp_batch_set_slot_tuning(rmp_batch* b, int32_t slot, const rmp_tuning* t)
+{
+    rmp_status st = slot_ok(b, slot);
+    if (st != RMP_OK) return st;
+    if (!t) return RMP_EINVAL;
+    b->reps[slot].tile_cells = t->collide_cells > 0 ? t->collide_cells : 0;
     b->dirty = true;
     b->graph_valid = false;
     return RMP_OK;
