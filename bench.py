@@ -1,12 +1,12 @@
 """Benchmark of the MPCD+MD solvent hot path on one MI355X.
 
-Workload (default): chemically powered dimer nanomotor, periodic 32^3 cells,
-10 solvent particles per cell = 327,680 particles, catalytic C and
-non-catalytic N spheres (sigma 4, bond 6.7), eps_B = 0.5 on N, catalytic
-conversion with probability 1, bulk B->A rate 0.01, dt = 0.01,
-tau = 0.5 (50 MD steps per collision), FP64 state.  Synthetic seeded input:
-the library's own initialisation (uniform positions outside the colloids,
-Maxwellian velocities at kT = 1).
+Default workload (the one `value` is quoted on): chemically powered dimer
+nanomotor, periodic 32^3 cells, 10 solvent particles per cell = 327,680
+particles, catalytic C and non-catalytic N spheres (sigma 4, bond 6.7),
+eps_B = 0.5 on N, catalytic conversion with probability 1, bulk B->A rate
+0.01, dt = 0.01, tau = 0.5 (50 MD steps per collision), FP64 state.
+Synthetic seeded input: the library's own initialisation (uniform positions
+outside the colloids, Maxwellian velocities at kT = 1).
 
 One benchmark step = one interval of the method: 50 velocity-Verlet MD steps
 of all solvent particles and the dimer, then one MPCD collision with the
@@ -18,6 +18,12 @@ duration is measured with HIP events recorded by the library on the stream
 that kernel runs on, over a second pass of the same workload; achieved =
 algorithmic bytes per launch / that duration.  cpu_baseline times the FP64
 CPU oracle on a bounded sample of the same workload on the host cores.
+
+Extra objects on the same line: the same workload in FP32 state, and the
+128^3-cell, 8-dimer system (20,971,520 particles, FP64 and FP32) where the
+state exceeds the caches and the streaming and collision kernels are
+HBM-bound.  Other modes (--workload batch / serve / large128 / sphere10)
+print their own line.
 """
 from __future__ import annotations
 
@@ -34,6 +40,7 @@ sys.path.insert(0, ROOT)
 METRIC = "solvent particle-steps/s + % HBM peak; batched FP32 vs FP64; p50/p99 job latency"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FLOPS_PER_LIST_STEP = 120.0
 
 
 def algorithmic_bytes(kernel: str, n: int, ncell: int, tb: int, n_cand: int) -> float:
@@ -91,13 +98,16 @@ def workload(name: str, precision: int):
     import workloads as W
     if name == "dimer32":
         p = W.dimer32(precision=precision)
-        return p, 50, W.BASE_SEED + 2, "dimer32: 32^3 cells, rho 10, N=327,680, 1 dimer (C+N, sigma 4, d 6.7), tau 0.5 (50 MD steps/collision)"
+        return p, 50, W.BASE_SEED + 2, ("dimer32: 32^3 cells, rho 10, N=327,680, 1 dimer (C+N, "
+                                         "sigma 4, d 6.7), tau 0.5 (50 MD steps/collision)")
     if name == "sphere10":
         p = W.sphere10(precision=precision)
-        return p, 10, W.BASE_SEED + 1, "sphere10: 10^3 cells, rho 10, N=10,000, 1 WCA sphere sigma 2, tau 0.1 (10 MD steps/collision)"
+        return p, 10, W.BASE_SEED + 1, ("sphere10: 10^3 cells, rho 10, N=10,000, 1 WCA sphere "
+                                         "sigma 2, tau 0.1 (10 MD steps/collision)")
     if name == "large128":
         p = W.large128(precision=precision)
-        return p, 50, W.BASE_SEED + 3, "large128: 128^3 cells, rho 10, N=20,971,520, 8 dimers, tau 0.5 (50 MD steps/collision)"
+        return p, 50, W.BASE_SEED + 3, ("large128: 128^3 cells, rho 10, N=20,971,520, 8 dimers, "
+                                         "tau 0.5 (50 MD steps/collision)")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -122,73 +132,40 @@ def cpu_baseline(p, n_md, seed, budget_s: float):
                        f"({p['n_solvent']} particles), {dt:.1f} s")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="dimer32")
-    ap.add_argument("--precision", type=int, default=64)
-    ap.add_argument("--profile-steps", type=int, default=10)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--graph", type=int, default=1)
-    ap.add_argument("--collide-cells", type=int, default=0)
-    ap.add_argument("--chain-k", type=int, default=0)
-    ap.add_argument("--stream-block", type=int, default=0)
-    ap.add_argument("--stream-ppt", type=int, default=0)
-    ap.add_argument("--calibrate-copy", type=int, default=0,
-                    help="MiB copied by one plain device copy before the run (counter calibration)")
-    args = ap.parse_args()
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus > 1 or world > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(each replica or job is independent; see the design notes for how a "
-              "single large system would shard).", file=sys.stderr)
-        sys.exit(2)
 
-    import torch
-    import paper_1608_04904_amd as rm
-
-    if args.calibrate_copy > 0:
-        nbytes = args.calibrate_copy << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {nbytes} bytes done", file=sys.stderr, flush=True)
-        del src, dst
-
-    p, n_md, seed, desc = workload(args.workload, args.precision)
-    n = p["n_solvent"]
-    ncell = p["L"][0] * p["L"][1] * p["L"][2]
-    tb = 8 if args.precision == 64 else 4
-
-    print(f"[bench] workload {args.workload} N={n} n_md={n_md} precision={args.precision}",
-          file=sys.stderr, flush=True)
-    s = rm.System(p, seed)
+def tuning_from_args(args) -> dict:
     tun = dict(use_graph=args.graph)
     for k in ("collide_cells", "chain_k", "stream_block", "stream_ppt"):
         if getattr(args, k) > 0:
             tun[k] = getattr(args, k)
+    return tun
+
+
+def run_single(name, precision, steps, warmup, profile_steps, tun):
+    """Time `steps` intervals of one system, then a profiled pass.  Returns a
+    dict with value, wall, per-kernel averages and the roofline object."""
+    import torch
+    import paper_1608_04904_amd as rm
+    p, n_md, seed, desc = workload(name, precision)
+    n = p["n_solvent"]
+    ncell = p["L"][0] * p["L"][1] * p["L"][2]
+    tb = 8 if precision == 64 else 4
+    _log(f"workload {name} N={n} n_md={n_md} precision={precision}")
+    s = rm.System(p, seed)
     s.set_tuning(**tun)
-    s.step(n_md, args.warmup)
+    s.step(n_md, warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.step(n_md, args.steps)
+    s.step(n_md, steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    value = n * n_md * args.steps / wall
+    wall = time.perf_counter() - t0
     ob = s.observables(raise_on_flags=False)
-    print(f"[bench] timed {args.steps} steps in {wall:.3f} s, flags={ob['flags']}",
-          file=sys.stderr, flush=True)
-
-    # per-kernel device time over a second pass (HIP events on each kernel's stream)
+    _log(f"{name} fp{precision}: {steps} steps in {wall:.4f} s, flags={ob['flags']}")
     s.profile(True)
-    s.step(n_md, args.profile_steps)
+    s.step(n_md, profile_steps)
     prof = s.profile_read()
     s.profile(False)
     n_cand = ob["n_candidates"]
@@ -196,40 +173,175 @@ def main():
     dom = max(kern, key=lambda k: kern[k][0] * kern[k][1])
     avg_ms = kern[dom][0]
     if dom == "chain":
-        # latency-bound chain of n_md small steps: report FP64 work against the
-        # vector FP64 peak (about 120 flops per list entry per MD step)
-        flops = 120.0 * n_cand * n_md
+        # the MD chain is a dependent sequence of n_md small steps (latency
+        # bound); its FP64 work is reported against the vector FP64 peak
+        flops = FLOPS_PER_LIST_STEP * n_cand * n_md
         achieved = flops / (avg_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP64_PEAK_TFLOPS,
-                    traffic=measured_traffic(args.workload, args.precision, dom), kernel=dom,
-                    avg_launch_ms=avg_ms)
+                    frac=achieved / FP64_PEAK_TFLOPS)
     else:
-        byts = algorithmic_bytes(dom, n, ncell, tb, n_cand)
-        achieved = byts / (avg_ms * 1e-3) / 1e9
+        achieved = algorithmic_bytes(dom, n, ncell, tb, n_cand) / (avg_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS,
-                    traffic=measured_traffic(args.workload, args.precision, dom), kernel=dom,
-                    avg_launch_ms=avg_ms)
+                    frac=achieved / HBM_PEAK_GBS)
+    roof.update(traffic=measured_traffic(name, precision, dom), kernel=dom, avg_launch_ms=avg_ms)
     kernels = {k: dict(avg_ms=round(v[0], 5), launches=v[1],
                        algorithmic_GBps=round(algorithmic_bytes(k, n, ncell, tb, n_cand)
                                               / (v[0] * 1e-3) / 1e9, 1))
                for k, v in kern.items()}
-    print(f"[bench] kernels {json.dumps(kernels)}", file=sys.stderr, flush=True)
+    _log(f"{name} fp{precision} kernels {json.dumps(kernels)}")
+    out = dict(value=n * n_md * steps / wall, wall=wall, n=n, n_md=n_md, desc=desc,
+               n_cand=n_cand, roofline=roof, kernels=kernels, tuning=s.get_tuning(),
+               flags=ob["flags"])
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
 
+
+def run_batch(precision, ticks, warmup, tun, n_rep=64):
+    """64 dimer replicas, box edges from {16,20,24,32}, per-replica seeds,
+    one interval (50 MD steps + collision) per replica per tick."""
+    import torch
+    import paper_1608_04904_amd as rm
+    import workloads as W
+    reps = W.batch_replicas(n=n_rep, precision=precision)
+    b = rm.Batch(len(reps), precision=precision)
+    b.set_tuning(**tun)
+    for i, p in enumerate(reps):
+        b.set_slot(i, p, p["seed"], p["n_md"])
+    n_tot = sum(p["n_solvent"] for p in reps)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(ticks)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    flags = [b.observables(i, raise_on_flags=False)["flags"] for i in range(len(reps))]
+    val = n_tot * 50 * ticks / wall
+    _log(f"batch fp{precision}: {len(reps)} replicas, N_total={n_tot}, {ticks} ticks in "
+         f"{wall:.3f} s -> {val:.3e} particle-steps/s, flags={sum(1 for f in flags if f)}")
+    b.close()
+    torch.cuda.empty_cache()
+    return dict(value=val, wall=wall, n_total=n_tot, n_replicas=len(reps), ticks=ticks,
+                flagged=sum(1 for f in flags if f))
+
+
+def run_serve(n_jobs, rate, scale, budget_gb, slots, seed=None):
+    """Poisson trace (box edge 12..48, density 5..20, sphere or dimer,
+    tau 0.1..0.5, FP32 or FP64); collisions per job scaled by `scale`."""
+    import workloads as W
+    from paper_1608_04904_amd.serve import Server, summarize
+    jobs = W.serve_trace(n_jobs=n_jobs, rate=rate, seed=seed)
+    for j in jobs:
+        j["n_collide"] = max(1, int(round(j["n_collide"] * scale)))
+    srv = Server.on_gpu(hbm_budget=int(budget_gb * (1 << 30)), slots_per_pool=slots)
+    t0 = time.perf_counter()
+    res = srv.run(jobs, realtime=True)
+    wall = time.perf_counter() - t0
+    s = summarize(res)
+    s.update(wall_s=wall, peak_hbm_bytes=srv.peak_used, n_jobs_offered=n_jobs,
+             arrival_rate=rate, collision_scale=scale)
+    _log(f"serve: {json.dumps(s)}")
+    return s
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="dimer32",
+                    choices=["dimer32", "sphere10", "large128", "batch", "serve"])
+    ap.add_argument("--precision", type=int, default=64)
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--collide-cells", type=int, default=0)
+    ap.add_argument("--chain-k", type=int, default=0)
+    ap.add_argument("--stream-block", type=int, default=0)
+    ap.add_argument("--stream-ppt", type=int, default=0)
+    ap.add_argument("--serve-jobs", type=int, default=60)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-scale", type=float, default=0.05)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB copied by one plain device copy before the run (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(each replica or job is independent; the design notes describe how a "
+              "single large system would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        _log(f"calibration copy of {nbytes} bytes done")
+        del src, dst
+
+    tun = tuning_from_args(args)
+    base = dict(metric=METRIC, unit="particle-steps/s", n_gpus=1, higher_is_better=True,
+                scaling="weak", vs_baseline=None, data="synthetic")
+
+    if args.workload == "batch":
+        r64 = run_batch(64, args.steps, args.warmup, tun)
+        r32 = run_batch(32, args.steps, args.warmup, tun)
+        line = dict(base, value=r32["value"], steps=args.steps, warmup=args.warmup,
+                    ms_per_step=1e3 * r32["wall"] / args.steps, dtype="f32",
+                    config=dict(workload="batch: 64 dimer replicas, box edge from {16,20,24,32}, "
+                                "rho 10, tau 0.5, per-replica seeds, one interval per replica "
+                                "per step", tuning=tun),
+                    fp32=r32, fp64=r64, fp32_over_fp64=r32["value"] / r64["value"])
+        print(json.dumps(line), flush=True)
+        return
+    if args.workload == "serve":
+        s = run_serve(args.serve_jobs, args.serve_rate, args.serve_scale,
+                      args.serve_budget_gb, args.serve_slots)
+        line = dict(base, value=s.get("particle_steps_per_s", 0.0), steps=s.get("n_jobs", 0),
+                    warmup=0, ms_per_step=None, dtype="f32+f64",
+                    config=dict(workload=f"serve: Poisson trace, {args.serve_jobs} jobs at "
+                                f"{args.serve_rate}/s, collisions x{args.serve_scale}, budget "
+                                f"{args.serve_budget_gb} GiB, {args.serve_slots} slots per pool"),
+                    serve=s)
+        print(json.dumps(line), flush=True)
+        return
+
+    main_r = run_single(args.workload, args.precision, args.steps, args.warmup,
+                        args.profile_steps, tun)
+    extras = {}
+    if not args.no_extras and args.workload == "dimer32":
+        other = 32 if args.precision == 64 else 64
+        r = run_single("dimer32", other, args.steps, args.warmup, args.profile_steps, tun)
+        extras[f"dimer32_fp{other}"] = dict(value=r["value"], roofline=r["roofline"])
+        for prec in (64, 32):
+            r = run_single("large128", prec, 6, 2, 3, tun)
+            extras[f"large128_fp{prec}"] = dict(
+                value=r["value"], roofline=r["roofline"],
+                kernels={k: r["kernels"][k] for k in ("stream_bin", "collide", "chain")
+                         if k in r["kernels"]})
     cpu = None
     if not args.no_cpu:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        _log("timing the CPU oracle")
+        p, n_md, seed, _ = workload(args.workload, 64)
         cpu = cpu_baseline(p, n_md, seed, args.cpu_seconds)
-
-    line = dict(
-        metric=METRIC, value=value, unit="particle-steps/s", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=1e3 * wall / args.steps, higher_is_better=True,
-        scaling="weak", vs_baseline=None, dtype="f64" if args.precision == 64 else "f32",
-        data="synthetic",
-        config=dict(workload=desc, n_solvent=n, n_md=n_md, precision=args.precision,
-                    n_candidates=n_cand, tuning=s.get_tuning()),
-        roofline=roof, cpu_baseline=cpu, kernels=kernels)
+    line = dict(base, value=main_r["value"], steps=args.steps, warmup=args.warmup,
+                ms_per_step=1e3 * main_r["wall"] / args.steps,
+                dtype="f64" if args.precision == 64 else "f32",
+                config=dict(workload=main_r["desc"], n_solvent=main_r["n"], n_md=main_r["n_md"],
+                            precision=args.precision, n_candidates=main_r["n_cand"],
+                            tuning=main_r["tuning"]),
+                roofline=main_r["roofline"], cpu_baseline=cpu, kernels=main_r["kernels"],
+                **extras)
     print(json.dumps(line), flush=True)
 
 

@@ -241,10 +241,18 @@ rmp_status last_launch(const char* what)
     return RMP_OK;
 }
 
+// Verlet-list entries per chain thread: the tuned value, raised to the
+// smallest power of two for which every occupied replica's list capacity
+// fits in MAX_G workgroups
 int chain_k_of(const rmp_batch* b)
 {
     int k = b->tun.chain_k;
-    return (k == 1 || k == 2 || k == 4) ? k : 2;
+    if (k != 1 && k != 2 && k != 4) k = 1;
+    for (const auto& R : b->reps) {
+        if (!R.used) continue;
+        while (k < K_MAX && (int64_t)R.sz.cand_cap > (int64_t)MAX_G * CHAIN_BLOCK * k) k *= 2;
+    }
+    return k;
 }
 
 int tile_cells_of(const rmp_batch* b, int override_cells = 0)

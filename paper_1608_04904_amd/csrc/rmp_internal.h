@@ -13,7 +13,7 @@ constexpr int CHUNK = 1024;          // particles per chunk (list compaction, in
 constexpr int SCAN_BLK = 4096;       // cells per block of the multi-block cell scan
 constexpr int CHAIN_BLOCK = 256;     // threads per Verlet-list workgroup
 constexpr int NVAL_MAX = 3 * MAXC + 1;  // reduced values per MD step: F per colloid + U
-constexpr int TILE_CAP = 2048;       // particles per collision tile held in LDS
+constexpr uint64_t BARRIER_BUDGET_TICKS = 25000000;  // 0.25 s of the 100 MHz wall clock
 
 // Philox stream tags (key word 1); key word 0 is the replica seed.
 enum : uint64_t {

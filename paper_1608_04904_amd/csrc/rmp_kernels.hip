@@ -547,7 +547,7 @@ template <class T, int K>
 __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D, const ColloidParams* cp,
                              int nc, const bool* valid, const T (*x)[3], const uint8_t* st,
                              double (*f)[3], bool* inside, int g, int Gact, int Gpad,
-                             uint32_t& nbar, uint32_t epoch0)
+                             uint32_t& nbar, uint32_t epoch0, bool want_potential)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double u[K];
@@ -564,28 +564,37 @@ __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D
         const bool cat = cp->catalytic[c] != 0;
         double gx[K], gy[K], gz[K];
         bool any = false;
-        // branch-free over the K entries (selects instead of divergent
-        // branches, so the entries' dependency chains interleave); the
-        // untaken case evaluates the potential at the cut-off and discards it
+        // distances for the K entries, then the WCA terms only if some lane
+        // of the wave is inside this colloid's cut-off (wave-uniform test);
+        // within it the K entries are evaluated branch-free with selects, the
+        // untaken case at the cut-off radius (result discarded)
+        double dxs[K], dys[K], dzs[K], r2s[K];
+        bool hit[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const double dx = min_image((double)x[j][0] - Xc0, D.Ld[0], D.halfL[0]);
-            const double dy = min_image((double)x[j][1] - Xc1, D.Ld[1], D.halfL[1]);
-            const double dz = min_image((double)x[j][2] - Xc2, D.Ld[2], D.halfL[2]);
-            const double r2 = dot3(dx, dy, dz, dx, dy, dz);
-            const bool hit = valid[j] && (r2 < rc2);
-            double coef, pot;
-            wca(hit ? r2 : rc2, sig2, (st[j] & 1) ? eB : eA, coef, pot);
-            const double ax = coef * dx, ay = coef * dy, az = coef * dz;
-            gx[j] = hit ? ax : 0.0;
-            gy[j] = hit ? ay : 0.0;
-            gz[j] = hit ? az : 0.0;
-            f[j][0] = hit ? f[j][0] + ax : f[j][0];
-            f[j][1] = hit ? f[j][1] + ay : f[j][1];
-            f[j][2] = hit ? f[j][2] + az : f[j][2];
-            u[j] = hit ? u[j] + pot : u[j];
-            inside[j] = inside[j] || (hit && cat);
-            any = any || hit;
+            dxs[j] = min_image((double)x[j][0] - Xc0, D.Ld[0], D.halfL[0]);
+            dys[j] = min_image((double)x[j][1] - Xc1, D.Ld[1], D.halfL[1]);
+            dzs[j] = min_image((double)x[j][2] - Xc2, D.Ld[2], D.halfL[2]);
+            r2s[j] = dot3(dxs[j], dys[j], dzs[j], dxs[j], dys[j], dzs[j]);
+            hit[j] = valid[j] && (r2s[j] < rc2);
+            any = any || hit[j];
+            gx[j] = 0.0; gy[j] = 0.0; gz[j] = 0.0;
+        }
+        if (__ballot(any) != 0) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                double coef, pot;
+                wca(hit[j] ? r2s[j] : rc2, sig2, (st[j] & 1) ? eB : eA, coef, pot);
+                const double ax = coef * dxs[j], ay = coef * dys[j], az = coef * dzs[j];
+                gx[j] = hit[j] ? ax : 0.0;
+                gy[j] = hit[j] ? ay : 0.0;
+                gz[j] = hit[j] ? az : 0.0;
+                f[j][0] = hit[j] ? f[j][0] + ax : f[j][0];
+                f[j][1] = hit[j] ? f[j][1] + ay : f[j][1];
+                f[j][2] = hit[j] ? f[j][2] + az : f[j][2];
+                u[j] = hit[j] ? u[j] + pot : u[j];
+                inside[j] = inside[j] || (hit[j] && cat);
+            }
         }
         // reduce the three components over list positions
         const bool wave_any = __ballot(any) != 0;
@@ -660,33 +669,68 @@ __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D
             __hip_atomic_store(&part[((int64_t)g * NVAL_MAX + t) * 2 + 1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // tree over workgroups, padded with zeros to Gpad (a power of two);
-        // lane l holds workgroups [l*Q, l*Q+Q), Q = max(1, Gpad/64) <= 4
+        // lane l holds workgroups [l*Q, l*Q+Q), Q = max(1, Gpad/64) <= 4.
+        // A wave handles values v = wave, wave + NW, ...; it polls the words
+        // of up to VB of them per round so that their loads are in flight
+        // together.
+        constexpr int VB = 4;
+        // wall_clock64() counts at 100 MHz: 0.25 s per barrier at most
         const int Q = Gpad > 64 ? Gpad / 64 : 1;
-        for (int v = wave; v < nv; v += NW) {
-            double b4[4] = {0.0, 0.0, 0.0, 0.0};
-            uint32_t spins = 0;
+        for (int v0 = wave; v0 < nv; v0 += NW * VB) {
+            double b4[VB][4];
+            // bounded wait: once this workgroup has given up on one barrier
+            // (RMP_FLAG_BARRIER) it does not wait on later ones, so a kernel
+            // whose peers cannot all run ends within about one time budget
+            const uint64_t t_start = wall_clock64();
             while (true) {
+                // unconditional loads from clamped addresses, all issued
+                // before any result is examined; unused entries are masked
+                uint64_t wl[VB][4], wh[VB][4];
+#pragma unroll
+                for (int vb = 0; vb < VB; ++vb) {
+                    const int v = v0 + vb * NW;
+                    const int vc = v < nv ? v : nv - 1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int gg = lane * Q + q;
+                        const int gc = (q < Q && gg < Gact) ? gg : 0;
+                        const int64_t o = ((int64_t)gc * NVAL_MAX + vc) * 2;
+                        wl[vb][q] = __hip_atomic_load(&part[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        wh[vb][q] = __hip_atomic_load(&part[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
                 bool ok = true;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int gg = lane * Q + q;
-                    if (q < Q && gg < Gact) {
-                        const int64_t o = ((int64_t)gg * NVAL_MAX + v) * 2;
-                        const uint64_t lo = __hip_atomic_load(&part[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        const uint64_t hi = __hip_atomic_load(&part[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        ok = ok && ((uint32_t)lo == epoch) && ((uint32_t)hi == epoch);
-                        b4[q] = __hiloint2double((int)(hi >> 32), (int)(lo >> 32));
+                for (int vb = 0; vb < VB; ++vb) {
+                    const int v = v0 + vb * NW;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int gg = lane * Q + q;
+                        const bool use = v < nv && q < Q && gg < Gact;
+                        const bool good = ((uint32_t)wl[vb][q] == epoch) & ((uint32_t)wh[vb][q] == epoch);
+                        ok = ok & (!use | good);
+                        b4[vb][q] = use ? __hiloint2double((int)(wh[vb][q] >> 32), (int)(wl[vb][q] >> 32)) : 0.0;
                     }
                 }
                 if (__ballot(!ok) == 0) break;
-                if (++spins > (1u << 22)) {
+                if (__hip_atomic_load(&S.sflags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) &
+                    RMP_FLAG_BARRIER)
+                    break;
+                if (wall_clock64() - t_start > BARRIER_BUDGET_TICKS) {
                     if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
                     break;
                 }
             }
-            double a2 = (Q == 1) ? b4[0] : (Q == 2) ? (b4[0] + b4[1]) : ((b4[0] + b4[1]) + (b4[2] + b4[3]));
-            a2 = wave_tree_sum(a2);
-            if (lane == 0) S.sNode[v] = a2;
+#pragma unroll
+            for (int vb = 0; vb < VB; ++vb) {
+                const int v = v0 + vb * NW;
+                if (v >= nv) break;
+                double a2 = (Q == 1) ? b4[vb][0]
+                          : (Q == 2) ? (b4[vb][0] + b4[vb][1])
+                                     : ((b4[vb][0] + b4[vb][1]) + (b4[vb][2] + b4[vb][3]));
+                a2 = wave_tree_sum(a2);
+                if (lane == 0) S.sNode[v] = a2;
+            }
         }
         __syncthreads();
     } else {
@@ -714,7 +758,7 @@ __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D
         }
         for (int d = 0; d < 3; ++d) S.sF[c][d] = F[d];
     }
-    if (t == 0) {
+    if (t == 0 && want_potential) {
         double ucc = 0.0;
         for (int a = 0; a < nc; ++a)
             for (int b = a + 1; b < nc; ++b) {
@@ -802,7 +846,8 @@ __global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
     // barrier epochs: unique per barrier of the replica between list
     // rebuilds (md_step + coll_step grows by n_md + 1 per interval)
     const uint32_t epoch0 = (uint32_t)(md0 + coll);
-    chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, epoch0);
+    chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, epoch0,
+                       nmd == 0);
 
     const double dt = D.dt;
     const T dtT = (T)dt, hT = (T)D.h;
@@ -864,7 +909,8 @@ __global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
             }
         }
         __syncthreads();
-        chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, epoch0);
+        chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, epoch0,
+                       step == nmd - 1);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
 #pragma unroll

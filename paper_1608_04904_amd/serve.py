@@ -202,9 +202,10 @@ def summarize(results, makespan: float | None = None) -> dict:
     steps = sum(r.particle_steps for r in ok)
     end = makespan if makespan is not None else max(r.finished for r in ok)
     start = min(r.arrival for r in ok)
+    errs = [(r.job_id, r.error) for r in results if r.error is not None]
     return dict(n_jobs=len(ok), p50_latency_s=float(np.percentile(lat, 50)),
                 p99_latency_s=float(np.percentile(lat, 99)),
                 mean_latency_s=float(lat.mean()), makespan_s=float(end - start),
                 particle_steps=int(steps),
                 particle_steps_per_s=float(steps / max(end - start, 1e-9)),
-                errors=len(results) - len(ok))
+                errors=len(results) - len(ok), error_jobs=errs[:10])

@@ -182,6 +182,23 @@ def test_fp64_many_list_workgroups():
     _assert_obs(ob, o.observables())
 
 
+def test_fp64_many_colloids_with_contacts():
+    """Three dimers placed inside each other's colloid-colloid cut-off plus
+    two free spheres: many colloids per list entry, colloid-colloid WCA."""
+    p = W.base_params(L=(26, 26, 26), rho=5, n_md=10)
+    p["bulk_rate"] = 0.03
+    ex = np.array([1.0, 0.0, 0.0])
+    W.add_dimer(p, (8.0, 8.0, 8.0), ex)                 # C at (11.35, 8, 8)
+    W.add_dimer(p, (8.0, 16.6, 8.0), ex)                # C-C 8.6 apart (< 8.98)
+    W.add_dimer(p, (20.0, 20.0, 19.0), np.array([0.0, 0.6, 0.8]))
+    W.add_colloid(p, (17.85, 8.0, 8.0), sigma=2.0, catalytic=True)   # 6.5 from C (< 6.73)
+    W.add_colloid(p, (3.0, 3.0, 20.0), sigma=2.5)
+    s0 = W.random_state(p, 109, species_B_fraction=0.3)
+    g, o = _run_both(p, s0, 16, 10, 3)
+    _assert_bitwise(g.get_state(), o.get_state(), "many colloids")
+    _assert_obs(g.observables(), o.observables())
+
+
 def test_fp64_resume_and_determinism():
     rm = _rm()
     p = W.dimer_system(L=14, rho=6, n_md=10, seed=8, bulk_rate=0.05)

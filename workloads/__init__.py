@@ -175,6 +175,10 @@ def serve_trace(n_jobs=200, rate=20.0, seed=None, edge=(12, 48), rho=(5, 20),
         else:
             p = base_params(L=(L, L, L), rho=dens, dt=0.01, n_md=n_md, precision=prec)
             add_colloid(p, (L / 2.0, L / 2.0, L / 2.0), sigma=2.0)
+        # Verlet-list skin: at least twice a generous colloid displacement per
+        # interval (4 thermal speeds sqrt(3 kT / M) times tau)
+        m_min = min(c["mass"] for c in p["colloids"])
+        p["skin"] = max(p["skin"], round(2 * 4 * math.sqrt(3 * p["kT"] / m_min) * tau, 2))
         p["name"] = f"job{j}_{kind}_L{L}_rho{dens}"
         jobs.append(dict(arrival=t, params=p, seed=BASE_SEED + 100000 + j,
                          n_collide=int(rng.integers(n_collide[0], n_collide[1] + 1))))
