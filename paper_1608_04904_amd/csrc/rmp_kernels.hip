@@ -526,6 +526,14 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
 
 // ------------------------------------------------------------- MD chain
 
+// ordering of LDS accesses between lanes of one wave (no workgroup barrier)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Chain workgroup g of a replica holds Verlet-list positions
 // [g*B, (g+1)*B), B = 256*K, K consecutive positions per thread, in
 // registers for the whole interval.
@@ -538,16 +546,17 @@ struct ChainCtx {
     uint32_t sflags;
 };
 
-// Forces on this workgroup's list entries from all colloids, per-colloid
-// force sums and the potential reduced over list positions with the fixed
-// binary tree (within thread over K, wave butterfly, waves, workgroups).
-// On return sF holds the colloid forces (solvent part plus colloid-colloid),
-// sU the potential.
+// First half of a force evaluation: forces on this workgroup's list
+// entries from all colloids, and the per-colloid force sums and the
+// potential reduced over this workgroup's list positions with the fixed
+// binary tree (within a thread over K, over the lanes of a wave, over the
+// waves).  With several workgroups the node values are then published for
+// the others (chain_collect completes the tree over workgroups).
 template <class T, int K>
-__device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D, const ColloidParams* cp,
-                             int nc, const bool* valid, const T (*x)[3], const uint8_t* st,
-                             double (*f)[3], bool* inside, int g, int Gact, int Gpad,
-                             uint32_t& nbar, uint32_t epoch0, bool want_potential)
+__device__ __forceinline__ void chain_compute(ChainCtx<T, K>& S, const RepDesc& D, const ColloidParams* cp,
+                              int nc, const bool* valid, const T (*x)[3], const uint8_t* st,
+                              double (*f)[3], bool* inside, int g, int Gact,
+                              uint32_t& nbar, uint32_t epoch0)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double u[K];
@@ -668,6 +677,25 @@ __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D
             __hip_atomic_store(&part[((int64_t)g * NVAL_MAX + t) * 2 + 0], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&part[((int64_t)g * NVAL_MAX + t) * 2 + 1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+    }
+}
+
+// Second half: wait for the other workgroups' node values of this
+// evaluation, finish the tree over workgroups, then the colloid forces
+// (solvent part, then colloid-colloid pairs in (a<b) order) into sF and,
+// when requested, the potential into sU.
+template <class T, int K>
+__device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& D, const ColloidParams* cp,
+                              int nc, int Gact, int Gpad, uint32_t nbar, uint32_t epoch0,
+                              bool want_potential)
+{
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nv = 3 * nc + 1;
+    constexpr int NW = CHAIN_BLOCK / 64;
+    if (Gact > 1) {
+        const uint32_t epoch = epoch0 + nbar;
+        uint64_t* part = reinterpret_cast<uint64_t*>(D.partials) +
+                         (int64_t)(nbar & 1) * D.G * NVAL_MAX * 2;
         // tree over workgroups, padded with zeros to Gpad (a power of two);
         // lane l holds workgroups [l*Q, l*Q+Q), Q = max(1, Gpad/64) <= 4.
         // A wave handles values v = wave, wave + NW, ...; it polls the words
@@ -732,10 +760,8 @@ __device__ __forceinline__ void chain_forces(ChainCtx<T, K>& S, const RepDesc& D
                 if (lane == 0) S.sNode[v] = a2;
             }
         }
-        __syncthreads();
-    } else {
-        __syncthreads();
     }
+    __syncthreads();
     // colloid forces: solvent part, then colloid-colloid pairs in (a<b) order
     if (t < nc) {
         const int c = t;
@@ -846,97 +872,82 @@ __global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
     // barrier epochs: unique per barrier of the replica between list
     // rebuilds (md_step + coll_step grows by n_md + 1 per interval)
     const uint32_t epoch0 = (uint32_t)(md0 + coll);
-    chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, epoch0,
-                       nmd == 0);
-
     const double dt = D.dt;
     const T dtT = (T)dt, hT = (T)D.h;
     const T Lt[3] = {(T)D.Ld[0], (T)D.Ld[1], (T)D.Ld[2]};
+    const bool colloid_wave = t < 64;
+
+    // forces at the start of the interval
+    chain_compute<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
+    chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, false);
+    // list entries: first half kick and drift of step 0
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            v[j][d] = tfma(hT, (T)f[j][d], v[j][d]);
+            x[j][d] = wrap_coord<T>(tfma(dtT, v[j][d], x[j][d]), Lt[d]);
+        }
+
     double eu = 0.0, ef = 0.0;
     for (int step = 0; step < nmd; ++step) {
         const int64_t md = md0 + step;
-        // colloids: half kick, drift, RATTLE position stage
-        if (t < nc) {
-            const int c = t;
-            for (int d = 0; d < 3; ++d) {
-                S.sV[c][d] = fma(cp->hc[c], S.sF[c][d], S.sV[c][d]);
-                S.sXold[c][d] = S.sX[c][d];
-                S.sX[c][d] = fma(dt, S.sV[c][d], S.sX[c][d]);
+        // colloids (wave 0 only, ordered by wave-level fences): half kick,
+        // drift, RATTLE position stage, periodic images
+        if (colloid_wave) {
+            if (t < nc) {
+                const int c = t;
+                for (int d = 0; d < 3; ++d) {
+                    S.sV[c][d] = fma(cp->hc[c], S.sF[c][d], S.sV[c][d]);
+                    S.sXold[c][d] = S.sX[c][d];
+                    S.sX[c][d] = fma(dt, S.sV[c][d], S.sX[c][d]);
+                }
             }
+            wave_sync();
+            if (t < cp->nbonds) {
+                const int a = cp->bond_a[t], b = cp->bond_b[t];
+                const double dd = cp->bond_d[t];
+                double r0[3], sv[3];
+                for (int d = 0; d < 3; ++d) {
+                    r0[d] = S.sXold[a][d] - S.sXold[b][d];
+                    sv[d] = S.sX[a][d] - S.sX[b][d];
+                }
+                double mu = cp->imass[a] + cp->imass[b];
+                double r0r0 = dot3(r0[0], r0[1], r0[2], r0[0], r0[1], r0[2]);
+                double sr0 = dot3(sv[0], sv[1], sv[2], r0[0], r0[1], r0[2]);
+                double ss = dot3(sv[0], sv[1], sv[2], sv[0], sv[1], sv[2]);
+                double A = (mu * mu) * r0r0;
+                double Bh = mu * sr0;
+                double C = ss - (dd * dd);
+                double disc = (Bh * Bh) - (A * C);
+                if (disc < 0.0) {
+                    atomicOr(&S.sflags, RMP_FLAG_RATTLE);
+                    disc = 0.0;
+                }
+                double gq = C / (Bh + sqrt(disc));
+                double ga = gq * cp->imass[a], gb = gq * cp->imass[b];
+                double gad = ga / dt, gbd = gb / dt;
+                for (int d = 0; d < 3; ++d) {
+                    S.sX[a][d] = S.sX[a][d] - (ga * r0[d]);
+                    S.sX[b][d] = S.sX[b][d] + (gb * r0[d]);
+                    S.sV[a][d] = S.sV[a][d] - (gad * r0[d]);
+                    S.sV[b][d] = S.sV[b][d] + (gbd * r0[d]);
+                }
+            }
+            wave_sync();
+            if (t < nc)
+                for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(S.sX[t][d], D.Ld[d]);
         }
         __syncthreads();
-        if (t < cp->nbonds) {
-            const int a = cp->bond_a[t], b = cp->bond_b[t];
-            const double dd = cp->bond_d[t];
-            double r0[3], sv[3];
-            for (int d = 0; d < 3; ++d) {
-                r0[d] = S.sXold[a][d] - S.sXold[b][d];
-                sv[d] = S.sX[a][d] - S.sX[b][d];
-            }
-            double mu = cp->imass[a] + cp->imass[b];
-            double r0r0 = dot3(r0[0], r0[1], r0[2], r0[0], r0[1], r0[2]);
-            double sr0 = dot3(sv[0], sv[1], sv[2], r0[0], r0[1], r0[2]);
-            double ss = dot3(sv[0], sv[1], sv[2], sv[0], sv[1], sv[2]);
-            double A = (mu * mu) * r0r0;
-            double Bh = mu * sr0;
-            double C = ss - (dd * dd);
-            double disc = (Bh * Bh) - (A * C);
-            if (disc < 0.0) {
-                atomicOr(&S.sflags, RMP_FLAG_RATTLE);
-                disc = 0.0;
-            }
-            double gq = C / (Bh + sqrt(disc));
-            double ga = gq * cp->imass[a], gb = gq * cp->imass[b];
-            double gad = ga / dt, gbd = gb / dt;
-            for (int d = 0; d < 3; ++d) {
-                S.sX[a][d] = S.sX[a][d] - (ga * r0[d]);
-                S.sX[b][d] = S.sX[b][d] + (gb * r0[d]);
-                S.sV[a][d] = S.sV[a][d] - (gad * r0[d]);
-                S.sV[b][d] = S.sV[b][d] + (gbd * r0[d]);
-            }
-        }
-        __syncthreads();
-        if (t < nc)
-            for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(S.sX[t][d], D.Ld[d]);
-        // solvent list entries: half kick, drift, wrap (entries past the end
-        // of the list hold dummies that are never written back)
+        chain_compute<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
+        // while the other workgroups' sums arrive: the list entries' second
+        // half kick, catalysis, and (except after the last step) the next
+        // step's first half kick and drift -- each entry's own arithmetic,
+        // in the same order as a step-by-step update
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                v[j][d] = tfma(hT, (T)f[j][d], v[j][d]);
-                x[j][d] = wrap_coord<T>(tfma(dtT, v[j][d], x[j][d]), Lt[d]);
-            }
-        }
-        __syncthreads();
-        chain_forces<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, Gpad, nbar, epoch0,
-                       step == nmd - 1);
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
+        for (int j = 0; j < K; ++j)
 #pragma unroll
             for (int d = 0; d < 3; ++d) v[j][d] = tfma(hT, (T)f[j][d], v[j][d]);
-        }
-        // colloids: second half kick, RATTLE velocity stage
-        if (t < nc)
-            for (int d = 0; d < 3; ++d) S.sV[t][d] = fma(cp->hc[t], S.sF[t][d], S.sV[t][d]);
-        __syncthreads();
-        if (t < cp->nbonds) {
-            const int a = cp->bond_a[t], b = cp->bond_b[t];
-            double r[3], vr[3];
-            for (int d = 0; d < 3; ++d) {
-                r[d] = S.sX[a][d] - S.sX[b][d];
-                vr[d] = S.sV[a][d] - S.sV[b][d];
-            }
-            double mu = cp->imass[a] + cp->imass[b];
-            double rr = dot3(r[0], r[1], r[2], r[0], r[1], r[2]);
-            double vrr = dot3(vr[0], vr[1], vr[2], r[0], r[1], r[2]);
-            double k = vrr / (mu * rr);
-            double ka = k * cp->imass[a], kb = k * cp->imass[b];
-            for (int d = 0; d < 3; ++d) {
-                S.sV[a][d] = S.sV[a][d] - (ka * r[d]);
-                S.sV[b][d] = S.sV[b][d] + (kb * r[d]);
-            }
-        }
         // catalysis: A inside a catalytic sphere is flagged; a flagged A
         // outside all of them converts to B with probability cat_prob
 #pragma unroll
@@ -963,14 +974,51 @@ __global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
                 }
             }
         }
-        // Verlet-list soundness: colloid displacement within the interval
-        if (t < nc) {
-            double dx = S.sX[t][0] - S.sX0[t][0], dy = S.sX[t][1] - S.sX0[t][1],
-                   dz = S.sX[t][2] - S.sX0[t][2];
-            if (dot3(dx, dy, dz, dx, dy, dz) >= D.skin_half2) atomicOr(&S.sflags, RMP_FLAG_DISPLACEMENT);
+        if (step < nmd - 1) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    v[j][d] = tfma(hT, (T)f[j][d], v[j][d]);
+                    x[j][d] = wrap_coord<T>(tfma(dtT, v[j][d], x[j][d]), Lt[d]);
+                }
         }
-        __syncthreads();
+        // the potential energy is an observable of the last force evaluation
+        chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, step == nmd - 1);
+        // colloids (wave 0): second half kick, RATTLE velocity stage,
+        // Verlet-list soundness check (displacement within the interval)
+        if (colloid_wave) {
+            if (t < nc)
+                for (int d = 0; d < 3; ++d) S.sV[t][d] = fma(cp->hc[t], S.sF[t][d], S.sV[t][d]);
+            wave_sync();
+            if (t < cp->nbonds) {
+                const int a = cp->bond_a[t], b = cp->bond_b[t];
+                double r[3], vr[3];
+                for (int d = 0; d < 3; ++d) {
+                    r[d] = S.sX[a][d] - S.sX[b][d];
+                    vr[d] = S.sV[a][d] - S.sV[b][d];
+                }
+                double mu = cp->imass[a] + cp->imass[b];
+                double rr = dot3(r[0], r[1], r[2], r[0], r[1], r[2]);
+                double vrr = dot3(vr[0], vr[1], vr[2], r[0], r[1], r[2]);
+                double k = vrr / (mu * rr);
+                double ka = k * cp->imass[a], kb = k * cp->imass[b];
+                for (int d = 0; d < 3; ++d) {
+                    S.sV[a][d] = S.sV[a][d] - (ka * r[d]);
+                    S.sV[b][d] = S.sV[b][d] + (kb * r[d]);
+                }
+            }
+            wave_sync();
+            if (t < nc) {
+                double dx = S.sX[t][0] - S.sX0[t][0], dy = S.sX[t][1] - S.sX0[t][1],
+                       dz = S.sX[t][2] - S.sX0[t][2];
+                if (dot3(dx, dy, dz, dx, dy, dz) >= D.skin_half2)
+                    atomicOr(&S.sflags, RMP_FLAG_DISPLACEMENT);
+            }
+            wave_sync();
+        }
     }
+    __syncthreads();
     // write back list entries and bin them for the coming collision
     double s3[3];
     shift_of(D.seed, coll, s3);
