@@ -150,7 +150,7 @@ Layout layout_of(const rmp_params* p)
 
 size_t ctl_bytes_for(int32_t nslots)
 {
-    return aup(sizeof(RepDesc) * (size_t)nslots) + 6 * aup(4 * (size_t)(nslots + 1));
+    return aup(sizeof(RepDesc) * (size_t)nslots) + 6 * aup(4 * (size_t)(nslots + 1)) + aup(16);
 }
 
 const char* KNAMES[] = {"stream_bin", "chain", "scan_blocks", "scan_final", "scatter",
@@ -186,6 +186,8 @@ struct rmp_batch {
     char* ctl = nullptr;
     RepDesc* d_desc = nullptr;
     int32_t* d_prefix[6] = {};
+    uint32_t* d_tick = nullptr;     // chain work-list tickets (two counters)
+    int32_t chain_resident[3] = {}; // chain workgroups the device holds at once, K = 1, 2, 4
     std::vector<Replica> reps;
     std::vector<RepDesc> hdesc;
     std::vector<int32_t> hprefix[6];
@@ -193,7 +195,7 @@ struct rmp_batch {
     bool dirty = true;
     bool have_rule[2] = {false, false};
     bool multi_scan = false;
-    rmp_tuning tun{256, 1, 32, 1, 1};
+    rmp_tuning tun{256, 1, 32, 1, 1, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
@@ -244,6 +246,21 @@ rmp_status last_launch(const char* what)
 // Verlet-list entries per chain thread: the tuned value, raised to the
 // smallest power of two for which every occupied replica's list capacity
 // fits in MAX_G workgroups
+int chain_groups(const rmp_batch* b, int k)
+{
+    int64_t total = 0;
+    for (const auto& R : b->reps) {
+        if (!R.used) continue;
+        int64_t g = (R.sz.cand_cap + (int64_t)CHAIN_BLOCK * k - 1) / ((int64_t)CHAIN_BLOCK * k);
+        total += std::max<int64_t>(1, std::min<int64_t>(g, R.sz.G));
+    }
+    return (int)std::min<int64_t>(total, INT32_MAX);
+}
+
+// Entries per chain thread: the tuned value, raised until every system's
+// list fits its workgroups, then raised while the batch's chain workgroups
+// exceed what the device holds at once (past that point they would run in
+// waves, each wave paying the full per-step exchange latency).
 int chain_k_of(const rmp_batch* b)
 {
     int k = b->tun.chain_k;
@@ -252,6 +269,11 @@ int chain_k_of(const rmp_batch* b)
         if (!R.used) continue;
         while (k < K_MAX && (int64_t)R.sz.cand_cap > (int64_t)MAX_G * CHAIN_BLOCK * k) k *= 2;
     }
+    auto resident = [b](int kk) {
+        return b->tun.chain_resident > 0 ? b->tun.chain_resident
+                                         : b->chain_resident[kk == 1 ? 0 : (kk == 2 ? 1 : 2)];
+    };
+    while (k < K_MAX && chain_groups(b, k) > resident(k)) k *= 2;
     return k;
 }
 
@@ -412,6 +434,7 @@ Work work(const rmp_batch* b, int kind)
     Work w;
     w.desc = b->d_desc;
     w.prefix = b->d_prefix[kind];
+    w.tick = b->d_tick;
     w.nrep = b->nslots;
     w.pad = 0;
     return w;
@@ -469,9 +492,18 @@ rmp_status launch_chain(rmp_batch* b, hipStream_t s)
     Timer tm(b, KN_CHAIN, s);
     const int K = chain_k_of(b);
     dim3 g(b->totals[PF_CHAIN]), blk(CHAIN_BLOCK);
-    if (K == 1) hipLaunchKernelGGL((k_chain<T, 1>), g, blk, 0, s, work(b, PF_CHAIN));
-    else if (K == 2) hipLaunchKernelGGL((k_chain<T, 2>), g, blk, 0, s, work(b, PF_CHAIN));
-    else hipLaunchKernelGGL((k_chain<T, 4>), g, blk, 0, s, work(b, PF_CHAIN));
+    const int q = K == 1 ? 0 : (K == 2 ? 1 : 2);
+    // more workgroups than the device holds at once: ticketed work list
+    const bool ticket = b->totals[PF_CHAIN] > b->chain_resident[q];
+    if (ticket) {
+        if (K == 1) hipLaunchKernelGGL((k_chain<T, 1, true>), g, blk, 0, s, work(b, PF_CHAIN));
+        else if (K == 2) hipLaunchKernelGGL((k_chain<T, 2, true>), g, blk, 0, s, work(b, PF_CHAIN));
+        else hipLaunchKernelGGL((k_chain<T, 4, true>), g, blk, 0, s, work(b, PF_CHAIN));
+    } else {
+        if (K == 1) hipLaunchKernelGGL((k_chain<T, 1, false>), g, blk, 0, s, work(b, PF_CHAIN));
+        else if (K == 2) hipLaunchKernelGGL((k_chain<T, 2, false>), g, blk, 0, s, work(b, PF_CHAIN));
+        else hipLaunchKernelGGL((k_chain<T, 4, false>), g, blk, 0, s, work(b, PF_CHAIN));
+    }
     return last_launch("k_chain");
 }
 
@@ -699,6 +731,26 @@ rmp_status batch_init(rmp_batch* b, int32_t nslots, int32_t precision, void* ctl
     for (int k = 0; k < 6; ++k) {
         b->d_prefix[k] = (int32_t*)(b->ctl + o);
         o += aup(4 * (size_t)(nslots + 1));
+    }
+    b->d_tick = (uint32_t*)(b->ctl + o);
+    o += aup(16);
+    HIPCHK(hipMemsetAsync(b->d_tick, 0, 16, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    {
+        int dev = 0, ncu = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        int per[3] = {0, 0, 0};
+        if (precision == 64) {
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<double, 1, false>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<double, 2, false>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<double, 4, false>, CHAIN_BLOCK, 0));
+        } else {
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<float, 1, false>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<float, 2, false>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<float, 4, false>, CHAIN_BLOCK, 0));
+        }
+        for (int q = 0; q < 3; ++q) b->chain_resident[q] = std::max(1, per[q]) * std::max(1, ncu);
     }
     b->reps.assign(nslots, Replica{});
     b->hdesc.assign(nslots, RepDesc{});
@@ -1075,6 +1127,7 @@ rmp_status rmp_batch_set_tuning(rmp_batch* b, const rmp_tuning* t)
     if (t->collide_cells > 0) n.collide_cells = t->collide_cells;
     if (t->chain_k > 0) n.chain_k = t->chain_k;
     if (t->use_graph >= 0) n.use_graph = t->use_graph;
+    if (t->chain_resident >= 0) n.chain_resident = t->chain_resident;
     if (n.chain_k != 1 && n.chain_k != 2 && n.chain_k != 4) return RMP_EINVAL;
     if (n.stream_block != 64 && n.stream_block != 128 && n.stream_block != 256) return RMP_EINVAL;
     b->tun = n;

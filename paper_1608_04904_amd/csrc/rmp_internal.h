@@ -88,6 +88,7 @@ struct RepDesc {
 struct Work {
     const RepDesc* desc;
     const int32_t* prefix;
+    uint32_t* tick;   // [0] next ticket, [1] finished workgroups; zero between launches
     int32_t nrep;
     int32_t pad;
 };

@@ -710,21 +710,28 @@ __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& 
             // (RMP_FLAG_BARRIER) it does not wait on later ones, so a kernel
             // whose peers cannot all run ends within about one time budget
             const uint64_t t_start = wall_clock64();
+            int nap = 1;
             while (true) {
-                // unconditional loads from clamped addresses, all issued
-                // before any result is examined; unused entries are masked
+                // the loads of one round are all issued before any result is
+                // examined; only (value, workgroup) slots that exist are
+                // loaded (wave-uniform guards): a co-resident workgroup that
+                // is still computing must not be starved by polling traffic
                 uint64_t wl[VB][4], wh[VB][4];
 #pragma unroll
                 for (int vb = 0; vb < VB; ++vb) {
                     const int v = v0 + vb * NW;
-                    const int vc = v < nv ? v : nv - 1;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int gg = lane * Q + q;
-                        const int gc = (q < Q && gg < Gact) ? gg : 0;
-                        const int64_t o = ((int64_t)gc * NVAL_MAX + vc) * 2;
-                        wl[vb][q] = __hip_atomic_load(&part[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        wh[vb][q] = __hip_atomic_load(&part[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const int gc = gg < Gact ? gg : 0;
+                        const int64_t o = ((int64_t)gc * NVAL_MAX + v) * 2;
+                        if (v < nv && q < Q) {
+                            wl[vb][q] = __hip_atomic_load(&part[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            wh[vb][q] = __hip_atomic_load(&part[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        } else {
+                            wl[vb][q] = 0;
+                            wh[vb][q] = 0;
+                        }
                     }
                 }
                 bool ok = true;
@@ -748,6 +755,9 @@ __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& 
                     if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
                     break;
                 }
+                // exponential back-off (64 to 512 clocks) for longer waits
+                for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(1);
+                nap = nap < 8 ? 2 * nap : 8;
             }
 #pragma unroll
             for (int vb = 0; vb < VB; ++vb) {
@@ -807,9 +817,8 @@ __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& 
 }
 
 template <class T, int K>
-__global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
+__device__ __forceinline__ void chain_run(Work w, int item)
 {
-    const int item = blockIdx.x;
     const int rep = find_rep(w.prefix, w.nrep, item);
     const int g = item - w.prefix[rep];
     const RepDesc& D = w.desc[rep];
@@ -1058,6 +1067,37 @@ __global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
             for (int c = 0; c < nc; ++c)
                 for (int d = 0; d < 3; ++d)
                     if (!isfinite(S.sF[c][d])) atomicOr(&rs->flags, RMP_FLAG_NONFINITE);
+        }
+    }
+}
+
+// Work-list position of a chain workgroup.  When every workgroup of the
+// launch fits on the device at once it is blockIdx.  Otherwise (TICKET)
+// workgroups take their positions in the order they start running, from a
+// device counter: the workgroups of one system hold consecutive positions,
+// so every system whose positions have all been taken is entirely resident
+// and its exchange waits end, even though the launch runs in waves.  The
+// last workgroup to finish puts the counters back to zero for the next
+// launch.  (The ticket is a separate instantiation because an atomic at
+// kernel entry keeps the descriptor loads of the whole kernel off the
+// scalar unit.)
+template <class T, int K, bool TICKET>
+__global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
+{
+    if (!TICKET) {
+        chain_run<T, K>(w, (int)blockIdx.x);
+        return;
+    }
+    __shared__ int s_item;
+    if (threadIdx.x == 0)
+        s_item = (int)__hip_atomic_fetch_add(&w.tick[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    chain_run<T, K>(w, s_item);
+    if (threadIdx.x == 0) {
+        const uint32_t fin = __hip_atomic_fetch_add(&w.tick[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (fin == gridDim.x - 1) {
+            __hip_atomic_store(&w.tick[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&w.tick[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -1497,9 +1537,12 @@ __global__ __launch_bounds__(256) void k_observe(Work w)
     template __global__ void k_init_sub<T>(const RepDesc*, const double*);       \
     template __global__ void k_list<T>(Work);                                    \
     template __global__ void k_stream_bin<T>(Work, int);                         \
-    template __global__ void k_chain<T, 1>(Work);                                \
-    template __global__ void k_chain<T, 2>(Work);                                \
-    template __global__ void k_chain<T, 4>(Work);                                \
+    template __global__ void k_chain<T, 1, false>(Work);                         \
+    template __global__ void k_chain<T, 2, false>(Work);                         \
+    template __global__ void k_chain<T, 4, false>(Work);                         \
+    template __global__ void k_chain<T, 1, true>(Work);                          \
+    template __global__ void k_chain<T, 2, true>(Work);                          \
+    template __global__ void k_chain<T, 4, true>(Work);                          \
     template __global__ void k_collide<T, 0>(Work);                              \
     template __global__ void k_collide<T, 1>(Work);                              \
     template __global__ void k_observe<T>(Work);

@@ -48,16 +48,19 @@ def _run_both(p, state, seed, n_md, n_coll, tuning=None, per_call=None):
 
 
 def _assert_bitwise(gs, os_, what=""):
+    errs = []
     for k in ("id", "state", "x", "v", "X", "V"):
         a, b = np.asarray(gs[k]), np.asarray(os_[k])
         if not np.array_equal(a, b):
-            if a.dtype.kind == "f":
-                bad = np.argwhere(a != b)
-                diff = np.abs(a - b).max()
-                raise AssertionError(f"{what}: {k} differs at {len(bad)} entries, first {bad[:3].tolist()}, "
-                                     f"max abs diff {diff}")
             bad = np.argwhere(a != b)
-            raise AssertionError(f"{what}: {k} differs at {len(bad)} entries, first {bad[:5].tolist()}")
+            first = [tuple(int(q) for q in i) for i in bad[:3]]
+            vals = [(a[i].tolist(), b[i].tolist()) for i in first]
+            msg = f"{k} differs at {len(bad)} entries, first {first} (gpu, oracle) {vals}"
+            if a.dtype.kind == "f":
+                msg += f", max abs diff {np.abs(a - b).max()}"
+            errs.append(msg)
+    if errs:
+        raise AssertionError(f"{what}: " + "; ".join(errs))
     assert gs["md_step"] == os_["md_step"] and gs["coll_step"] == os_["coll_step"]
 
 
@@ -292,7 +295,8 @@ def test_batch_replicas_match_alone_and_oracle():
         o = oracle.Oracle(p, seeds[i], init=False)
         o.set_state(states[i])
         o.run(p["n_md"], 3)
-        _assert_bitwise(b.get_state(i), o.get_state(), f"replica {i}")
+        fl = b.observables(i, raise_on_flags=False)["flags"]
+        _assert_bitwise(b.get_state(i), o.get_state(), f"replica {i} (flags {fl})")
         _assert_obs(b.observables(i), o.observables())
     # retire one, admit another, keep stepping: the others are unaffected
     b.clear_slot(1)
@@ -309,3 +313,37 @@ def test_batch_replicas_match_alone_and_oracle():
     o0.set_state(states[0])
     o0.run(ps[0]["n_md"], 5)
     _assert_bitwise(b.get_state(0), o0.get_state(), "replica 0 after 5 ticks")
+
+
+def test_batch_chain_waves_match_resident_launch_and_oracle():
+    """64 replicas with one list entry per chain thread and the K raise
+    switched off: far more chain workgroups than the device holds at once,
+    so they run in waves through the ticketed work list.  Every replica ends
+    bit-identical to the launch shape that fits on the device, none reports a
+    timed-out exchange wait, and two sampled replicas match the oracle."""
+    rm = _rm()
+    ps = W.batch_replicas(n=64, edges=(16, 20, 24), precision=64)
+    for p in ps:
+        p["n_md"] = 10
+    states = [W.random_state(p, 500 + i, species_B_fraction=0.1) for i, p in enumerate(ps)]
+    out = {}
+    for name, tun in (("waves", dict(chain_k=1, chain_resident=1 << 30)), ("resident", {})):
+        print(f"[parity] batch of {len(ps)} tuning={tun}", flush=True)
+        b = rm.Batch(len(ps), precision=64)
+        if tun:
+            b.set_tuning(**tun)
+        for i, p in enumerate(ps):
+            b.set_slot(i, p, p["seed"], p["n_md"])
+            b.set_state(i, states[i])
+        b.step(1)
+        out[name] = [b.get_state(i) for i in range(len(ps))]
+        flags = [b.observables(i, raise_on_flags=False)["flags"] for i in range(len(ps))]
+        assert not any(flags), f"{name}: flagged replicas {[i for i, f in enumerate(flags) if f]}"
+        del b
+    for i in range(len(ps)):
+        _assert_bitwise(out["waves"][i], out["resident"][i], f"replica {i}")
+    for i in (0, len(ps) - 1):
+        o = oracle.Oracle(ps[i], ps[i]["seed"], init=False)
+        o.set_state(states[i])
+        o.run(ps[i]["n_md"], 1)
+        _assert_bitwise(out["waves"][i], o.get_state(), f"replica {i} vs oracle")
