@@ -358,6 +358,7 @@ ColloidParams make_cp(const rmp_params* p)
     c.nc = p->n_colloids;
     c.nbonds = p->n_bonds;
     for (int i = 0; i < RMP_MAX_COLLOIDS; ++i) c.partner[i] = -1;
+    for (int i = 0; i < RMP_MAX_COLLOIDS; ++i) c.bond_of[i] = -1;
     for (int i = 0; i < p->n_colloids; ++i) {
         c.catalytic[i] = p->catalytic[i] ? 1 : 0;
         c.ctype[i] = p->ctype[i];
@@ -380,6 +381,8 @@ ColloidParams make_cp(const rmp_params* p)
         c.bond_d[b] = p->bond_d[b];
         c.partner[p->bond_a[b]] = p->bond_b[b];
         c.partner[p->bond_b[b]] = p->bond_a[b];
+        c.bond_of[p->bond_a[b]] = b;
+        c.bond_of[p->bond_b[b]] = b;
     }
     return c;
 }

@@ -25,7 +25,7 @@ enum : uint64_t {
 struct ColloidParams {
     int32_t nc, nbonds;
     int32_t catalytic[MAXC], ctype[MAXC], partner[MAXC];
-    int32_t bond_a[MAXC], bond_b[MAXC];
+    int32_t bond_a[MAXC], bond_b[MAXC], bond_of[MAXC];   // bond_of: bond of a colloid, -1 if none
     double bond_d[MAXC];
     double sigma[MAXC], sig2[MAXC], rc2[MAXC], reachR[MAXC];
     double epsA[MAXC], epsB[MAXC];

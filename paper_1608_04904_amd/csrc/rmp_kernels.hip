@@ -60,6 +60,31 @@ __device__ __forceinline__ double wave_tree_sum(double v)
     return a + b;
 }
 
+// wave_tree_sum of N independent values, level by level so that the N
+// dependent chains overlap (each value's additions are the same as above)
+template <int N>
+__device__ __forceinline__ void wave_tree_sum_n(double (&v)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_d<0xB1, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_d<0x4E, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_d<0x141, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_d<0x140, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_d<0x142, 0xA>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v[i]), 31),
+                                          __builtin_amdgcn_readlane(__double2loint(v[i]), 31));
+        const double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v[i]), 63),
+                                          __builtin_amdgcn_readlane(__double2loint(v[i]), 63));
+        v[i] = a + b;
+    }
+}
+
 // deterministic block sum: wave butterfly, then a pairwise tree over the
 // wave sums (xor butterfly over the first NT/64 lanes of wave 0)
 template <int NT>
@@ -534,12 +559,126 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ double shfl_d(double v, int src)
+{
+    const int lo = __shfl(__double2loint(v), src, 64);
+    const int hi = __shfl(__double2hiint(v), src, 64);
+    return __hiloint2double(hi, lo);
+}
+
+// Bond of the colloid of lane t (t < nc), loaded once per interval
+struct BondLane {
+    int other;                 // lane of the bond partner (t itself if none)
+    bool has, ia;              // has a bond; is its first colloid a
+    double dd, ima, imb, mu;   // bond length, inverse masses of a and b, sum
+};
+
+__device__ __forceinline__ BondLane bond_lane(const ColloidParams* cp, int nc)
+{
+    const int t = threadIdx.x & 63;
+    BondLane L;
+    const int k = t < nc ? cp->bond_of[t] : -1;
+    L.has = k >= 0;
+    const int a = L.has ? cp->bond_a[k] : t, b = L.has ? cp->bond_b[k] : t;
+    L.ia = t == a;
+    L.other = L.ia ? b : a;
+    L.dd = L.has ? cp->bond_d[k] : 0.0;
+    L.ima = L.has ? cp->imass[a] : 0.0;
+    L.imb = L.has ? cp->imass[b] : 0.0;
+    L.mu = L.ima + L.imb;
+    return L;
+}
+
+// RATTLE position stage for the colloid of lane t (t < nc, all 64 lanes of
+// the wave call it).  Both colloids of a bond evaluate the bond's
+// correction from the same operands in the bond's (a, b) order, so they
+// agree exactly; Xo are the positions before the drift.
+__device__ __forceinline__ void rattle_pos_lane(const BondLane& L, double dt, double (&X)[3], double (&V)[3],
+                                                const double (&Xo)[3], uint32_t& flags)
+{
+    double pXo[3], pX[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        pXo[d] = shfl_d(Xo[d], L.other);
+        pX[d] = shfl_d(X[d], L.other);
+    }
+    if (!L.has) return;
+    const bool ia = L.ia;
+    double r0[3], sv[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        r0[d] = ia ? Xo[d] - pXo[d] : pXo[d] - Xo[d];
+        sv[d] = ia ? X[d] - pX[d] : pX[d] - X[d];
+    }
+    const double mu = L.mu;
+    const double r0r0 = dot3(r0[0], r0[1], r0[2], r0[0], r0[1], r0[2]);
+    const double sr0 = dot3(sv[0], sv[1], sv[2], r0[0], r0[1], r0[2]);
+    const double ss = dot3(sv[0], sv[1], sv[2], sv[0], sv[1], sv[2]);
+    const double A = (mu * mu) * r0r0;
+    const double Bh = mu * sr0;
+    const double C = ss - (L.dd * L.dd);
+    double disc = (Bh * Bh) - (A * C);
+    if (disc < 0.0) {
+        flags |= RMP_FLAG_RATTLE;
+        disc = 0.0;
+    }
+    const double gq = C / (Bh + sqrt(disc));
+    if (ia) {
+        const double ga = gq * L.ima;
+        const double gad = ga / dt;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            X[d] = X[d] - (ga * r0[d]);
+            V[d] = V[d] - (gad * r0[d]);
+        }
+    } else {
+        const double gb = gq * L.imb;
+        const double gbd = gb / dt;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            X[d] = X[d] + (gb * r0[d]);
+            V[d] = V[d] + (gbd * r0[d]);
+        }
+    }
+}
+
+// RATTLE velocity stage for the colloid of lane t (same conventions)
+__device__ __forceinline__ void rattle_vel_lane(const BondLane& L, const double (&X)[3], double (&V)[3])
+{
+    double pX[3], pV[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        pX[d] = shfl_d(X[d], L.other);
+        pV[d] = shfl_d(V[d], L.other);
+    }
+    if (!L.has) return;
+    const bool ia = L.ia;
+    double r[3], vr[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        r[d] = ia ? X[d] - pX[d] : pX[d] - X[d];
+        vr[d] = ia ? V[d] - pV[d] : pV[d] - V[d];
+    }
+    const double rr = dot3(r[0], r[1], r[2], r[0], r[1], r[2]);
+    const double vrr = dot3(vr[0], vr[1], vr[2], r[0], r[1], r[2]);
+    const double kk = vrr / (L.mu * rr);
+    if (ia) {
+        const double ka = kk * L.ima;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) V[d] = V[d] - (ka * r[d]);
+    } else {
+        const double kb = kk * L.imb;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) V[d] = V[d] + (kb * r[d]);
+    }
+}
+
 // Chain workgroup g of a replica holds Verlet-list positions
 // [g*B, (g+1)*B), B = 256*K, K consecutive positions per thread, in
 // registers for the whole interval.
 template <class T, int K>
 struct ChainCtx {
-    double sX[MAXC][3], sV[MAXC][3], sF[MAXC][3], sXw[MAXC][3], sX0[MAXC][3], sXold[MAXC][3];
+    double sXw[MAXC][3];       // periodic images of the colloid positions
     double sRed[CHAIN_BLOCK / 64][NVAL_MAX];
     double sNode[NVAL_MAX];
     double sU;
@@ -566,85 +705,95 @@ __device__ __forceinline__ void chain_compute(ChainCtx<T, K>& S, const RepDesc& 
         u[j] = 0.0;
         inside[j] = false;
     }
-    for (int c = 0; c < nc; ++c) {
-        const double Xc0 = S.sXw[c][0], Xc1 = S.sXw[c][1], Xc2 = S.sXw[c][2];
-        const double rc2 = cp->rc2[c], sig2 = cp->sig2[c];
-        const double eA = cp->epsA[c], eB = cp->epsB[c];
-        const bool cat = cp->catalytic[c] != 0;
-        double gx[K], gy[K], gz[K];
-        bool any = false;
-        // distances for the K entries, then the WCA terms only if some lane
-        // of the wave is inside this colloid's cut-off (wave-uniform test);
-        // within it the K entries are evaluated branch-free with selects, the
-        // untaken case at the cut-off radius (result discarded)
-        double dxs[K], dys[K], dzs[K], r2s[K];
-        bool hit[K];
+    // colloids two at a time: forces and the reduction over the K entries
+    // of each thread, then the wave trees of the six components (and, after
+    // the last pair, of the potential) side by side
+    constexpr int CB = 2;
+    for (int c0 = 0; c0 < nc; c0 += CB) {
+        double tv[3 * CB + 1];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            dxs[j] = min_image((double)x[j][0] - Xc0, D.Ld[0], D.halfL[0]);
-            dys[j] = min_image((double)x[j][1] - Xc1, D.Ld[1], D.halfL[1]);
-            dzs[j] = min_image((double)x[j][2] - Xc2, D.Ld[2], D.halfL[2]);
-            r2s[j] = dot3(dxs[j], dys[j], dzs[j], dxs[j], dys[j], dzs[j]);
-            hit[j] = valid[j] && (r2s[j] < rc2);
-            any = any || hit[j];
-            gx[j] = 0.0; gy[j] = 0.0; gz[j] = 0.0;
-        }
-        if (__ballot(any) != 0) {
+        for (int cb = 0; cb < CB; ++cb) {
+            const int c = c0 + cb;
+            tv[3 * cb + 0] = 0.0; tv[3 * cb + 1] = 0.0; tv[3 * cb + 2] = 0.0;
+            if (c >= nc) continue;
+            const double Xc0 = S.sXw[c][0], Xc1 = S.sXw[c][1], Xc2 = S.sXw[c][2];
+            const double rc2 = cp->rc2[c], sig2 = cp->sig2[c];
+            const double eA = cp->epsA[c], eB = cp->epsB[c];
+            const bool cat = cp->catalytic[c] != 0;
+            double gx[K], gy[K], gz[K];
+            bool any = false;
+            // distances for the K entries, then the WCA terms only if some
+            // lane of the wave is inside this colloid's cut-off (wave-uniform
+            // test); within it the K entries are evaluated branch-free with
+            // selects, the untaken case at the cut-off radius (discarded)
+            double dxs[K], dys[K], dzs[K], r2s[K];
+            bool hit[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                double coef, pot;
-                wca(hit[j] ? r2s[j] : rc2, sig2, (st[j] & 1) ? eB : eA, coef, pot);
-                const double ax = coef * dxs[j], ay = coef * dys[j], az = coef * dzs[j];
-                gx[j] = hit[j] ? ax : 0.0;
-                gy[j] = hit[j] ? ay : 0.0;
-                gz[j] = hit[j] ? az : 0.0;
-                f[j][0] = hit[j] ? f[j][0] + ax : f[j][0];
-                f[j][1] = hit[j] ? f[j][1] + ay : f[j][1];
-                f[j][2] = hit[j] ? f[j][2] + az : f[j][2];
-                u[j] = hit[j] ? u[j] + pot : u[j];
-                inside[j] = inside[j] || (hit[j] && cat);
+                dxs[j] = min_image((double)x[j][0] - Xc0, D.Ld[0], D.halfL[0]);
+                dys[j] = min_image((double)x[j][1] - Xc1, D.Ld[1], D.halfL[1]);
+                dzs[j] = min_image((double)x[j][2] - Xc2, D.Ld[2], D.halfL[2]);
+                r2s[j] = dot3(dxs[j], dys[j], dzs[j], dxs[j], dys[j], dzs[j]);
+                hit[j] = valid[j] && (r2s[j] < rc2);
+                any = any || hit[j];
+                gx[j] = 0.0; gy[j] = 0.0; gz[j] = 0.0;
             }
-        }
-        // reduce the three components over list positions
-        const bool wave_any = __ballot(any) != 0;
-        double r[3];
-        {
-            double a0[K], a1[K], a2[K];
+            if (__ballot(any) != 0) {
 #pragma unroll
-            for (int j = 0; j < K; ++j) { a0[j] = gx[j]; a1[j] = gy[j]; a2[j] = gz[j]; }
-#pragma unroll
-            for (int s = 1; s < K; s <<= 1)
-#pragma unroll
-                for (int j = 0; j + s < K; j += 2 * s) {
-                    a0[j] = a0[j] + a0[j + s];
-                    a1[j] = a1[j] + a1[j + s];
-                    a2[j] = a2[j] + a2[j + s];
+                for (int j = 0; j < K; ++j) {
+                    double coef, pot;
+                    wca(hit[j] ? r2s[j] : rc2, sig2, (st[j] & 1) ? eB : eA, coef, pot);
+                    const double ax = coef * dxs[j], ay = coef * dys[j], az = coef * dzs[j];
+                    gx[j] = hit[j] ? ax : 0.0;
+                    gy[j] = hit[j] ? ay : 0.0;
+                    gz[j] = hit[j] ? az : 0.0;
+                    f[j][0] = hit[j] ? f[j][0] + ax : f[j][0];
+                    f[j][1] = hit[j] ? f[j][1] + ay : f[j][1];
+                    f[j][2] = hit[j] ? f[j][2] + az : f[j][2];
+                    u[j] = hit[j] ? u[j] + pot : u[j];
+                    inside[j] = inside[j] || (hit[j] && cat);
                 }
-            r[0] = a0[0]; r[1] = a1[0]; r[2] = a2[0];
+            }
+            // the three components over this thread's K list positions
+#pragma unroll
+            for (int s2 = 1; s2 < K; s2 <<= 1)
+#pragma unroll
+                for (int j = 0; j + s2 < K; j += 2 * s2) {
+                    gx[j] = gx[j] + gx[j + s2];
+                    gy[j] = gy[j] + gy[j + s2];
+                    gz[j] = gz[j] + gz[j + s2];
+                }
+            tv[3 * cb + 0] = gx[0]; tv[3 * cb + 1] = gy[0]; tv[3 * cb + 2] = gz[0];
         }
-        if (wave_any) {
-            r[0] = wave_tree_sum(r[0]);
-            r[1] = wave_tree_sum(r[1]);
-            r[2] = wave_tree_sum(r[2]);
-        } else {
-            r[0] = 0.0; r[1] = 0.0; r[2] = 0.0;
+        const bool last = c0 + CB >= nc;
+        tv[3 * CB] = 0.0;
+        if (last) {
+            double a[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) a[j] = u[j];
+#pragma unroll
+            for (int s2 = 1; s2 < K; s2 <<= 1)
+#pragma unroll
+                for (int j = 0; j + s2 < K; j += 2 * s2) a[j] = a[j] + a[j + s2];
+            tv[3 * CB] = a[0];
         }
+        wave_tree_sum_n<3 * CB + 1>(tv);
         if (lane == 0) {
-            S.sRed[wave][3 * c + 0] = r[0];
-            S.sRed[wave][3 * c + 1] = r[1];
-            S.sRed[wave][3 * c + 2] = r[2];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int c = c0 + cb;
+                if (c < nc) {
+                    S.sRed[wave][3 * c + 0] = tv[3 * cb + 0];
+                    S.sRed[wave][3 * c + 1] = tv[3 * cb + 1];
+                    S.sRed[wave][3 * c + 2] = tv[3 * cb + 2];
+                }
+            }
+            if (last) S.sRed[wave][3 * nc] = tv[3 * CB];
         }
     }
-    {
-        double a[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) a[j] = u[j];
-#pragma unroll
-        for (int s = 1; s < K; s <<= 1)
-#pragma unroll
-            for (int j = 0; j + s < K; j += 2 * s) a[j] = a[j] + a[j + s];
-        const double r = wave_tree_sum(a[0]);
-        if (lane == 0) S.sRed[wave][3 * nc] = r;
+    if (nc == 0) {
+        // no colloid: the potential of the list is zero (tree of zeros)
+        if (lane == 0) S.sRed[wave][0] = 0.0;
     }
     __syncthreads();
     const int nv = 3 * nc + 1;
@@ -680,98 +829,121 @@ __device__ __forceinline__ void chain_compute(ChainCtx<T, K>& S, const RepDesc& 
     }
 }
 
+// Wait (bounded) for the exchange words of values v = v0 + vb*vs (vb < VB,
+// v < nv) of workgroups [0, Gact) at this barrier, then reduce each value
+// over the workgroups with the fixed tree: lane l holds workgroups
+// [l*Q, l*Q+Q) (Q <= QM), summed pairwise, then the wave tree, padded with
+// zeros to a power of two.  out[vb] is the same in every lane.  Only slots
+// that exist are loaded (wave-uniform guards): a co-resident workgroup that
+// is still computing must not be starved by polling traffic.
+template <int VB, int QM, class Ctx>
+__device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0, int vs, int nv, int Gact,
+                                            int Q, uint32_t epoch, double (&out)[VB])
+{
+    const int lane = threadIdx.x & 63;
+    double b4[VB][QM];
+    // once this workgroup has given up on one barrier (RMP_FLAG_BARRIER) it
+    // does not wait on later ones, so a kernel whose peers cannot all run
+    // ends within about one time budget (wall_clock64 counts at 100 MHz)
+    const uint64_t t_start = wall_clock64();
+    int nap = 1;
+    while (true) {
+        uint64_t wl[VB][QM], wh[VB][QM];
+#pragma unroll
+        for (int vb = 0; vb < VB; ++vb) {
+            const int v = v0 + vb * vs;
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                const int gg = lane * Q + q;
+                const int gc = gg < Gact ? gg : 0;
+                const int64_t o = ((int64_t)gc * NVAL_MAX + v) * 2;
+                if (v < nv && q < Q) {
+                    wl[vb][q] = __hip_atomic_load(&part[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    wh[vb][q] = __hip_atomic_load(&part[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    wl[vb][q] = 0;
+                    wh[vb][q] = 0;
+                }
+            }
+        }
+        bool ok = true;
+#pragma unroll
+        for (int vb = 0; vb < VB; ++vb) {
+            const int v = v0 + vb * vs;
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                const int gg = lane * Q + q;
+                const bool use = v < nv && q < Q && gg < Gact;
+                const bool good = ((uint32_t)wl[vb][q] == epoch) & ((uint32_t)wh[vb][q] == epoch);
+                ok = ok & (!use | good);
+                b4[vb][q] = use ? __hiloint2double((int)(wh[vb][q] >> 32), (int)(wl[vb][q] >> 32)) : 0.0;
+            }
+        }
+        if (__ballot(!ok) == 0) break;
+        if (__hip_atomic_load(&S.sflags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & RMP_FLAG_BARRIER)
+            break;
+        if (wall_clock64() - t_start > BARRIER_BUDGET_TICKS) {
+            if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
+            break;
+        }
+        // exponential back-off (64 to 512 clocks) for longer waits
+        for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(1);
+        nap = nap < 8 ? 2 * nap : 8;
+    }
+#pragma unroll
+    for (int vb = 0; vb < VB; ++vb) {
+        double a2 = b4[vb][0];
+        if (QM >= 2 && Q == 2) a2 = b4[vb][0] + b4[vb][QM >= 2 ? 1 : 0];
+        if (QM >= 4 && Q == 4)
+            a2 = (b4[vb][0] + b4[vb][QM >= 4 ? 1 : 0]) + (b4[vb][QM >= 4 ? 2 : 0] + b4[vb][QM >= 4 ? 3 : 0]);
+        out[vb] = a2;
+    }
+    wave_tree_sum_n<VB>(out);
+}
+
 // Second half: wait for the other workgroups' node values of this
 // evaluation, finish the tree over workgroups, then the colloid forces
-// (solvent part, then colloid-colloid pairs in (a<b) order) into sF and,
-// when requested, the potential into sU.
+// (solvent part, then colloid-colloid pairs in (a<b) order) into cF of
+// thread c (c < nc) and, when requested, the potential into sU.  With at
+// most 8 values and 64 workgroups (one workgroup per lane) wave 0 does all
+// of it alone, and the other waves go straight on; otherwise every wave
+// collects a share of the values and the workgroup meets at a barrier.
 template <class T, int K>
 __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& D, const ColloidParams* cp,
                               int nc, int Gact, int Gpad, uint32_t nbar, uint32_t epoch0,
-                              bool want_potential)
+                              bool want_potential, double (&cF)[3])
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nv = 3 * nc + 1;
     constexpr int NW = CHAIN_BLOCK / 64;
+    const int Q = Gpad > 64 ? Gpad / 64 : 1;
+    const bool solo = Q == 1 && nv <= 8;
+    if (solo && wave != 0) return;
     if (Gact > 1) {
         const uint32_t epoch = epoch0 + nbar;
-        uint64_t* part = reinterpret_cast<uint64_t*>(D.partials) +
-                         (int64_t)(nbar & 1) * D.G * NVAL_MAX * 2;
-        // tree over workgroups, padded with zeros to Gpad (a power of two);
-        // lane l holds workgroups [l*Q, l*Q+Q), Q = max(1, Gpad/64) <= 4.
-        // A wave handles values v = wave, wave + NW, ...; it polls the words
-        // of up to VB of them per round so that their loads are in flight
-        // together.
-        constexpr int VB = 4;
-        // wall_clock64() counts at 100 MHz: 0.25 s per barrier at most
-        const int Q = Gpad > 64 ? Gpad / 64 : 1;
-        for (int v0 = wave; v0 < nv; v0 += NW * VB) {
-            double b4[VB][4];
-            // bounded wait: once this workgroup has given up on one barrier
-            // (RMP_FLAG_BARRIER) it does not wait on later ones, so a kernel
-            // whose peers cannot all run ends within about one time budget
-            const uint64_t t_start = wall_clock64();
-            int nap = 1;
-            while (true) {
-                // the loads of one round are all issued before any result is
-                // examined; only (value, workgroup) slots that exist are
-                // loaded (wave-uniform guards): a co-resident workgroup that
-                // is still computing must not be starved by polling traffic
-                uint64_t wl[VB][4], wh[VB][4];
+        const uint64_t* part = reinterpret_cast<const uint64_t*>(D.partials) +
+                               (int64_t)(nbar & 1) * D.G * NVAL_MAX * 2;
+        if (solo) {
+            double out[8];
+            poll_reduce<8, 1>(S, part, 0, 1, nv, Gact, 1, epoch, out);
+            if (lane == 0)
 #pragma unroll
-                for (int vb = 0; vb < VB; ++vb) {
-                    const int v = v0 + vb * NW;
+                for (int v = 0; v < 8; ++v)
+                    if (v < nv) S.sNode[v] = out[v];
+        } else {
+            constexpr int VB = 4;
+            for (int v0 = wave; v0 < nv; v0 += NW * VB) {
+                double out[VB];
+                poll_reduce<VB, 4>(S, part, v0, NW, nv, Gact, Q, epoch, out);
+                if (lane == 0)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int gg = lane * Q + q;
-                        const int gc = gg < Gact ? gg : 0;
-                        const int64_t o = ((int64_t)gc * NVAL_MAX + v) * 2;
-                        if (v < nv && q < Q) {
-                            wl[vb][q] = __hip_atomic_load(&part[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            wh[vb][q] = __hip_atomic_load(&part[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        } else {
-                            wl[vb][q] = 0;
-                            wh[vb][q] = 0;
-                        }
-                    }
-                }
-                bool ok = true;
-#pragma unroll
-                for (int vb = 0; vb < VB; ++vb) {
-                    const int v = v0 + vb * NW;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int gg = lane * Q + q;
-                        const bool use = v < nv && q < Q && gg < Gact;
-                        const bool good = ((uint32_t)wl[vb][q] == epoch) & ((uint32_t)wh[vb][q] == epoch);
-                        ok = ok & (!use | good);
-                        b4[vb][q] = use ? __hiloint2double((int)(wh[vb][q] >> 32), (int)(wl[vb][q] >> 32)) : 0.0;
-                    }
-                }
-                if (__ballot(!ok) == 0) break;
-                if (__hip_atomic_load(&S.sflags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) &
-                    RMP_FLAG_BARRIER)
-                    break;
-                if (wall_clock64() - t_start > BARRIER_BUDGET_TICKS) {
-                    if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
-                    break;
-                }
-                // exponential back-off (64 to 512 clocks) for longer waits
-                for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(1);
-                nap = nap < 8 ? 2 * nap : 8;
-            }
-#pragma unroll
-            for (int vb = 0; vb < VB; ++vb) {
-                const int v = v0 + vb * NW;
-                if (v >= nv) break;
-                double a2 = (Q == 1) ? b4[vb][0]
-                          : (Q == 2) ? (b4[vb][0] + b4[vb][1])
-                                     : ((b4[vb][0] + b4[vb][1]) + (b4[vb][2] + b4[vb][3]));
-                a2 = wave_tree_sum(a2);
-                if (lane == 0) S.sNode[v] = a2;
+                    for (int vb = 0; vb < VB; ++vb)
+                        if (v0 + vb * NW < nv) S.sNode[v0 + vb * NW] = out[vb];
             }
         }
     }
-    __syncthreads();
+    if (solo) wave_sync();
+    else __syncthreads();
     // colloid forces: solvent part, then colloid-colloid pairs in (a<b) order
     if (t < nc) {
         const int c = t;
@@ -792,7 +964,7 @@ __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& 
                 for (int d = 0; d < 3; ++d) F[d] = (c == lo) ? F[d] + g3[d] : F[d] - g3[d];
             }
         }
-        for (int d = 0; d < 3; ++d) S.sF[c][d] = F[d];
+        for (int d = 0; d < 3; ++d) cF[d] = F[d];
     }
     if (t == 0 && want_potential) {
         double ucc = 0.0;
@@ -813,7 +985,8 @@ __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& 
             }
         S.sU = S.sNode[3 * nc] + ucc;
     }
-    __syncthreads();
+    // no barrier here: the node values and colloid images are next written
+    // after the workgroup barrier that follows the colloid position update
 }
 
 template <class T, int K>
@@ -839,12 +1012,18 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     __shared__ ChainCtx<T, K> S;
     const int t = threadIdx.x;
     if (t == 0) S.sflags = 0;
+    // colloid c lives in registers of thread c (c < nc, wave 0): position,
+    // velocity, force, position at the start of the interval
+    double cX[3] = {0.0, 0.0, 0.0}, cV[3] = {0.0, 0.0, 0.0}, cF[3] = {0.0, 0.0, 0.0};
+    double cX0[3] = {0.0, 0.0, 0.0};
+    const BondLane BL = bond_lane(cp, nc);
+    const double chc = t < nc ? cp->hc[t] : 0.0;
     if (t < nc) {
         for (int d = 0; d < 3; ++d) {
-            S.sX[t][d] = rs->X[t][d];
-            S.sV[t][d] = rs->V[t][d];
-            S.sX0[t][d] = S.sX[t][d];
-            S.sXw[t][d] = colloid_image(S.sX[t][d], D.Ld[d]);
+            cX[d] = rs->X[t][d];
+            cV[d] = rs->V[t][d];
+            cX0[d] = cX[d];
+            S.sXw[t][d] = colloid_image(cX[d], D.Ld[d]);
         }
     }
     const int64_t coll = rs->coll_step;
@@ -888,7 +1067,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
 
     // forces at the start of the interval
     chain_compute<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
-    chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, false);
+    chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, false, cF);
     // list entries: first half kick and drift of step 0
 #pragma unroll
     for (int j = 0; j < K; ++j)
@@ -901,51 +1080,24 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     double eu = 0.0, ef = 0.0;
     for (int step = 0; step < nmd; ++step) {
         const int64_t md = md0 + step;
-        // colloids (wave 0 only, ordered by wave-level fences): half kick,
-        // drift, RATTLE position stage, periodic images
+        // colloids (wave 0, in registers): half kick, drift, RATTLE
+        // position stage, periodic images for the force evaluation
         if (colloid_wave) {
+            double cXo[3];
             if (t < nc) {
-                const int c = t;
                 for (int d = 0; d < 3; ++d) {
-                    S.sV[c][d] = fma(cp->hc[c], S.sF[c][d], S.sV[c][d]);
-                    S.sXold[c][d] = S.sX[c][d];
-                    S.sX[c][d] = fma(dt, S.sV[c][d], S.sX[c][d]);
+                    cV[d] = fma(chc, cF[d], cV[d]);
+                    cXo[d] = cX[d];
+                    cX[d] = fma(dt, cV[d], cX[d]);
                 }
+            } else {
+                for (int d = 0; d < 3; ++d) cXo[d] = cX[d];
             }
-            wave_sync();
-            if (t < cp->nbonds) {
-                const int a = cp->bond_a[t], b = cp->bond_b[t];
-                const double dd = cp->bond_d[t];
-                double r0[3], sv[3];
-                for (int d = 0; d < 3; ++d) {
-                    r0[d] = S.sXold[a][d] - S.sXold[b][d];
-                    sv[d] = S.sX[a][d] - S.sX[b][d];
-                }
-                double mu = cp->imass[a] + cp->imass[b];
-                double r0r0 = dot3(r0[0], r0[1], r0[2], r0[0], r0[1], r0[2]);
-                double sr0 = dot3(sv[0], sv[1], sv[2], r0[0], r0[1], r0[2]);
-                double ss = dot3(sv[0], sv[1], sv[2], sv[0], sv[1], sv[2]);
-                double A = (mu * mu) * r0r0;
-                double Bh = mu * sr0;
-                double C = ss - (dd * dd);
-                double disc = (Bh * Bh) - (A * C);
-                if (disc < 0.0) {
-                    atomicOr(&S.sflags, RMP_FLAG_RATTLE);
-                    disc = 0.0;
-                }
-                double gq = C / (Bh + sqrt(disc));
-                double ga = gq * cp->imass[a], gb = gq * cp->imass[b];
-                double gad = ga / dt, gbd = gb / dt;
-                for (int d = 0; d < 3; ++d) {
-                    S.sX[a][d] = S.sX[a][d] - (ga * r0[d]);
-                    S.sX[b][d] = S.sX[b][d] + (gb * r0[d]);
-                    S.sV[a][d] = S.sV[a][d] - (gad * r0[d]);
-                    S.sV[b][d] = S.sV[b][d] + (gbd * r0[d]);
-                }
-            }
-            wave_sync();
+            uint32_t lflags = 0;
+            rattle_pos_lane(BL, dt, cX, cV, cXo, lflags);
+            if (lflags) atomicOr(&S.sflags, lflags);
             if (t < nc)
-                for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(S.sX[t][d], D.Ld[d]);
+                for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(cX[d], D.Ld[d]);
         }
         __syncthreads();
         chain_compute<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
@@ -993,38 +1145,19 @@ __device__ __forceinline__ void chain_run(Work w, int item)
                 }
         }
         // the potential energy is an observable of the last force evaluation
-        chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, step == nmd - 1);
-        // colloids (wave 0): second half kick, RATTLE velocity stage,
-        // Verlet-list soundness check (displacement within the interval)
+        chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF);
+        // colloids (wave 0, in registers): second half kick, RATTLE
+        // velocity stage, Verlet-list soundness check (displacement within
+        // the interval)
         if (colloid_wave) {
             if (t < nc)
-                for (int d = 0; d < 3; ++d) S.sV[t][d] = fma(cp->hc[t], S.sF[t][d], S.sV[t][d]);
-            wave_sync();
-            if (t < cp->nbonds) {
-                const int a = cp->bond_a[t], b = cp->bond_b[t];
-                double r[3], vr[3];
-                for (int d = 0; d < 3; ++d) {
-                    r[d] = S.sX[a][d] - S.sX[b][d];
-                    vr[d] = S.sV[a][d] - S.sV[b][d];
-                }
-                double mu = cp->imass[a] + cp->imass[b];
-                double rr = dot3(r[0], r[1], r[2], r[0], r[1], r[2]);
-                double vrr = dot3(vr[0], vr[1], vr[2], r[0], r[1], r[2]);
-                double k = vrr / (mu * rr);
-                double ka = k * cp->imass[a], kb = k * cp->imass[b];
-                for (int d = 0; d < 3; ++d) {
-                    S.sV[a][d] = S.sV[a][d] - (ka * r[d]);
-                    S.sV[b][d] = S.sV[b][d] + (kb * r[d]);
-                }
-            }
-            wave_sync();
+                for (int d = 0; d < 3; ++d) cV[d] = fma(chc, cF[d], cV[d]);
+            rattle_vel_lane(BL, cX, cV);
             if (t < nc) {
-                double dx = S.sX[t][0] - S.sX0[t][0], dy = S.sX[t][1] - S.sX0[t][1],
-                       dz = S.sX[t][2] - S.sX0[t][2];
+                double dx = cX[0] - cX0[0], dy = cX[1] - cX0[1], dz = cX[2] - cX0[2];
                 if (dot3(dx, dy, dz, dx, dy, dz) >= D.skin_half2)
                     atomicOr(&S.sflags, RMP_FLAG_DISPLACEMENT);
             }
-            wave_sync();
         }
     }
     __syncthreads();
@@ -1054,19 +1187,20 @@ __device__ __forceinline__ void chain_run(Work w, int item)
         if (S.sflags) atomicOr(&rs->flags, S.sflags);
     }
     if (g == 0) {
-        if (t < nc)
+        if (t < nc) {
+            bool fin = true;
             for (int d = 0; d < 3; ++d) {
-                rs->X[t][d] = S.sX[t][d];
-                rs->V[t][d] = S.sV[t][d];
-                rs->F[t][d] = S.sF[t][d];
+                rs->X[t][d] = cX[d];
+                rs->V[t][d] = cV[d];
+                rs->F[t][d] = cF[d];
+                fin = fin && isfinite(cF[d]);
             }
+            if (!fin) atomicOr(&rs->flags, RMP_FLAG_NONFINITE);
+        }
         if (t == 0) {
             rs->U = S.sU;
             rs->md_step = md0 + nmd;
             rs->n_cand_used = ncand;
-            for (int c = 0; c < nc; ++c)
-                for (int d = 0; d < 3; ++d)
-                    if (!isfinite(S.sF[c][d])) atomicOr(&rs->flags, RMP_FLAG_NONFINITE);
         }
     }
 }
