@@ -188,6 +188,7 @@ struct rmp_batch {
     int32_t* d_prefix[6] = {};
     uint32_t* d_tick = nullptr;     // chain work-list tickets (two counters)
     int32_t chain_resident[3] = {}; // chain workgroups the device holds at once, K = 1, 2, 4
+    int32_t nc_common = -1;         // colloid count shared by every occupied slot, -1 if mixed
     std::vector<Replica> reps;
     std::vector<RepDesc> hdesc;
     std::vector<int32_t> hprefix[6];
@@ -423,6 +424,15 @@ rmp_status sync_ctl(rmp_batch* b)
         for (int k = 0; k < 6; ++k) b->hprefix[k][r + 1] = b->hprefix[k][r] + items[k];
     }
     for (int k = 0; k < 6; ++k) b->totals[k] = b->hprefix[k][S];
+    b->nc_common = -1;
+    bool first = true;
+    for (int r = 0; r < S; ++r) {
+        if (!b->reps[r].used) continue;
+        const int nc = b->reps[r].p.n_colloids;
+        if (first) b->nc_common = nc;
+        else if (b->nc_common != nc) b->nc_common = -1;
+        first = false;
+    }
     HIPCHK(hipMemcpyAsync(b->d_desc, b->hdesc.data(), sizeof(RepDesc) * S, hipMemcpyHostToDevice, b->stream));
     for (int k = 0; k < 6; ++k)
         HIPCHK(hipMemcpyAsync(b->d_prefix[k], b->hprefix[k].data(), 4 * (S + 1), hipMemcpyHostToDevice, b->stream));
@@ -498,14 +508,28 @@ rmp_status launch_chain(rmp_batch* b, hipStream_t s)
     const int q = K == 1 ? 0 : (K == 2 ? 1 : 2);
     // more workgroups than the device holds at once: ticketed work list
     const bool ticket = b->totals[PF_CHAIN] > b->chain_resident[q];
+    const Work w = work(b, PF_CHAIN);
     if (ticket) {
-        if (K == 1) hipLaunchKernelGGL((k_chain<T, 1, true>), g, blk, 0, s, work(b, PF_CHAIN));
-        else if (K == 2) hipLaunchKernelGGL((k_chain<T, 2, true>), g, blk, 0, s, work(b, PF_CHAIN));
-        else hipLaunchKernelGGL((k_chain<T, 4, true>), g, blk, 0, s, work(b, PF_CHAIN));
+        if (K == 1) hipLaunchKernelGGL((k_chain<T, 1, true, 0>), g, blk, 0, s, w);
+        else if (K == 2) hipLaunchKernelGGL((k_chain<T, 2, true, 0>), g, blk, 0, s, w);
+        else hipLaunchKernelGGL((k_chain<T, 4, true, 0>), g, blk, 0, s, w);
+        return last_launch("k_chain");
+    }
+    // colloid count common to every occupied slot: 1 or 2 have unrolled
+    // variants, anything else (or a mix) the generic one
+    const int nc = b->nc_common == 1 || b->nc_common == 2 ? b->nc_common : 0;
+    if (K == 1) {
+        if (nc == 2) hipLaunchKernelGGL((k_chain<T, 1, false, 2>), g, blk, 0, s, w);
+        else if (nc == 1) hipLaunchKernelGGL((k_chain<T, 1, false, 1>), g, blk, 0, s, w);
+        else hipLaunchKernelGGL((k_chain<T, 1, false, 0>), g, blk, 0, s, w);
+    } else if (K == 2) {
+        if (nc == 2) hipLaunchKernelGGL((k_chain<T, 2, false, 2>), g, blk, 0, s, w);
+        else if (nc == 1) hipLaunchKernelGGL((k_chain<T, 2, false, 1>), g, blk, 0, s, w);
+        else hipLaunchKernelGGL((k_chain<T, 2, false, 0>), g, blk, 0, s, w);
     } else {
-        if (K == 1) hipLaunchKernelGGL((k_chain<T, 1, false>), g, blk, 0, s, work(b, PF_CHAIN));
-        else if (K == 2) hipLaunchKernelGGL((k_chain<T, 2, false>), g, blk, 0, s, work(b, PF_CHAIN));
-        else hipLaunchKernelGGL((k_chain<T, 4, false>), g, blk, 0, s, work(b, PF_CHAIN));
+        if (nc == 2) hipLaunchKernelGGL((k_chain<T, 4, false, 2>), g, blk, 0, s, w);
+        else if (nc == 1) hipLaunchKernelGGL((k_chain<T, 4, false, 1>), g, blk, 0, s, w);
+        else hipLaunchKernelGGL((k_chain<T, 4, false, 0>), g, blk, 0, s, w);
     }
     return last_launch("k_chain");
 }
@@ -745,13 +769,13 @@ rmp_status batch_init(rmp_batch* b, int32_t nslots, int32_t precision, void* ctl
         HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         int per[3] = {0, 0, 0};
         if (precision == 64) {
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<double, 1, false>, CHAIN_BLOCK, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<double, 2, false>, CHAIN_BLOCK, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<double, 4, false>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<double, 1, false, 0>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<double, 2, false, 0>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<double, 4, false, 0>, CHAIN_BLOCK, 0));
         } else {
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<float, 1, false>, CHAIN_BLOCK, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<float, 2, false>, CHAIN_BLOCK, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<float, 4, false>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<float, 1, false, 0>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<float, 2, false, 0>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<float, 4, false, 0>, CHAIN_BLOCK, 0));
         }
         for (int q = 0; q < 3; ++q) b->chain_resident[q] = std::max(1, per[q]) * std::max(1, ncu);
     }

@@ -989,7 +989,7 @@ __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& 
     // after the workgroup barrier that follows the colloid position update
 }
 
-template <class T, int K>
+template <class T, int K, int NC>
 __device__ __forceinline__ void chain_run(Work w, int item)
 {
     const int rep = find_rep(w.prefix, w.nrep, item);
@@ -998,7 +998,9 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     if (!D.active) return;
     RepState* rs = D.rs;
     const ColloidParams* cp = D.cp;
-    const int nc = cp->nc;
+    // NC > 0: every system of the launch has NC colloids (loops over the
+    // colloids unrolled at compile time); NC == 0: read per system
+    const int nc = NC > 0 ? NC : cp->nc;
     constexpr int B = CHAIN_BLOCK * K;
     int64_t ncand = rs->n_cand;
     if (ncand > D.cand_cap) ncand = D.cand_cap;
@@ -1215,18 +1217,18 @@ __device__ __forceinline__ void chain_run(Work w, int item)
 // launch.  (The ticket is a separate instantiation because an atomic at
 // kernel entry keeps the descriptor loads of the whole kernel off the
 // scalar unit.)
-template <class T, int K, bool TICKET>
+template <class T, int K, bool TICKET, int NC>
 __global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
 {
     if (!TICKET) {
-        chain_run<T, K>(w, (int)blockIdx.x);
+        chain_run<T, K, NC>(w, (int)blockIdx.x);
         return;
     }
     __shared__ int s_item;
     if (threadIdx.x == 0)
         s_item = (int)__hip_atomic_fetch_add(&w.tick[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    chain_run<T, K>(w, s_item);
+    chain_run<T, K, NC>(w, s_item);
     if (threadIdx.x == 0) {
         const uint32_t fin = __hip_atomic_fetch_add(&w.tick[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (fin == gridDim.x - 1) {
@@ -1666,17 +1668,20 @@ __global__ __launch_bounds__(256) void k_observe(Work w)
 
 // ----------------------------------------------------- explicit instances
 
+#define RMP_CHAIN_INST(T, K)                                                     \
+    template __global__ void k_chain<T, K, false, 0>(Work);                      \
+    template __global__ void k_chain<T, K, false, 1>(Work);                      \
+    template __global__ void k_chain<T, K, false, 2>(Work);                      \
+    template __global__ void k_chain<T, K, true, 0>(Work);
+
 #define RMP_INST(T)                                                              \
     template __global__ void k_init<T>(const RepDesc*);                          \
     template __global__ void k_init_sub<T>(const RepDesc*, const double*);       \
     template __global__ void k_list<T>(Work);                                    \
     template __global__ void k_stream_bin<T>(Work, int);                         \
-    template __global__ void k_chain<T, 1, false>(Work);                         \
-    template __global__ void k_chain<T, 2, false>(Work);                         \
-    template __global__ void k_chain<T, 4, false>(Work);                         \
-    template __global__ void k_chain<T, 1, true>(Work);                          \
-    template __global__ void k_chain<T, 2, true>(Work);                          \
-    template __global__ void k_chain<T, 4, true>(Work);                          \
+    RMP_CHAIN_INST(T, 1)                                                         \
+    RMP_CHAIN_INST(T, 2)                                                         \
+    RMP_CHAIN_INST(T, 4)                                                         \
     template __global__ void k_collide<T, 0>(Work);                              \
     template __global__ void k_collide<T, 1>(Work);                              \
     template __global__ void k_observe<T>(Work);
