@@ -1312,6 +1312,23 @@ __global__ __launch_bounds__(256) void k_scatter(Work w)
 
 // ------------------------------------------------------------- collision
 
+// Add this lane's Verlet-list flag to the count of its chunk.  The active
+// lanes of the wave hold consecutive slots o, so they span at most two
+// chunks: one atomic per chunk and wave instead of one per flagged slot.
+__device__ __forceinline__ void count_flag(uint32_t* chunk_cnt, int64_t o, bool f)
+{
+    const int64_t ch = o / CHUNK;
+    const int64_t c_lo = (int64_t)__builtin_amdgcn_readfirstlane((int)ch);
+    const uint32_t n_lo = (uint32_t)__popcll(__ballot(f && ch == c_lo));
+    const uint32_t n_hi = (uint32_t)__popcll(__ballot(f && ch != c_lo));
+    const uint64_t act = __ballot(true);
+    const int leader = __ffsll((long long)act) - 1;
+    if ((int)(threadIdx.x & 63) == leader) {
+        if (n_lo) atomicAdd(&chunk_cnt[c_lo], n_lo);
+        if (n_hi) atomicAdd(&chunk_cnt[c_lo + 1], n_hi);
+    }
+}
+
 constexpr int COLL_NT = 256;
 constexpr int COLL_CAP = 1024;       // particles per LDS group
 constexpr int COLL_TCMAX = 64;       // cells per tile at most
@@ -1480,7 +1497,7 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
                 bool cnd = is_candidate(D, cp, nc, s_Xw, s, (double)xt[0], (double)xt[1], (double)xt[2],
                                         (double)vt[0], (double)vt[1], (double)vt[2]);
                 D.cflag[o] = cnd ? 1 : 0;
-                if (cnd) atomicAdd(&D.chunk_cnt[o / CHUNK], 1u);
+                count_flag(D.chunk_cnt, o, cnd);
             }
             __syncthreads();
             ga = gb;
@@ -1618,7 +1635,7 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
             bool cnd = is_candidate(D, cp, nc, s_Xw, s, (double)xt[0], (double)xt[1], (double)xt[2],
                                     (double)vt[0], (double)vt[1], (double)vt[2]);
             D.cflag[o] = cnd ? 1 : 0;
-            if (cnd) atomicAdd(&D.chunk_cnt[o / CHUNK], 1u);
+            count_flag(D.chunk_cnt, o, cnd);
         }
         __syncthreads();
         ga = gb;
