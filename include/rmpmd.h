@@ -161,11 +161,13 @@ rmp_status rmp_destroy(rmp_system* s);
 
 /* Per-kernel launch parameters (autotuning).  A negative field keeps its
  * current value; so does 0, except for use_graph and chain_resident, where 0
- * is a value.  Applies to the next rmp_step / rmp_batch_step. */
+ * is a value (collide_cells is 0 until set).  Applies to the next rmp_step /
+ * rmp_batch_step. */
 typedef struct rmp_tuning {
     int32_t stream_block;      /* threads per workgroup, particle kernels       */
     int32_t stream_ppt;        /* particles per thread in the streaming kernel  */
-    int32_t collide_cells;     /* cells per collision tile (power of two)       */
+    int32_t collide_cells;     /* cells per collision tile (power of two; 0:
+                                  by box size, the default)                     */
     int32_t chain_k;           /* Verlet-list entries per thread (1, 2 or 4)    */
     int32_t use_graph;         /* 1: replay a captured hipGraph per interval    */
     int32_t chain_resident;    /* chain workgroups taken to fit on the device at

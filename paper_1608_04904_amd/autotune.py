@@ -16,7 +16,7 @@ import os
 import time
 
 GRID = dict(chain_k=(1, 2, 4), collide_cells=(16, 32, 64), stream_block=(128, 256))
-DEFAULT = dict(chain_k=1, collide_cells=32, stream_block=256, stream_ppt=1)
+DEFAULT = dict(chain_k=1, collide_cells=0, stream_block=256, stream_ppt=1)   # collide_cells 0: by box size
 
 
 def default_cache_path() -> str:

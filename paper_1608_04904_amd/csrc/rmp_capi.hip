@@ -196,7 +196,7 @@ struct rmp_batch {
     bool dirty = true;
     bool have_rule[2] = {false, false};
     bool multi_scan = false;
-    rmp_tuning tun{256, 1, 32, 1, 1, 0};
+    rmp_tuning tun{256, 1, 0, 1, 1, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
@@ -278,9 +278,13 @@ int chain_k_of(const rmp_batch* b)
     return k;
 }
 
-int tile_cells_of(const rmp_batch* b, int override_cells = 0)
+// Cells per collision tile: the slot's override, else the batch tuning,
+// else by box size (measured: 32 cells for boxes up to 2^20 cells, 64 above,
+// where more particles per workgroup keep more gathers in flight)
+int tile_cells_of(const rmp_batch* b, int override_cells, int64_t ncell)
 {
     int tc = override_cells > 0 ? override_cells : b->tun.collide_cells;
+    if (tc <= 0) tc = ncell >= ((int64_t)1 << 20) ? 64 : 32;
     if (tc < MIN_TILE_CELLS) tc = MIN_TILE_CELLS;
     if (tc > COLL_TCMAX) tc = COLL_TCMAX;
     int p2 = MIN_TILE_CELLS;
@@ -307,7 +311,7 @@ void fill_desc(rmp_batch* b, Replica& r)
     D.n_md = r.n_md;
     D.rule = p->rule;
     D.n_chunks = s.n_chunks;
-    D.tile_cells = tile_cells_of(b, r.tile_cells);
+    D.tile_cells = tile_cells_of(b, r.tile_cells, s.ncell);
     D.n_tiles = (int32_t)((s.ncell + D.tile_cells - 1) / D.tile_cells);
     D.n_scanblk = s.n_scanblk;
     D.cand_cap = s.cand_cap;

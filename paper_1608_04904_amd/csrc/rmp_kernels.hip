@@ -709,8 +709,10 @@ __device__ __forceinline__ void chain_compute(ChainCtx<T, K>& S, const RepDesc& 
     // of each thread, then the wave trees of the six components (and, after
     // the last pair, of the potential) side by side
     constexpr int CB = 2;
+    bool hit_any = false;        // some entry of this wave hit some colloid so far
     for (int c0 = 0; c0 < nc; c0 += CB) {
         double tv[3 * CB + 1];
+        bool hit_chunk = false;  // ... one of this pair of colloids
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             const int c = c0 + cb;
@@ -739,6 +741,7 @@ __device__ __forceinline__ void chain_compute(ChainCtx<T, K>& S, const RepDesc& 
                 gx[j] = 0.0; gy[j] = 0.0; gz[j] = 0.0;
             }
             if (__ballot(any) != 0) {
+                hit_chunk = true;
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     double coef, pot;
@@ -777,7 +780,10 @@ __device__ __forceinline__ void chain_compute(ChainCtx<T, K>& S, const RepDesc& 
                 for (int j = 0; j + s2 < K; j += 2 * s2) a[j] = a[j] + a[j + s2];
             tv[3 * CB] = a[0];
         }
-        wave_tree_sum_n<3 * CB + 1>(tv);
+        hit_any = hit_any || hit_chunk;
+        // no entry of the wave inside either colloid's cut-off (and, for the
+        // potential, inside any): every value is +0.0, and so is its tree
+        if (hit_chunk || (last && hit_any)) wave_tree_sum_n<3 * CB + 1>(tv);
         if (lane == 0) {
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
@@ -846,7 +852,7 @@ __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0
     // does not wait on later ones, so a kernel whose peers cannot all run
     // ends within about one time budget (wall_clock64 counts at 100 MHz)
     const uint64_t t_start = wall_clock64();
-    int nap = 1;
+    int nap = 0;
     while (true) {
         uint64_t wl[VB][QM], wh[VB][QM];
 #pragma unroll
@@ -886,9 +892,8 @@ __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0
             if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
             break;
         }
-        // exponential back-off (64 to 512 clocks) for longer waits
-        for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(1);
-        nap = nap < 8 ? 2 * nap : 8;
+        // a long wait backs off (128 clocks a round after the first 16)
+        if (++nap > 16) __builtin_amdgcn_s_sleep(2);
     }
 #pragma unroll
     for (int vb = 0; vb < VB; ++vb) {
@@ -908,10 +913,17 @@ __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0
 // most 8 values and 64 workgroups (one workgroup per lane) wave 0 does all
 // of it alone, and the other waves go straight on; otherwise every wave
 // collects a share of the values and the workgroup meets at a barrier.
+// Constants of the colloid of lane c (c < nc) used by the pair forces,
+// loaded once per interval
+struct PairLane {
+    int partner, ctype;
+    double sigma;
+};
+
 template <class T, int K>
 __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& D, const ColloidParams* cp,
                               int nc, int Gact, int Gpad, uint32_t nbar, uint32_t epoch0,
-                              bool want_potential, double (&cF)[3])
+                              bool want_potential, double (&cF)[3], const PairLane& PL)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nv = 3 * nc + 1;
@@ -949,19 +961,27 @@ __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& 
         const int c = t;
         double F[3] = {-S.sNode[3 * c + 0], -S.sNode[3 * c + 1], -S.sNode[3 * c + 2]};
         for (int a = 0; a < nc; ++a) {
-            if (a == c || cp->partner[c] == a) continue;
-            const int lo = a < c ? a : c, hi = a < c ? c : a;
+            if (a == c || PL.partner == a) continue;
+            // colloid a's constants by its (uniform) index, this lane's from
+            // registers; operands in the pair's (lo, hi) order
+            const double sig_a = cp->sigma[a];
+            const int ct_a = cp->ctype[a];
+            const bool c_lo = c < a;
+            const int lo = c_lo ? c : a, hi = c_lo ? a : c;
             double dx = min_image(S.sXw[lo][0] - S.sXw[hi][0], D.Ld[0], D.halfL[0]);
             double dy = min_image(S.sXw[lo][1] - S.sXw[hi][1], D.Ld[1], D.halfL[1]);
             double dz = min_image(S.sXw[lo][2] - S.sXw[hi][2], D.Ld[2], D.halfL[2]);
             double r2 = dot3(dx, dy, dz, dx, dy, dz);
-            double sab = cp->sigma[lo] + cp->sigma[hi];
+            double sab = c_lo ? PL.sigma + sig_a : sig_a + PL.sigma;
             double rc = 0x1.1f59ac3c7d6c0p+0 * sab;
             if (r2 < rc * rc) {
+                const int t_lo = c_lo ? PL.ctype : ct_a, t_hi = c_lo ? ct_a : PL.ctype;
+                const double e_lo0 = t_lo == 0 ? cp->eps_cc[0][0] : cp->eps_cc[1][0];
+                const double e_lo1 = t_lo == 0 ? cp->eps_cc[0][1] : cp->eps_cc[1][1];
                 double coef, pot;
-                wca(r2, sab * sab, cp->eps_cc[cp->ctype[lo]][cp->ctype[hi]], coef, pot);
+                wca(r2, sab * sab, t_hi == 0 ? e_lo0 : e_lo1, coef, pot);
                 double g3[3] = {coef * dx, coef * dy, coef * dz};
-                for (int d = 0; d < 3; ++d) F[d] = (c == lo) ? F[d] + g3[d] : F[d] - g3[d];
+                for (int d = 0; d < 3; ++d) F[d] = c_lo ? F[d] + g3[d] : F[d] - g3[d];
             }
         }
         for (int d = 0; d < 3; ++d) cF[d] = F[d];
@@ -1019,6 +1039,10 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     double cX[3] = {0.0, 0.0, 0.0}, cV[3] = {0.0, 0.0, 0.0}, cF[3] = {0.0, 0.0, 0.0};
     double cX0[3] = {0.0, 0.0, 0.0};
     const BondLane BL = bond_lane(cp, nc);
+    PairLane PL;
+    PL.partner = t < nc ? cp->partner[t] : -1;
+    PL.ctype = t < nc ? cp->ctype[t] : 0;
+    PL.sigma = t < nc ? cp->sigma[t] : 0.0;
     const double chc = t < nc ? cp->hc[t] : 0.0;
     if (t < nc) {
         for (int d = 0; d < 3; ++d) {
@@ -1069,7 +1093,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
 
     // forces at the start of the interval
     chain_compute<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
-    chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, false, cF);
+    chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, false, cF, PL);
     // list entries: first half kick and drift of step 0
 #pragma unroll
     for (int j = 0; j < K; ++j)
@@ -1147,7 +1171,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
                 }
         }
         // the potential energy is an observable of the last force evaluation
-        chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF);
+        chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF, PL);
         // colloids (wave 0, in registers): second half kick, RATTLE
         // velocity stage, Verlet-list soundness check (displacement within
         // the interval)
