@@ -132,6 +132,75 @@ def cpu_baseline(p, n_md, seed, budget_s: float):
                        f"({p['n_solvent']} particles), {dt:.1f} s")
 
 
+def fp32_drift(intervals: int, oracle_intervals: int, with_oracle: bool):
+    """FP32 state against FP64 from the same initial state (dimer32): total
+    momentum P = sum m v (solvent and colloids, conserved exactly by the
+    method), total energy E = KE + U - e_rxn (e_rxn: potential change booked
+    at species flips), and the dimer centre-of-mass displacement.  The FP64
+    run is checked bit for bit against the CPU oracle over the first
+    `oracle_intervals` intervals, so it stands for the oracle trajectory."""
+    import numpy as np
+    import torch
+    import paper_1608_04904_amd as rm
+    import workloads as W
+    p64 = W.dimer32(precision=64)
+    p32 = W.dimer32(precision=32)
+    n_md = int(p64["n_md"])
+    seed = W.BASE_SEED + 77
+    st0 = W.random_state(p64, seed)
+    runs = {}
+    for prec, p in ((64, p64), (32, p32)):
+        s = rm.System(p, seed)
+        s.set_state(st0)
+        P, E, R = [], [], []
+        for k in range(intervals + 1):
+            if k:
+                s.step(n_md, 1)
+            o = s.observables(raise_on_flags=False)
+            P.append(np.array(o["momentum"]))
+            E.append(o["ke_solvent"] + o["ke_colloid"] + o["potential"] - o["e_rxn"])
+            X = np.array(o["colloid_X"])
+            R.append(X.mean(axis=0))
+        torch.cuda.synchronize()
+        runs[prec] = dict(P=np.array(P), E=np.array(E), R=np.array(R), flags=o["flags"])
+        if prec == 64 and with_oracle:
+            import oracle
+            g = rm.System(p, seed)
+            g.set_state(st0)
+            g.step(n_md, oracle_intervals)
+            oc = oracle.Oracle(p, seed, init=False)
+            oc.set_state(st0)
+            oc.run(n_md, oracle_intervals)
+            gs, os_ = g.get_state(), oc.get_state()
+            runs[64]["oracle_equal"] = all(np.array_equal(np.asarray(gs[k]), np.asarray(os_[k]))
+                                          for k in ("id", "state", "x", "v", "X", "V"))
+            g.close()
+        s.close()
+    r64, r32 = runs[64], runs[32]
+    n = p64["n_solvent"]
+    pscale = float(np.sqrt(n * p64["mass"] * p64["kT"]))     # thermal momentum of the system
+    e0 = float(r64["E"][0])
+    msd64 = float(np.sum((r64["R"][-1] - r64["R"][0]) ** 2))
+    msd32 = float(np.sum((r32["R"][-1] - r32["R"][0]) ** 2))
+    out = dict(
+        intervals=intervals, md_steps=intervals * n_md,
+        momentum_drift_fp64=float(np.max(np.linalg.norm(r64["P"] - r64["P"][0], axis=1)) / pscale),
+        momentum_drift_fp32=float(np.max(np.linalg.norm(r32["P"] - r32["P"][0], axis=1)) / pscale),
+        energy_drift_fp64=float(np.max(np.abs(r64["E"] - e0)) / abs(e0)),
+        energy_drift_fp32=float(np.max(np.abs(r32["E"] - r32["E"][0])) / abs(e0)),
+        energy_fp32_vs_fp64=float(np.max(np.abs(r32["E"] - r64["E"])) / abs(e0)),
+        dimer_msd_fp64=msd64, dimer_msd_fp32=msd32,
+        # the two trajectories decorrelate (the dynamics is chaotic): distance
+        # between the FP32 and FP64 dimer centres after k intervals
+        dimer_com_diff={str(k): float(np.linalg.norm(r32["R"][k] - r64["R"][k]))
+                        for k in (1, 2, 5, 10, 20, 50, 100, 200) if k <= intervals},
+        flags=[int(r64["flags"]), int(r32["flags"])],
+        note="momentum drifts are max_t |P(t) - P(0)| / sqrt(N m kT); energy drifts max_t |E(t) - E(0)| / E(0)")
+    if "oracle_equal" in r64:
+        out["fp64_bitwise_equal_to_oracle"] = dict(intervals=oracle_intervals, equal=bool(r64["oracle_equal"]))
+    return out
+
+
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -329,6 +398,8 @@ def main():
                 value=r["value"], roofline=r["roofline"],
                 kernels={k: r["kernels"][k] for k in ("stream_bin", "collide", "chain")
                          if k in r["kernels"]})
+        _log("FP32 against FP64 drift, dimer32")
+        extras["fp32_drift"] = fp32_drift(200, 3, not args.no_cpu)
     cpu = None
     if not args.no_cpu:
         _log("timing the CPU oracle")

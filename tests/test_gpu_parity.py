@@ -347,3 +347,33 @@ def test_batch_chain_waves_match_resident_launch_and_oracle():
         o.set_state(states[i])
         o.run(ps[i]["n_md"], 1)
         _assert_bitwise(out["waves"][i], o.get_state(), f"replica {i} vs oracle")
+
+
+def test_fp32_drift_against_fp64_is_bounded():
+    """FP32 state against FP64 (the oracle's trajectory, bitwise) from one
+    initial state, 20 intervals of a 16^3 dimer system: total momentum, which
+    the method conserves exactly, drifts by rounding only (FP64 to 1e-12,
+    FP32 to 1e-5 of the thermal momentum sqrt(N m kT)); the total energy
+    KE + U - e_rxn of the two forms agrees to 1e-4 relative."""
+    rm = _rm()
+    p64 = W.dimer_system(L=16, rho=10, n_md=50, seed=5, bulk_rate=0.01)
+    p32 = dict(p64, precision=32)
+    st0 = W.random_state(p64, 91)
+    out = {}
+    for prec, p in ((64, p64), (32, p32)):
+        s = rm.System(p, 17)
+        s.set_state(st0)
+        P, E = [], []
+        for k in range(21):
+            if k:
+                s.step(p["n_md"], 1)
+            o = s.observables()
+            P.append(np.array(o["momentum"]))
+            E.append(o["ke_solvent"] + o["ke_colloid"] + o["potential"] - o["e_rxn"])
+        out[prec] = (np.array(P), np.array(E))
+    scale = math.sqrt(p64["n_solvent"] * p64["mass"] * p64["kT"])
+    P64, E64 = out[64]
+    P32, E32 = out[32]
+    assert np.max(np.linalg.norm(P64 - P64[0], axis=1)) / scale < 1e-12
+    assert np.max(np.linalg.norm(P32 - P32[0], axis=1)) / scale < 1e-5
+    assert np.max(np.abs(E32 - E64)) / abs(E64[0]) < 1e-4
