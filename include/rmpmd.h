@@ -90,6 +90,12 @@ typedef struct rmp_params {
     int32_t bond_a[RMP_MAX_COLLOIDS];
     int32_t bond_b[RMP_MAX_COLLOIDS];
     double  bond_d[RMP_MAX_COLLOIDS];
+    int32_t cell_order;        /* order of cells in the sorted particle arrays:
+                                  0 row-major (x fastest); 1 compact Hilbert (the
+                                  box's cells along the Hilbert curve of the
+                                  enclosing power-of-two cube, "Implementation
+                                  and architecture": cell sorting)              */
+    int32_t pad_order;
 } rmp_params;
 
 /* FP64 observables.  `potential` is the colloid-solvent plus colloid-colloid

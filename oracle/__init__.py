@@ -46,7 +46,7 @@ class Params(C.Structure):
         ("epsB", C.c_double * MAXC), ("catalytic", C.c_int32 * MAXC),
         ("ctype", C.c_int32 * MAXC), ("eps_cc", (C.c_double * 2) * 2),
         ("bond_a", C.c_int32 * MAXC), ("bond_b", C.c_int32 * MAXC),
-        ("bond_d", C.c_double * MAXC),
+        ("bond_d", C.c_double * MAXC), ("cell_order", C.c_int32), ("pad", C.c_int32),
     ]
 
 
@@ -91,6 +91,10 @@ def lib():
         L.orc_shift.argtypes = [P, I64, P]
         L.orc_last_cells.restype = I64
         L.orc_last_cells.argtypes = [P, P, I64]
+        L.orc_cell_ranks.restype = I64
+        L.orc_cell_ranks.argtypes = [P, P, I64]
+        L.orc_hilbert.restype = U64
+        L.orc_hilbert.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
         L.orc_philox.argtypes = [P, P, P]
         L.orc_wca.argtypes = [D, D, D, C.POINTER(D), C.POINTER(D)]
         L.orc_tree_sum.restype = D
@@ -111,6 +115,7 @@ def make_params(p: dict) -> Params:
     for d in range(3):
         q.L[d] = int(p["L"][d])
     q.rule = {"srd": 0, "at": 1}[p.get("rule", "srd")]
+    q.cell_order = {"row": 0, "hilbert": 1}[p.get("cell_order", "row")]
     q.n_solvent = int(p["n_solvent"])
     q.kT, q.mass, q.dt = p["kT"], p["mass"], p["dt"]
     q.alpha, q.skin = p["alpha"], p["skin"]
@@ -158,6 +163,11 @@ def marsaglia(seed: int, coll_step: int, cell: int) -> np.ndarray:
     n = np.zeros(3)
     lib().orc_marsaglia(seed, coll_step, cell, _ptr(n))
     return n
+
+
+def hilbert(x: int, y: int, z: int, bits: int) -> int:
+    """Index of (x, y, z) along the Hilbert curve of the 2^bits cube."""
+    return int(lib().orc_hilbert(int(x), int(y), int(z), int(bits)))
 
 
 def rotate(n, alpha: float, w) -> np.ndarray:
@@ -267,6 +277,14 @@ class Oracle:
         k = np.zeros(self.n, dtype=np.uint32)
         lib().orc_cell_keys(self.h, _ptr(sh), _ptr(k))
         return k
+
+    def cell_ranks(self) -> np.ndarray:
+        """Sort rank of every cell (linear cell index -> position in the
+        Hilbert cell order)."""
+        m = lib().orc_cell_ranks(self.h, None, 0)
+        a = np.zeros(m, dtype=np.uint32)
+        lib().orc_cell_ranks(self.h, _ptr(a), m)
+        return a
 
     def last_cells(self) -> np.ndarray:
         m = lib().orc_last_cells(self.h, None, 0)

@@ -137,7 +137,9 @@ struct orc_system {
     uint8_t* inside;          /* [cap] inside a catalytic colloid's range */
     /* scratch for the sort */
     uint32_t* keys;
-    uint32_t* start;          /* [ncell+1] of the last collision */
+    uint32_t* start;          /* [ncell+1] of the last collision, by sort rank */
+    uint32_t* rank_of;        /* [ncell] sort rank of a cell (Hilbert order)  */
+    uint32_t* cell_of;        /* [ncell] cell of a sort rank                  */
     int64_t ncell;
     double *tx[3], *tv[3];
     uint32_t* tid;
@@ -177,9 +179,81 @@ static double wrapX(double X, double L)
 
 static void *xalloc(size_t n) { void* q = calloc(n ? n : 1, 1); return q; }
 
+/* Position of the point (x, y, z) along the Hilbert curve through the
+ * 2^bits cube (J. Skilling, "Programming the Hilbert curve", AIP Conf. Proc.
+ * 707 (2004) 381): the coordinates are turned into the curve's "transpose"
+ * form by undoing the excess work (for each level Q from the top: invert the
+ * low bits of the first coordinate where a coordinate's Q bit is set, else
+ * exchange the low bits of the first coordinate and that one), then Gray
+ * encoding; the index takes one bit from each coordinate per level, first
+ * coordinate most significant. */
+uint64_t orc_hilbert(uint32_t x, uint32_t y, uint32_t z, int bits)
+{
+    uint32_t X[3] = { x, y, z };
+    if (bits <= 0) return 0;
+    const uint32_t top = 1u << (bits - 1);
+    for (uint32_t Q = top; Q > 1; Q >>= 1) {
+        const uint32_t low = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= low;
+            } else {
+                uint32_t t = (X[0] ^ X[i]) & low;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t g = 0;
+    for (uint32_t Q = top; Q > 1; Q >>= 1)
+        if (X[2] & Q) g ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= g;
+    uint64_t h = 0;
+    for (int b = bits - 1; b >= 0; --b)
+        for (int i = 0; i < 3; ++i) h = (h << 1) | ((X[i] >> b) & 1u);
+    return h;
+}
+
+/* Sort order of the cells when the compact-Hilbert ordering of the paper's
+ * cell sort is selected, read as: cells of the box ranked by their position
+ * along the Hilbert curve of the smallest power-of-two cube that contains the
+ * box.  The default order is row-major (rank = cell index). */
+static int cmp_u64_pair(const void* a, const void* b)
+{
+    const uint64_t* p = (const uint64_t*)a;
+    const uint64_t* q = (const uint64_t*)b;
+    return p[0] < q[0] ? -1 : (p[0] > q[0] ? 1 : 0);
+}
+
+static void hilbert_order(const int32_t L[3], uint32_t* rank_of, uint32_t* cell_of)
+{
+    int bits = 0;
+    int32_t m = L[0] > L[1] ? L[0] : L[1];
+    if (L[2] > m) m = L[2];
+    while ((1 << bits) < m) bits++;
+    const int64_t ncell = (int64_t)L[0] * L[1] * L[2];
+    uint64_t* pairs = (uint64_t*)xalloc(sizeof(uint64_t) * 2 * ncell);
+    for (int64_t c = 0; c < ncell; ++c) {
+        const uint32_t x = (uint32_t)(c % L[0]);
+        const uint32_t y = (uint32_t)((c / L[0]) % L[1]);
+        const uint32_t z = (uint32_t)(c / ((int64_t)L[0] * L[1]));
+        pairs[2 * c] = orc_hilbert(x, y, z, bits);
+        pairs[2 * c + 1] = (uint64_t)c;
+    }
+    qsort(pairs, (size_t)ncell, 2 * sizeof(uint64_t), cmp_u64_pair);
+    for (int64_t r = 0; r < ncell; ++r) {
+        cell_of[r] = (uint32_t)pairs[2 * r + 1];
+        rank_of[pairs[2 * r + 1]] = (uint32_t)r;
+    }
+    free(pairs);
+}
+
 orc_system* orc_create(const orc_params* p, uint64_t seed)
 {
     if (p->L[0] < 1 || p->L[1] < 1 || p->L[2] < 1 || p->n_solvent < 0 ||
+        (p->cell_order != 0 && p->cell_order != 1) ||
         p->n_colloids < 0 || p->n_colloids > ORC_MAXC || p->dt <= 0.0 || p->mass <= 0.0)
         return NULL;
     orc_system* s = (orc_system*)xalloc(sizeof(orc_system));
@@ -202,6 +276,13 @@ orc_system* orc_create(const orc_params* p, uint64_t seed)
     s->keys = (uint32_t*)xalloc(sizeof(uint32_t) * s->n);
     s->ncell = (int64_t)p->L[0] * p->L[1] * p->L[2];
     s->start = (uint32_t*)xalloc(sizeof(uint32_t) * (s->ncell + 1));
+    s->rank_of = (uint32_t*)xalloc(sizeof(uint32_t) * s->ncell);
+    s->cell_of = (uint32_t*)xalloc(sizeof(uint32_t) * s->ncell);
+    if (p->cell_order == 1) {
+        hilbert_order(p->L, s->rank_of, s->cell_of);
+    } else {
+        for (int64_t c = 0; c < s->ncell; ++c) { s->rank_of[c] = (uint32_t)c; s->cell_of[c] = (uint32_t)c; }
+    }
     s->nc = p->n_colloids;
     s->h = (0.5 * p->dt) / p->mass;
     s->ca = cos(p->alpha);
@@ -226,6 +307,7 @@ void orc_destroy(orc_system* s)
     if (!s) return;
     for (int d = 0; d < 3; ++d) { free(s->x[d]); free(s->v[d]); free(s->f[d]); free(s->tx[d]); free(s->tv[d]); }
     free(s->id); free(s->st); free(s->tid); free(s->tst); free(s->keys); free(s->start);
+    free(s->rank_of); free(s->cell_of);
     free(s->idx); free(s->contrib); free(s->upart); free(s->inside);
     free(s);
 }
@@ -688,14 +770,15 @@ static void collide(orc_system* s, int32_t n_md)
     double shift[3];
     orc_shift(s, s->coll_step, shift);
     orc_cell_keys(s, shift, s->keys);
-    /* stable counting sort by key (cell_system / particle_system sorting) */
+    /* stable counting sort by the cell's rank in the Hilbert order
+     * (cell_system / particle_system sorting with the compact-Hilbert key) */
     uint32_t* cnt = (uint32_t*)xalloc(sizeof(uint32_t) * (ncell + 1));
-    for (int64_t i = 0; i < n; ++i) cnt[s->keys[i]]++;
+    for (int64_t i = 0; i < n; ++i) cnt[s->rank_of[s->keys[i]]]++;
     s->start[0] = 0;
-    for (int64_t c = 0; c < ncell; ++c) s->start[c + 1] = s->start[c] + cnt[c];
-    for (int64_t c = 0; c < ncell; ++c) cnt[c] = s->start[c];
+    for (int64_t r = 0; r < ncell; ++r) s->start[r + 1] = s->start[r] + cnt[r];
+    for (int64_t r = 0; r < ncell; ++r) cnt[r] = s->start[r];
     for (int64_t i = 0; i < n; ++i) {
-        int64_t j = cnt[s->keys[i]]++;
+        int64_t j = cnt[s->rank_of[s->keys[i]]]++;
         for (int d = 0; d < 3; ++d) { s->tx[d][j] = s->x[d][i]; s->tv[d][j] = s->v[d][i]; }
         s->tid[j] = s->id[i];
         s->tst[j] = s->st[i];
@@ -716,9 +799,12 @@ static void collide(orc_system* s, int32_t n_md)
     double* erx = (double*)xalloc(sizeof(double) * (ncell ? ncell : 1));
     uint8_t* flipped = (uint8_t*)xalloc(ncell ? ncell : 1);
     const double sc = sqrt(s->p.kT / s->p.mass);
+    /* cells in sort order: rank r holds the particles of cell c = cell_of[r];
+     * per-cell random streams are keyed by the cell c */
     #pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t c = 0; c < ncell; ++c) {
-        int64_t b = s->start[c], e = s->start[c + 1];
+    for (int64_t r = 0; r < ncell; ++r) {
+        const int64_t c = s->cell_of[r];
+        int64_t b = s->start[r], e = s->start[r + 1];
         int64_t nn = e - b;
         tterm[c] = 0.0;
         if (nn >= 2) {
@@ -792,7 +878,8 @@ static void collide(orc_system* s, int32_t n_md)
     double T = 0.0;
     int64_t ncT = 0;
     for (int64_t c = 0; c < ncell; ++c) {
-        int64_t nn = (int64_t)s->start[c + 1] - s->start[c];
+        const int64_t r = s->rank_of[c];
+        int64_t nn = (int64_t)s->start[r + 1] - s->start[r];
         if (nn >= 2) { T = T + tterm[c]; ncT++; }
         if (flipped[c]) { s->n_bulk++; s->e_rxn += erx[c]; }
     }
@@ -895,6 +982,13 @@ void orc_forces_allpairs(orc_system* s, double* f, double* F)
         }
         f[i] = fx; f[s->n + i] = fy; f[2 * s->n + i] = fz;
     }
+}
+
+int64_t orc_cell_ranks(const orc_system* s, uint32_t* rank_of, int64_t cap)
+{
+    int64_t m = s->ncell < cap ? s->ncell : cap;
+    if (rank_of) memcpy(rank_of, s->rank_of, sizeof(uint32_t) * m);
+    return s->ncell;
 }
 
 int64_t orc_last_cells(const orc_system* s, uint32_t* start, int64_t cap)

@@ -55,6 +55,8 @@ typedef struct orc_params {
     int32_t bond_a[ORC_MAXC];
     int32_t bond_b[ORC_MAXC];
     double  bond_d[ORC_MAXC];
+    int32_t cell_order;      /* 0 row-major cell order, 1 compact Hilbert       */
+    int32_t pad;
 } orc_params;
 
 typedef struct orc_obs {
@@ -102,7 +104,9 @@ int         orc_build_list(orc_system* s, int32_t n_md);            /* list + fo
 void        orc_forces_allpairs(orc_system* s, double* f, double* F);/* 3N, 3*nc */
 void        orc_cell_keys(const orc_system* s, const double shift[3], uint32_t* keys);
 void        orc_shift(const orc_system* s, int64_t coll_step, double shift[3]);
-int64_t     orc_last_cells(const orc_system* s, uint32_t* start, int64_t cap);
+int64_t     orc_last_cells(const orc_system* s, uint32_t* start, int64_t cap); /* by sort rank */
+int64_t     orc_cell_ranks(const orc_system* s, uint32_t* rank_of, int64_t cap);
+uint64_t    orc_hilbert(uint32_t x, uint32_t y, uint32_t z, int bits);
 void        orc_marsaglia(uint64_t seed, int64_t coll_step, int64_t cell, double n[3]);
 void        orc_rotate(const double n[3], double ca, double sa, const double w[3], double out[3]);
 void        orc_ptable(double bulk_rate, double tau, double* table);

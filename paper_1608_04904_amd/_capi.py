@@ -33,7 +33,10 @@ class Params(C.Structure):
         ("catalytic", C.c_int32 * MAX_COLLOIDS), ("ctype", C.c_int32 * MAX_COLLOIDS),
         ("eps_cc", (C.c_double * 2) * 2), ("bond_a", C.c_int32 * MAX_COLLOIDS),
         ("bond_b", C.c_int32 * MAX_COLLOIDS), ("bond_d", C.c_double * MAX_COLLOIDS),
+        ("cell_order", C.c_int32), ("pad_order", C.c_int32),
     ]
+
+CELL_ORDERS = {"row": 0, "hilbert": 1}
 
 
 class Obs(C.Structure):
@@ -140,6 +143,7 @@ def make_params(p: dict) -> Params:
     q.cat_prob, q.bulk_rate = float(p["cat_prob"]), float(p["bulk_rate"])
     q.rule = {"srd": 0, "at": 1}[p.get("rule", "srd")]
     q.cand_capacity = int(p.get("cand_capacity", 0))
+    q.cell_order = CELL_ORDERS[p.get("cell_order", "row")]
     cols = p["colloids"]
     if len(cols) > MAX_COLLOIDS:
         raise ValueError("too many colloids")

@@ -67,6 +67,7 @@ rmp_status validate(const rmp_params* p)
     if (p->rule != 0 && p->rule != 1) return RMP_EINVAL;
     if (p->n_colloids < 0 || p->n_colloids > RMP_MAX_COLLOIDS) return RMP_EINVAL;
     if (p->n_bonds < 0 || p->n_bonds > RMP_MAX_COLLOIDS / 2) return RMP_EINVAL;
+    if (p->cell_order != 0 && p->cell_order != 1) return RMP_EINVAL;
     if (p->cand_capacity < 0) return RMP_EINVAL;
     int used[RMP_MAX_COLLOIDS] = {0};
     for (int c = 0; c < p->n_colloids; ++c) {
@@ -111,7 +112,7 @@ Sizes sizes_of(const rmp_params* p)
 // offsets of every array inside a replica workspace
 struct Layout {
     size_t cp, rs, x[2], v[2], id[2], st[2], keyrank, perm, cflag, count, start, scanblk,
-        chunk_cnt, chunk_off, cand_idx, partials, epart, tpart, ptable, obs_part, mean, total;
+        chunk_cnt, chunk_off, cand_idx, order, partials, epart, tpart, ptable, obs_part, mean, total;
 };
 
 Layout layout_of(const rmp_params* p)
@@ -138,6 +139,7 @@ Layout layout_of(const rmp_params* p)
     L.chunk_cnt = take(4 * (size_t)s.n_chunks);
     L.chunk_off = take(4 * (size_t)s.n_chunks);
     L.cand_idx = take(4 * (size_t)s.cand_cap);
+    L.order = take(2 * 4 * (size_t)s.ncell);
     L.partials = take(2 * (size_t)s.G * NVAL_MAX * 2 * 8);
     L.epart = take((size_t)s.G * 2 * 8);
     L.tpart = take((size_t)s.n_tiles_max * 4 * 8);
@@ -170,6 +172,7 @@ struct Replica {
     bool list_valid = false;
     int32_t list_nmd = -1;
     std::vector<double> ptable;
+    std::vector<uint32_t> order;   // host copy of the cell order tables (rank of cell, cell of rank)
     int32_t ptable_nmd = -1;
     int32_t tile_cells = 0;    // per-replica override of the collision tile size
 };
@@ -322,6 +325,14 @@ void fill_desc(rmp_batch* b, Replica& r)
     D.G = G;
     D.cand_cap = std::min<int64_t>(s.cand_cap, (int64_t)G * CHAIN_BLOCK * K);
     D.chain_k = K;
+    {
+        // row-major: rank = cell index (KEY_ROW); compact Hilbert: computed in
+        // the kernels for a cubic power-of-two box, else the table
+        int bits = 0;
+        while ((1 << bits) < p->L[0]) bits++;
+        const bool cube2 = p->L[0] == p->L[1] && p->L[1] == p->L[2] && (1 << bits) == p->L[0];
+        D.hbits = p->cell_order == 0 ? KEY_ROW : (cube2 ? bits : KEY_TABLE);
+    }
     D.dt = p->dt;
     D.h = (0.5 * p->dt) / p->mass;
     D.tau = (double)r.n_md * p->dt;
@@ -348,6 +359,8 @@ void fill_desc(rmp_batch* b, Replica& r)
     D.chunk_cnt = (uint32_t*)(w + L.chunk_cnt);
     D.chunk_off = (uint32_t*)(w + L.chunk_off);
     D.cand_idx = (uint32_t*)(w + L.cand_idx);
+    D.rank_of = (const uint32_t*)(w + L.order);
+    D.cell_of = (const uint32_t*)(w + L.order) + s.ncell;
     D.partials = (double*)(w + L.partials);
     D.epart = (double*)(w + L.epart);
     D.tpart = (double*)(w + L.tpart);
@@ -390,6 +403,65 @@ ColloidParams make_cp(const rmp_params* p)
         c.bond_of[p->bond_b[b]] = b;
     }
     return c;
+}
+
+// Hilbert curve (J. Skilling, "Programming the Hilbert curve", AIP Conf.
+// Proc. 707 (2004) 381), from the index to the point: the index's bits are
+// dealt to the three axes level by level (first axis most significant), the
+// Gray code is undone, then the excess work of the forward transform is
+// undone from the lowest level up (invert or exchange low bits with the
+// first axis).
+void hilbert_point(uint64_t h, int bits, uint32_t X[3])
+{
+    X[0] = X[1] = X[2] = 0;
+    for (int k = 0; k < bits; ++k)
+        for (int i = 0; i < 3; ++i) X[i] |= (uint32_t)((h >> (3 * k + 2 - i)) & 1u) << k;
+    const uint32_t t = X[2] >> 1;
+    X[2] ^= X[1];
+    X[1] ^= X[0];
+    X[0] ^= t;
+    for (uint32_t Q = 2; Q < (1u << bits); Q <<= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 2; i >= 0; --i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint32_t e = (X[0] ^ X[i]) & P;
+                X[0] ^= e;
+                X[i] ^= e;
+            }
+        }
+    }
+}
+
+// Cell sort order: the box's cells in the order the Hilbert curve of the
+// smallest power-of-two cube containing the box visits them (the paper's
+// compact-Hilbert cell ordering).  order[0..ncell) = rank of each cell,
+// order[ncell..2 ncell) = cell of each rank.
+void make_order(Replica& r)
+{
+    const int32_t* L = r.p.L;
+    const int64_t ncell = r.sz.ncell;
+    int bits = 0;
+    while ((1 << bits) < std::max(L[0], std::max(L[1], L[2]))) bits++;
+    r.order.assign(2 * (size_t)ncell, 0u);
+    uint32_t* rank_of = r.order.data();
+    uint32_t* cell_of = rank_of + ncell;
+    int64_t q = 0;
+    const uint64_t end = 1ull << (3 * bits);
+    if (r.p.cell_order == 0) {
+        for (int64_t c = 0; c < ncell; ++c) { rank_of[c] = (uint32_t)c; cell_of[c] = (uint32_t)c; }
+        return;
+    }
+    for (uint64_t h = 0; h < end && q < ncell; ++h) {
+        uint32_t X[3];
+        hilbert_point(h, bits, X);
+        if ((int32_t)X[0] >= L[0] || (int32_t)X[1] >= L[1] || (int32_t)X[2] >= L[2]) continue;
+        const int64_t c = X[0] + (int64_t)L[0] * (X[1] + (int64_t)L[1] * X[2]);
+        rank_of[c] = (uint32_t)q;
+        cell_of[q] = (uint32_t)c;
+        q++;
+    }
 }
 
 void make_ptable(Replica& r)
@@ -699,6 +771,8 @@ rmp_status init_replica(rmp_batch* b, int slot)
     HIPCHK(hipMemcpyAsync(R.ws + R.lay.rs, &rs, sizeof(rs), hipMemcpyHostToDevice, s));
     make_ptable(R);
     HIPCHK(hipMemcpyAsync(R.ws + R.lay.ptable, R.ptable.data(), RMP_PTABLE * 8, hipMemcpyHostToDevice, s));
+    make_order(R);
+    HIPCHK(hipMemcpyAsync(R.ws + R.lay.order, R.order.data(), R.order.size() * 4, hipMemcpyHostToDevice, s));
     b->dirty = true;
     rmp_status st = sync_ctl(b);
     if (st != RMP_OK) return st;

@@ -134,6 +134,37 @@ __device__ __forceinline__ void normals3(const uint64_t w[4], double z[3])
 }
 
 // replica owning work item `item`: largest r with prefix[r] <= item
+// Position of cell (x, y, z) along the Hilbert curve of the 2^bits cube
+// (J. Skilling, "Programming the Hilbert curve", AIP Conf. Proc. 707 (2004)
+// 381): undo the excess work level by level from the top (invert the low
+// bits of the first axis where an axis has the level's bit set, otherwise
+// exchange the low bits of the first axis and that axis), Gray-encode, then
+// read the bits level by level, first axis most significant.
+__device__ __forceinline__ uint32_t hilbert_index(uint32_t x, uint32_t y, uint32_t z, int bits)
+{
+    uint32_t a[3] = {x, y, z};
+    for (int lv = bits - 1; lv >= 1; --lv) {
+        const uint32_t Q = 1u << lv, low = Q - 1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const uint32_t sw = (a[0] ^ a[i]) & low;
+            const bool set = (a[i] & Q) != 0;
+            a[0] ^= set ? low : sw;
+            if (!set) a[i] ^= sw;
+        }
+    }
+    a[1] ^= a[0];
+    a[2] ^= a[1];
+    uint32_t g = 0;
+    for (int lv = bits - 1; lv >= 1; --lv)
+        if (a[2] & (1u << lv)) g ^= (1u << lv) - 1;
+    a[0] ^= g; a[1] ^= g; a[2] ^= g;
+    uint32_t h = 0;
+    for (int lv = bits - 1; lv >= 0; --lv)
+        h = (h << 3) | (((a[0] >> lv) & 1u) << 2) | (((a[1] >> lv) & 1u) << 1) | ((a[2] >> lv) & 1u);
+    return h;
+}
+
 __device__ __forceinline__ int find_rep(const int32_t* prefix, int nrep, int item)
 {
     int lo = 0, hi = nrep - 1;

@@ -14,6 +14,8 @@ constexpr int SCAN_BLK = 4096;       // cells per block of the multi-block cell 
 constexpr int CHAIN_BLOCK = 256;     // threads per Verlet-list workgroup
 constexpr int NVAL_MAX = 3 * MAXC + 1;  // reduced values per MD step: F per colloid + U
 constexpr uint64_t BARRIER_BUDGET_TICKS = 25000000;  // 0.25 s of the 100 MHz wall clock
+constexpr int32_t KEY_TABLE = -1;                    // cell sort rank from rank_of[]
+constexpr int32_t KEY_ROW = -2;                      // row-major: rank = cell index
 
 // Philox stream tags (key word 1); key word 0 is the replica seed.
 enum : uint64_t {
@@ -55,7 +57,8 @@ struct RepDesc {
     int32_t n_md, rule;
     int32_t n_chunks, n_tiles, n_scanblk, tile_cells;
     int32_t cand_cap, G;       // Verlet-list capacity, MD-chain workgroups
-    int32_t chain_k, pad0;
+    int32_t chain_k;
+    int32_t hbits;             // cell sort rank: >= 0 Hilbert index with hbits bits, KEY_TABLE, KEY_ROW
     double Ld[3], halfL[3];
     double dt, h, tau, vscale, mass, ca, sa, cat_prob, skin_half2;
     int32_t bulk_on, pad1;
@@ -73,6 +76,8 @@ struct RepDesc {
     uint32_t* chunk_cnt;       // [n_chunks]
     uint32_t* chunk_off;       // [n_chunks]
     uint32_t* cand_idx;        // [cand_cap]
+    const uint32_t* rank_of;   // [ncell] sort rank of a cell (Hilbert order)
+    const uint32_t* cell_of;   // [ncell] cell of a sort rank
     double* partials;          // [2][G][NVAL_MAX][2] 64-bit exchange words of the MD chain
     double* epart;             // [G][2] reaction energy / flips of the interval
     double* tpart;             // [n_tiles][2]

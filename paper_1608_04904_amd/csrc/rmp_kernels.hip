@@ -160,6 +160,10 @@ __device__ __forceinline__ void shift_of(uint64_t seed, int64_t coll, double s[3
     s[2] = u01(w[2]);
 }
 
+// Sort key of the shifted cell holding (x0, x1, x2): its linear index
+// x + Lx (y + Ly z) in the row-major order; in the compact-Hilbert order its
+// rank along the curve, computed for a cubic power-of-two box and otherwise
+// looked up by the linear index.
 __device__ __forceinline__ uint32_t cell_key(const RepDesc& D, double x0, double x1, double x2,
                                              const double s[3])
 {
@@ -172,7 +176,10 @@ __device__ __forceinline__ uint32_t cell_key(const RepDesc& D, double x0, double
         if (q < 0) q += D.L[d];
         c[d] = q;
     }
-    return (uint32_t)(c[0] + (int64_t)D.L[0] * (c[1] + (int64_t)D.L[1] * c[2]));
+    const uint32_t lin = (uint32_t)(c[0] + (int64_t)D.L[0] * (c[1] + (int64_t)D.L[1] * c[2]));
+    if (D.hbits == KEY_ROW) return lin;
+    if (D.hbits >= 0) return hilbert_index((uint32_t)c[0], (uint32_t)c[1], (uint32_t)c[2], D.hbits);
+    return D.rank_of[lin];
 }
 
 // Verlet-list membership for the coming interval of length tau: flagged
@@ -1423,7 +1430,7 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
             // One cell larger than an LDS group (the group is this cell
             // alone).  Stable order by counting ranks into scratch: the
             // key/rank array is dead after the scatter and is reused here.
-            const int64_t cell = c0 + ga;
+            const int64_t cell = D.hbits == KEY_ROW ? c0 + ga : D.cell_of[c0 + ga];   // tiles run over sort ranks
             const int nn = ns;
             uint32_t* srt = reinterpret_cast<uint32_t*>(D.keyrank);
             for (int j = t; j < nn; j += COLL_NT) {
@@ -1571,7 +1578,7 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
         //    stable order), temperature term, axis, bulk reaction
         for (int lc = t; lc < gb - ga; lc += COLL_NT) {
             const int cl = ga + lc;
-            const int64_t cell = c0 + cl;
+            const int64_t cell = D.hbits == KEY_ROW ? c0 + cl : D.cell_of[c0 + cl];   // cell of this sort rank
             const int cb = (int)(s_start[cl] - q0), ce = (int)(s_start[cl + 1] - q0);
             const int nn = ce - cb;
             s_nn[lc] = nn;

@@ -82,6 +82,11 @@ CASES = {
     "dimer_react": lambda: W.dimer_system(L=16, rho=5, n_md=20, seed=3, bulk_rate=0.05),
     "dimer_p05": lambda: W.dimer_system(L=14, rho=6, n_md=10, seed=4, bulk_rate=0.02, cat_prob=0.5),
     "free_ragged": lambda: W.base_params(L=(7, 5, 9), rho=6, n_md=5),
+    # compact-Hilbert cell order: a cubic power-of-two box (rank computed in
+    # the kernels) and a ragged box (rank table)
+    "dimer_hilbert_cube": lambda: dict(W.dimer_system(L=16, rho=5, n_md=10, seed=6, bulk_rate=0.03),
+                                       cell_order="hilbert"),
+    "ragged_hilbert": lambda: dict(W.base_params(L=(7, 5, 9), rho=6, n_md=5), cell_order="hilbert"),
 }
 
 

@@ -148,20 +148,66 @@ def test_cell_keys_contain_particle():
         assert np.all((rel >= 0) & (rel < 1))
 
 
-def test_sort_is_stable_argsort():
+@pytest.mark.parametrize("order", ["row", "hilbert"])
+def test_sort_is_stable_argsort(order):
+    """The collision's sort is numpy's stable argsort of the cells' ranks
+    (row-major: the rank is the cell index)."""
     p = _no_colloid()
+    p["cell_order"] = order
     o = oracle.Oracle(p, 12)
+    if order == "row":
+        assert np.array_equal(o.cell_ranks(), np.arange(int(np.prod(p["L"]))))
     s0 = o.get_state()
     sh = o.shift(0)
-    keys = o.cell_keys(sh)
+    rank = o.cell_ranks()[o.cell_keys(sh)]
     o.collide(3)
     s1 = o.get_state()
-    perm = np.argsort(keys, kind="stable")
+    perm = np.argsort(rank, kind="stable")
     assert np.array_equal(s1["id"], s0["id"][perm])
     assert np.array_equal(s1["x"], s0["x"][:, perm])
     start = o.last_cells()
     ncell = int(np.prod(p["L"]))
-    assert np.array_equal(start, np.concatenate([[0], np.cumsum(np.bincount(keys, minlength=ncell))]))
+    assert np.array_equal(start, np.concatenate([[0], np.cumsum(np.bincount(rank, minlength=ncell))]))
+
+
+@pytest.mark.parametrize("bits", [1, 2, 3, 4])
+def test_hilbert_curve_invariants(bits):
+    """The cell order's curve is a Hilbert curve of the 2^bits cube: a
+    bijection onto [0, 8^bits) starting at the origin, consecutive indices
+    are face neighbours, and every aligned run of 8^k indices fills an
+    aligned 2^k cube (k = 1 .. bits)."""
+    n = 1 << bits
+    pts = np.array([(x, y, z) for z in range(n) for y in range(n) for x in range(n)])
+    h = np.array([oracle.hilbert(x, y, z, bits) for x, y, z in pts])
+    assert sorted(h.tolist()) == list(range(n ** 3))
+    walk = pts[np.argsort(h)]
+    assert tuple(walk[0]) == (0, 0, 0)
+    assert np.all(np.abs(np.diff(walk, axis=0)).sum(axis=1) == 1)
+    for k in range(1, bits + 1):
+        m = 1 << k
+        for blk in walk.reshape(-1, m ** 3, 3):
+            lo = blk.min(axis=0)
+            assert np.all(lo % m == 0) and np.all(blk.max(axis=0) - lo == m - 1)
+
+
+@pytest.mark.parametrize("L", [(8, 8, 8), (7, 5, 9), (12, 12, 12), (1, 1, 1)])
+def test_cell_ranks_follow_the_curve(L):
+    """Cells are ranked by their curve index in the smallest power-of-two
+    cube holding the box: a permutation of the cells, increasing along the
+    curve; for a power-of-two cube the rank is the curve index itself."""
+    p = W.base_params(L=L, rho=1, dt=0.01, n_md=1)
+    p["cell_order"] = "hilbert"
+    o = oracle.Oracle(p, 3)
+    r = o.cell_ranks()
+    ncell = L[0] * L[1] * L[2]
+    assert sorted(r.tolist()) == list(range(ncell))
+    bits = max(1, int(np.ceil(np.log2(max(L))))) if max(L) > 1 else 0
+    c = np.arange(ncell)
+    xyz = np.stack([c % L[0], (c // L[0]) % L[1], c // (L[0] * L[1])], axis=1)
+    h = np.array([oracle.hilbert(x, y, z, bits) for x, y, z in xyz])
+    assert np.all(np.diff(h[np.argsort(r)]) > 0)
+    if L[0] == L[1] == L[2] and (L[0] & (L[0] - 1)) == 0 and L[0] > 1:
+        assert np.array_equal(r, h)
 
 
 # --------------------------------------------------------------------------
