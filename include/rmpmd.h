@@ -166,8 +166,8 @@ rmp_status rmp_set_state(rmp_system* s, const rmp_host_state* src);
 rmp_status rmp_destroy(rmp_system* s);
 
 /* Per-kernel launch parameters (autotuning).  A negative field keeps its
- * current value; so does 0, except for use_graph and chain_resident, where 0
- * is a value (collide_cells is 0 until set).  Applies to the next rmp_step /
+ * current value; so does 0, except for use_graph, chain_resident and
+ * chain_block, where 0 is a value (collide_cells is 0 until set).  Applies to the next rmp_step /
  * rmp_batch_step. */
 typedef struct rmp_tuning {
     int32_t stream_block;      /* threads per workgroup, particle kernels       */
@@ -179,6 +179,9 @@ typedef struct rmp_tuning {
     int32_t chain_resident;    /* chain workgroups taken to fit on the device at
                                   once when raising chain_k (0: the device's
                                   own occupancy figure)                         */
+    int32_t chain_block;       /* MD-chain workgroup size: 256, 512 (one list
+                                  entry per thread), or 0: 512 when a list
+                                  needs more than one entry per thread at 256 */
 } rmp_tuning;
 rmp_status rmp_set_tuning(rmp_system* s, const rmp_tuning* t);
 rmp_status rmp_get_tuning(rmp_system* s, rmp_tuning* t);

@@ -190,7 +190,7 @@ struct rmp_batch {
     RepDesc* d_desc = nullptr;
     int32_t* d_prefix[6] = {};
     uint32_t* d_tick = nullptr;     // chain work-list tickets (two counters)
-    int32_t chain_resident[3] = {}; // chain workgroups the device holds at once, K = 1, 2, 4
+    int32_t chain_resident[4] = {}; // chain workgroups the device holds at once, per shape
     int32_t nc_common = -1;         // colloid count shared by every occupied slot, -1 if mixed
     std::vector<Replica> reps;
     std::vector<RepDesc> hdesc;
@@ -199,7 +199,7 @@ struct rmp_batch {
     bool dirty = true;
     bool have_rule[2] = {false, false};
     bool multi_scan = false;
-    rmp_tuning tun{256, 1, 0, 1, 1, 0};
+    rmp_tuning tun{256, 1, 0, 1, 1, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
@@ -247,38 +247,49 @@ rmp_status last_launch(const char* what)
     return RMP_OK;
 }
 
-// Verlet-list entries per chain thread: the tuned value, raised to the
-// smallest power of two for which every occupied replica's list capacity
-// fits in MAX_G workgroups
-int chain_groups(const rmp_batch* b, int k)
+// Shape of the MD-chain workgroups: NT threads with K list entries each.
+// Shapes 0, 1, 2: 256 threads with K = 1, 2, 4; shape 3: 512 threads, K = 1.
+struct ChainShape {
+    int nt, k, q;
+};
+
+int chain_groups(const rmp_batch* b, int k, int nt)
 {
     int64_t total = 0;
     for (const auto& R : b->reps) {
         if (!R.used) continue;
-        int64_t g = (R.sz.cand_cap + (int64_t)CHAIN_BLOCK * k - 1) / ((int64_t)CHAIN_BLOCK * k);
+        int64_t g = (R.sz.cand_cap + (int64_t)nt * k - 1) / ((int64_t)nt * k);
         total += std::max<int64_t>(1, std::min<int64_t>(g, R.sz.G));
     }
     return (int)std::min<int64_t>(total, INT32_MAX);
 }
 
-// Entries per chain thread: the tuned value, raised until every system's
-// list fits its workgroups, then raised while the batch's chain workgroups
-// exceed what the device holds at once (past that point they would run in
-// waves, each wave paying the full per-step exchange latency).
-int chain_k_of(const rmp_batch* b)
+int chain_resident_of(const rmp_batch* b, int q)
+{
+    return b->tun.chain_resident > 0 ? b->tun.chain_resident : b->chain_resident[q];
+}
+
+// 256-thread workgroups: the tuned entries per thread, raised until every
+// system's list fits its workgroups, then raised while the batch's chain
+// workgroups exceed what the device holds at once (past that point they
+// would run in waves, each wave paying the full per-step exchange latency).
+// 512-thread workgroups with one entry per thread are used when asked for,
+// or, by default, when a system's list needs more than one entry per thread
+// at 256 threads and the 512-thread shape still fits on the device.
+ChainShape chain_shape_of(const rmp_batch* b)
 {
     int k = b->tun.chain_k;
     if (k != 1 && k != 2 && k != 4) k = 1;
-    for (const auto& R : b->reps) {
-        if (!R.used) continue;
-        while (k < K_MAX && (int64_t)R.sz.cand_cap > (int64_t)MAX_G * CHAIN_BLOCK * k) k *= 2;
-    }
-    auto resident = [b](int kk) {
-        return b->tun.chain_resident > 0 ? b->tun.chain_resident
-                                         : b->chain_resident[kk == 1 ? 0 : (kk == 2 ? 1 : 2)];
-    };
-    while (k < K_MAX && chain_groups(b, k) > resident(k)) k *= 2;
-    return k;
+    int64_t cap_max = 0;
+    for (const auto& R : b->reps)
+        if (R.used) cap_max = std::max<int64_t>(cap_max, R.sz.cand_cap);
+    while (k < K_MAX && cap_max > (int64_t)MAX_G * 256 * k) k *= 2;
+    while (k < K_MAX && chain_groups(b, k, 256) > chain_resident_of(b, k == 1 ? 0 : (k == 2 ? 1 : 2))) k *= 2;
+    const bool want512 = b->tun.chain_block == 512 ||
+                         (b->tun.chain_block <= 0 && cap_max > (int64_t)MAX_G * 256);
+    if (want512 && cap_max <= (int64_t)MAX_G * 512 && chain_groups(b, 1, 512) <= chain_resident_of(b, 3))
+        return ChainShape{512, 1, 3};
+    return ChainShape{256, k, k == 1 ? 0 : (k == 2 ? 1 : 2)};
 }
 
 // Cells per collision tile: the slot's override, else the batch tuning,
@@ -318,12 +329,14 @@ void fill_desc(rmp_batch* b, Replica& r)
     D.n_tiles = (int32_t)((s.ncell + D.tile_cells - 1) / D.tile_cells);
     D.n_scanblk = s.n_scanblk;
     D.cand_cap = s.cand_cap;
-    const int K = chain_k_of(b);
-    int G = (int)((s.cand_cap + CHAIN_BLOCK * K - 1) / (CHAIN_BLOCK * K));
+    const ChainShape cs = chain_shape_of(b);
+    const int K = cs.k;
+    const int64_t per_wg = (int64_t)cs.nt * K;
+    int G = (int)((s.cand_cap + per_wg - 1) / per_wg);
     if (G < 1) G = 1;
     if (G > s.G) G = s.G;
     D.G = G;
-    D.cand_cap = std::min<int64_t>(s.cand_cap, (int64_t)G * CHAIN_BLOCK * K);
+    D.cand_cap = std::min<int64_t>(s.cand_cap, (int64_t)G * per_wg);
     D.chain_k = K;
     {
         // row-major: rank = cell index (KEY_ROW); compact Hilbert: computed in
@@ -575,37 +588,33 @@ rmp_status flush_profile(rmp_batch* b)
     return RMP_OK;
 }
 
+template <class T, int K, int NT>
+void launch_chain_shape(rmp_batch* b, hipStream_t s, dim3 g, bool ticket, int nc, const Work& w)
+{
+    const dim3 blk(NT);
+    if (ticket) hipLaunchKernelGGL((k_chain<T, K, true, 0, NT>), g, blk, 0, s, w);
+    else if (nc == 2) hipLaunchKernelGGL((k_chain<T, K, false, 2, NT>), g, blk, 0, s, w);
+    else if (nc == 1) hipLaunchKernelGGL((k_chain<T, K, false, 1, NT>), g, blk, 0, s, w);
+    else hipLaunchKernelGGL((k_chain<T, K, false, 0, NT>), g, blk, 0, s, w);
+}
+
 template <class T>
 rmp_status launch_chain(rmp_batch* b, hipStream_t s)
 {
     Timer tm(b, KN_CHAIN, s);
-    const int K = chain_k_of(b);
-    dim3 g(b->totals[PF_CHAIN]), blk(CHAIN_BLOCK);
-    const int q = K == 1 ? 0 : (K == 2 ? 1 : 2);
+    const ChainShape cs = chain_shape_of(b);
+    const dim3 g(b->totals[PF_CHAIN]);
     // more workgroups than the device holds at once: ticketed work list
-    const bool ticket = b->totals[PF_CHAIN] > b->chain_resident[q];
-    const Work w = work(b, PF_CHAIN);
-    if (ticket) {
-        if (K == 1) hipLaunchKernelGGL((k_chain<T, 1, true, 0>), g, blk, 0, s, w);
-        else if (K == 2) hipLaunchKernelGGL((k_chain<T, 2, true, 0>), g, blk, 0, s, w);
-        else hipLaunchKernelGGL((k_chain<T, 4, true, 0>), g, blk, 0, s, w);
-        return last_launch("k_chain");
-    }
+    const bool ticket = b->totals[PF_CHAIN] > b->chain_resident[cs.q];
     // colloid count common to every occupied slot: 1 or 2 have unrolled
     // variants, anything else (or a mix) the generic one
     const int nc = b->nc_common == 1 || b->nc_common == 2 ? b->nc_common : 0;
-    if (K == 1) {
-        if (nc == 2) hipLaunchKernelGGL((k_chain<T, 1, false, 2>), g, blk, 0, s, w);
-        else if (nc == 1) hipLaunchKernelGGL((k_chain<T, 1, false, 1>), g, blk, 0, s, w);
-        else hipLaunchKernelGGL((k_chain<T, 1, false, 0>), g, blk, 0, s, w);
-    } else if (K == 2) {
-        if (nc == 2) hipLaunchKernelGGL((k_chain<T, 2, false, 2>), g, blk, 0, s, w);
-        else if (nc == 1) hipLaunchKernelGGL((k_chain<T, 2, false, 1>), g, blk, 0, s, w);
-        else hipLaunchKernelGGL((k_chain<T, 2, false, 0>), g, blk, 0, s, w);
-    } else {
-        if (nc == 2) hipLaunchKernelGGL((k_chain<T, 4, false, 2>), g, blk, 0, s, w);
-        else if (nc == 1) hipLaunchKernelGGL((k_chain<T, 4, false, 1>), g, blk, 0, s, w);
-        else hipLaunchKernelGGL((k_chain<T, 4, false, 0>), g, blk, 0, s, w);
+    const Work w = work(b, PF_CHAIN);
+    switch (cs.q) {
+        case 0: launch_chain_shape<T, 1, 256>(b, s, g, ticket, nc, w); break;
+        case 1: launch_chain_shape<T, 2, 256>(b, s, g, ticket, nc, w); break;
+        case 2: launch_chain_shape<T, 4, 256>(b, s, g, ticket, nc, w); break;
+        default: launch_chain_shape<T, 1, 512>(b, s, g, ticket, nc, w); break;
     }
     return last_launch("k_chain");
 }
@@ -845,17 +854,19 @@ rmp_status batch_init(rmp_batch* b, int32_t nslots, int32_t precision, void* ctl
         int dev = 0, ncu = 0;
         HIPCHK(hipGetDevice(&dev));
         HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        int per[3] = {0, 0, 0};
+        int per[4] = {0, 0, 0, 0};
         if (precision == 64) {
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<double, 1, false, 0>, CHAIN_BLOCK, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<double, 2, false, 0>, CHAIN_BLOCK, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<double, 4, false, 0>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<double, 1, false, 0, 256>, 256, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<double, 2, false, 0, 256>, 256, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<double, 4, false, 0, 256>, 256, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[3], k_chain<double, 1, false, 0, 512>, 512, 0));
         } else {
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<float, 1, false, 0>, CHAIN_BLOCK, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<float, 2, false, 0>, CHAIN_BLOCK, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<float, 4, false, 0>, CHAIN_BLOCK, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<float, 1, false, 0, 256>, 256, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<float, 2, false, 0, 256>, 256, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<float, 4, false, 0, 256>, 256, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[3], k_chain<float, 1, false, 0, 512>, 512, 0));
         }
-        for (int q = 0; q < 3; ++q) b->chain_resident[q] = std::max(1, per[q]) * std::max(1, ncu);
+        for (int q = 0; q < 4; ++q) b->chain_resident[q] = std::max(1, per[q]) * std::max(1, ncu);
     }
     b->reps.assign(nslots, Replica{});
     b->hdesc.assign(nslots, RepDesc{});
@@ -1233,6 +1244,8 @@ rmp_status rmp_batch_set_tuning(rmp_batch* b, const rmp_tuning* t)
     if (t->chain_k > 0) n.chain_k = t->chain_k;
     if (t->use_graph >= 0) n.use_graph = t->use_graph;
     if (t->chain_resident >= 0) n.chain_resident = t->chain_resident;
+    if (t->chain_block >= 0) n.chain_block = t->chain_block;
+    if (n.chain_block != 0 && n.chain_block != 256 && n.chain_block != 512) return RMP_EINVAL;
     if (n.chain_k != 1 && n.chain_k != 2 && n.chain_k != 4) return RMP_EINVAL;
     if (n.stream_block != 64 && n.stream_block != 128 && n.stream_block != 256) return RMP_EINVAL;
     b->tun = n;

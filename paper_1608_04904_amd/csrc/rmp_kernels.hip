@@ -681,16 +681,41 @@ __device__ __forceinline__ void rattle_vel_lane(const BondLane& L, const double 
 }
 
 // Chain workgroup g of a replica holds Verlet-list positions
-// [g*B, (g+1)*B), B = 256*K, K consecutive positions per thread, in
-// registers for the whole interval.
-template <class T, int K>
+// [g*B, (g+1)*B), B = NT*K (NT = 256 or 512 threads), K consecutive
+// positions per thread, in registers for the whole interval.
+template <int NT>
 struct ChainCtx {
     double sXw[MAXC][3];       // periodic images of the colloid positions
-    double sRed[CHAIN_BLOCK / 64][NVAL_MAX];
+    // colloid constants read in every MD step, staged once per interval
+    double cRc2[MAXC], cSig2[MAXC], cEpsA[MAXC], cEpsB[MAXC], cSigma[MAXC];
+    int32_t cCat[MAXC], cType[MAXC];
+    double sRed[NT / 64][NVAL_MAX];
     double sNode[NVAL_MAX];
     double sU;
     uint32_t sflags;
 };
+
+// species_dU for an A -> B flip inside the MD chain, with the colloid
+// constants from LDS (same arithmetic)
+template <class Ctx>
+__device__ __forceinline__ double species_dU_lds(const Ctx& S, const RepDesc& D, int nc, double x0, double x1,
+                                                 double x2)
+{
+    double du = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        double dx = min_image(x0 - S.sXw[c][0], D.Ld[0], D.halfL[0]);
+        double dy = min_image(x1 - S.sXw[c][1], D.Ld[1], D.halfL[1]);
+        double dz = min_image(x2 - S.sXw[c][2], D.Ld[2], D.halfL[2]);
+        double r2 = dot3(dx, dy, dz, dx, dy, dz);
+        if (r2 < S.cRc2[c]) {
+            double cf, p0, p1;
+            wca(r2, S.cSig2[c], S.cEpsA[c], cf, p0);
+            wca(r2, S.cSig2[c], S.cEpsB[c], cf, p1);
+            du += p1 - p0;
+        }
+    }
+    return du;
+}
 
 // First half of a force evaluation: forces on this workgroup's list
 // entries from all colloids, and the per-colloid force sums and the
@@ -698,8 +723,8 @@ struct ChainCtx {
 // binary tree (within a thread over K, over the lanes of a wave, over the
 // waves).  With several workgroups the node values are then published for
 // the others (chain_collect completes the tree over workgroups).
-template <class T, int K>
-__device__ __forceinline__ void chain_compute(ChainCtx<T, K>& S, const RepDesc& D, const ColloidParams* cp,
+template <class T, int K, int NT>
+__device__ __forceinline__ void chain_compute(ChainCtx<NT>& S, const RepDesc& D, const ColloidParams* cp,
                               int nc, const bool* valid, const T (*x)[3], const uint8_t* st,
                               double (*f)[3], bool* inside, int g, int Gact,
                               uint32_t& nbar, uint32_t epoch0)
@@ -726,9 +751,9 @@ __device__ __forceinline__ void chain_compute(ChainCtx<T, K>& S, const RepDesc& 
             tv[3 * cb + 0] = 0.0; tv[3 * cb + 1] = 0.0; tv[3 * cb + 2] = 0.0;
             if (c >= nc) continue;
             const double Xc0 = S.sXw[c][0], Xc1 = S.sXw[c][1], Xc2 = S.sXw[c][2];
-            const double rc2 = cp->rc2[c], sig2 = cp->sig2[c];
-            const double eA = cp->epsA[c], eB = cp->epsB[c];
-            const bool cat = cp->catalytic[c] != 0;
+            const double rc2 = S.cRc2[c], sig2 = S.cSig2[c];
+            const double eA = S.cEpsA[c], eB = S.cEpsB[c];
+            const bool cat = S.cCat[c] != 0;
             double gx[K], gy[K], gz[K];
             bool any = false;
             // distances for the K entries, then the WCA terms only if some
@@ -810,7 +835,7 @@ __device__ __forceinline__ void chain_compute(ChainCtx<T, K>& S, const RepDesc& 
     }
     __syncthreads();
     const int nv = 3 * nc + 1;
-    constexpr int NW = CHAIN_BLOCK / 64;
+    constexpr int NW = NT / 64;
     if (t < nv) {
         double a[NW];
 #pragma unroll
@@ -927,14 +952,14 @@ struct PairLane {
     double sigma;
 };
 
-template <class T, int K>
-__device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& D, const ColloidParams* cp,
+template <class T, int K, int NT>
+__device__ __forceinline__ void chain_collect(ChainCtx<NT>& S, const RepDesc& D, const ColloidParams* cp,
                               int nc, int Gact, int Gpad, uint32_t nbar, uint32_t epoch0,
                               bool want_potential, double (&cF)[3], const PairLane& PL)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nv = 3 * nc + 1;
-    constexpr int NW = CHAIN_BLOCK / 64;
+    constexpr int NW = NT / 64;
     const int Q = Gpad > 64 ? Gpad / 64 : 1;
     const bool solo = Q == 1 && nv <= 8;
     if (solo && wave != 0) return;
@@ -971,8 +996,8 @@ __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& 
             if (a == c || PL.partner == a) continue;
             // colloid a's constants by its (uniform) index, this lane's from
             // registers; operands in the pair's (lo, hi) order
-            const double sig_a = cp->sigma[a];
-            const int ct_a = cp->ctype[a];
+            const double sig_a = S.cSigma[a];
+            const int ct_a = S.cType[a];
             const bool c_lo = c < a;
             const int lo = c_lo ? c : a, hi = c_lo ? a : c;
             double dx = min_image(S.sXw[lo][0] - S.sXw[hi][0], D.Ld[0], D.halfL[0]);
@@ -1016,7 +1041,7 @@ __device__ __forceinline__ void chain_collect(ChainCtx<T, K>& S, const RepDesc& 
     // after the workgroup barrier that follows the colloid position update
 }
 
-template <class T, int K, int NC>
+template <class T, int K, int NC, int NT>
 __device__ __forceinline__ void chain_run(Work w, int item)
 {
     const int rep = find_rep(w.prefix, w.nrep, item);
@@ -1028,7 +1053,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     // NC > 0: every system of the launch has NC colloids (loops over the
     // colloids unrolled at compile time); NC == 0: read per system
     const int nc = NC > 0 ? NC : cp->nc;
-    constexpr int B = CHAIN_BLOCK * K;
+    constexpr int B = NT * K;
     int64_t ncand = rs->n_cand;
     if (ncand > D.cand_cap) ncand = D.cand_cap;
     int Gact = (int)((ncand + B - 1) / B);
@@ -1038,7 +1063,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     int Gpad = 1;
     while (Gpad < Gact) Gpad <<= 1;
 
-    __shared__ ChainCtx<T, K> S;
+    __shared__ ChainCtx<NT> S;
     const int t = threadIdx.x;
     if (t == 0) S.sflags = 0;
     // colloid c lives in registers of thread c (c < nc, wave 0): position,
@@ -1058,6 +1083,13 @@ __device__ __forceinline__ void chain_run(Work w, int item)
             cX0[d] = cX[d];
             S.sXw[t][d] = colloid_image(cX[d], D.Ld[d]);
         }
+        S.cRc2[t] = cp->rc2[t];
+        S.cSig2[t] = cp->sig2[t];
+        S.cEpsA[t] = cp->epsA[t];
+        S.cEpsB[t] = cp->epsB[t];
+        S.cSigma[t] = cp->sigma[t];
+        S.cCat[t] = cp->catalytic[t];
+        S.cType[t] = cp->ctype[t];
     }
     const int64_t coll = rs->coll_step;
     const int cur = (int)(coll & 1);
@@ -1099,8 +1131,8 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     const bool colloid_wave = t < 64;
 
     // forces at the start of the interval
-    chain_compute<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
-    chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, false, cF, PL);
+    chain_compute<T, K, NT>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
+    chain_collect<T, K, NT>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, false, cF, PL);
     // list entries: first half kick and drift of step 0
 #pragma unroll
     for (int j = 0; j < K; ++j)
@@ -1133,7 +1165,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
                 for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(cX[d], D.Ld[d]);
         }
         __syncthreads();
-        chain_compute<T, K>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
+        chain_compute<T, K, NT>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
         // while the other workgroups' sums arrive: the list entries' second
         // half kick, catalysis, and (except after the last step) the next
         // step's first half kick and drift -- each entry's own arithmetic,
@@ -1161,8 +1193,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
                 if (flip) {
                     st[j] = 1;
                     ef += 1.0;
-                    eu += species_dU(D, cp, nc, S.sXw, (double)x[j][0], (double)x[j][1],
-                                     (double)x[j][2], 0, 1);
+                    eu += species_dU_lds(S, D, nc, (double)x[j][0], (double)x[j][1], (double)x[j][2]);
                 } else {
                     st[j] = 0;
                 }
@@ -1178,7 +1209,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
                 }
         }
         // the potential energy is an observable of the last force evaluation
-        chain_collect<T, K>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF, PL);
+        chain_collect<T, K, NT>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF, PL);
         // colloids (wave 0, in registers): second half kick, RATTLE
         // velocity stage, Verlet-list soundness check (displacement within
         // the interval)
@@ -1211,9 +1242,9 @@ __device__ __forceinline__ void chain_run(Work w, int item)
         D.keyrank[i] = ((uint64_t)key << 32) | rank;
     }
     // reaction bookkeeping of this workgroup (combined after the collision)
-    __shared__ double sred[CHAIN_BLOCK / 64 + 1];
-    eu = block_sum<CHAIN_BLOCK>(eu, sred);
-    ef = block_sum<CHAIN_BLOCK>(ef, sred);
+    __shared__ double sred[NT / 64 + 1];
+    eu = block_sum<NT>(eu, sred);
+    ef = block_sum<NT>(ef, sred);
     if (t == 0) {
         D.epart[(int64_t)g * 2 + 0] = eu;
         D.epart[(int64_t)g * 2 + 1] = ef;
@@ -1248,18 +1279,18 @@ __device__ __forceinline__ void chain_run(Work w, int item)
 // launch.  (The ticket is a separate instantiation because an atomic at
 // kernel entry keeps the descriptor loads of the whole kernel off the
 // scalar unit.)
-template <class T, int K, bool TICKET, int NC>
-__global__ __launch_bounds__(CHAIN_BLOCK) void k_chain(Work w)
+template <class T, int K, bool TICKET, int NC, int NT>
+__global__ __launch_bounds__(NT) void k_chain(Work w)
 {
     if (!TICKET) {
-        chain_run<T, K, NC>(w, (int)blockIdx.x);
+        chain_run<T, K, NC, NT>(w, (int)blockIdx.x);
         return;
     }
     __shared__ int s_item;
     if (threadIdx.x == 0)
         s_item = (int)__hip_atomic_fetch_add(&w.tick[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    chain_run<T, K, NC>(w, s_item);
+    chain_run<T, K, NC, NT>(w, s_item);
     if (threadIdx.x == 0) {
         const uint32_t fin = __hip_atomic_fetch_add(&w.tick[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (fin == gridDim.x - 1) {
@@ -1716,20 +1747,21 @@ __global__ __launch_bounds__(256) void k_observe(Work w)
 
 // ----------------------------------------------------- explicit instances
 
-#define RMP_CHAIN_INST(T, K)                                                     \
-    template __global__ void k_chain<T, K, false, 0>(Work);                      \
-    template __global__ void k_chain<T, K, false, 1>(Work);                      \
-    template __global__ void k_chain<T, K, false, 2>(Work);                      \
-    template __global__ void k_chain<T, K, true, 0>(Work);
+#define RMP_CHAIN_INST(T, K, NT)                                                 \
+    template __global__ void k_chain<T, K, false, 0, NT>(Work);                  \
+    template __global__ void k_chain<T, K, false, 1, NT>(Work);                  \
+    template __global__ void k_chain<T, K, false, 2, NT>(Work);                  \
+    template __global__ void k_chain<T, K, true, 0, NT>(Work);
 
 #define RMP_INST(T)                                                              \
     template __global__ void k_init<T>(const RepDesc*);                          \
     template __global__ void k_init_sub<T>(const RepDesc*, const double*);       \
     template __global__ void k_list<T>(Work);                                    \
     template __global__ void k_stream_bin<T>(Work, int);                         \
-    RMP_CHAIN_INST(T, 1)                                                         \
-    RMP_CHAIN_INST(T, 2)                                                         \
-    RMP_CHAIN_INST(T, 4)                                                         \
+    RMP_CHAIN_INST(T, 1, 256)                                                    \
+    RMP_CHAIN_INST(T, 2, 256)                                                    \
+    RMP_CHAIN_INST(T, 4, 256)                                                    \
+    RMP_CHAIN_INST(T, 1, 512)                                                    \
     template __global__ void k_collide<T, 0>(Work);                              \
     template __global__ void k_collide<T, 1>(Work);                              \
     template __global__ void k_observe<T>(Work);

@@ -117,6 +117,7 @@ def test_fp64_gpu_init_matches_oracle_init():
     dict(chain_k=1, collide_cells=8, stream_block=64, use_graph=0),
     dict(chain_k=2, collide_cells=16, stream_block=128, use_graph=1),
     dict(chain_k=4, collide_cells=64, stream_block=256, use_graph=1),
+    dict(chain_k=1, chain_block=512, collide_cells=32, stream_block=256, use_graph=0),
 ])
 def test_fp64_launch_configuration_does_not_change_results(tuning):
     """Different tile sizes, list blockings (and hence numbers of chain
