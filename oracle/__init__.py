@@ -102,6 +102,11 @@ def lib():
         L.orc_marsaglia.argtypes = [U64, I64, I64, P]
         L.orc_rotate.argtypes = [P, D, D, P, P]
         L.orc_ptable.argtypes = [D, D, P]
+        L.orc_dimer_sample.restype = C.c_int
+        L.orc_dimer_sample.argtypes = [P, I32, P]
+        L.orc_cyl_hist.restype = C.c_int
+        L.orc_cyl_hist.argtypes = [P, I32, I32, I32, D, D, P]
+        L.orc_msd.argtypes = [P, I64, I32, P]
         _lib = L
     return _lib
 
@@ -168,6 +173,18 @@ def marsaglia(seed: int, coll_step: int, cell: int) -> np.ndarray:
 def hilbert(x: int, y: int, z: int, bits: int) -> int:
     """Index of (x, y, z) along the Hilbert curve of the 2^bits cube."""
     return int(lib().orc_hilbert(int(x), int(y), int(z), int(bits)))
+
+
+def msd(R, max_lag: int) -> np.ndarray:
+    """Mean-squared displacement of a [T][3] series for lags 0..max_lag
+    (average over all time origins, summed in order)."""
+    R = np.ascontiguousarray(np.asarray(R, dtype=np.float64).reshape(-1, 3))
+    out = np.zeros(max_lag + 1)
+    lib().orc_msd(_ptr(R), R.shape[0], int(max_lag), _ptr(out))
+    return out
+
+
+SERIES_FIELDS = 10   # R_com[3], V_com[3], axis u[3], directed velocity V_com.u
 
 
 def rotate(n, alpha: float, w) -> np.ndarray:
@@ -291,3 +308,43 @@ class Oracle:
         a = np.zeros(m, dtype=np.uint32)
         lib().orc_last_cells(self.h, _ptr(a), m)
         return a
+
+    def dimer_sample(self, k: int) -> np.ndarray:
+        """R_com[3], V_com[3], unit axis u[3] (bond_a -> bond_b) and V_com.u
+        of bond k."""
+        rec = np.zeros(SERIES_FIELDS)
+        if lib().orc_dimer_sample(self.h, int(k), _ptr(rec)) != 0:
+            raise ValueError("no such bond")
+        return rec
+
+    def cyl_hist(self, k: int, nz: int, nr: int, zmax: float, rmax: float) -> np.ndarray:
+        """Counts [species A/B][nz][nr] of the current state around bond k."""
+        h = np.zeros((2, nz, nr), dtype=np.uint64)
+        if lib().orc_cyl_hist(self.h, int(k), int(nz), int(nr), float(zmax), float(rmax), _ptr(h)) != 0:
+            raise ValueError("bad histogram arguments")
+        return h
+
+    def run_analysed(self, n_md: int, n_collide: int, an: dict, acc: dict | None = None) -> dict:
+        """Intervals with the dimer analysis schedule: after every collision
+        whose count is a multiple of an["every"], one sample of every bond
+        (kept while fewer than an["series_cap"] are stored, else counted as
+        dropped) and the species histogram added."""
+        nb = len(self.params["bonds"])
+        nz, nr = int(an["hist_nz"]), int(an["hist_nr"])
+        if acc is None:
+            acc = dict(series=[], md_step=[], n_dropped=0,
+                       hist=np.zeros((nb, 2, nz, nr), dtype=np.uint64))
+        for _ in range(n_collide):
+            self.run(n_md, 1)
+            st = self.observables()
+            if st["coll_step"] % int(an["every"]):
+                continue
+            if len(acc["series"]) < int(an["series_cap"]):
+                acc["series"].append(np.stack([self.dimer_sample(k) for k in range(nb)]))
+                acc["md_step"].append(st["md_step"])
+            else:
+                acc["n_dropped"] += 1
+            for k in range(nb):
+                acc["hist"][k] += self.cyl_hist(k, nz, nr, an["hist_zmax"], an["hist_rmax"])
+        return acc
+

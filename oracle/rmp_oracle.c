@@ -997,3 +997,78 @@ int64_t orc_last_cells(const orc_system* s, uint32_t* start, int64_t cap)
     if (start) memcpy(start, s->start, sizeof(uint32_t) * m);
     return s->ncell + 1;
 }
+
+/* ------------------------------------------------------------------------
+ * Dimer analysis ("Applications of RMPCDMD": the dimer's directed velocity,
+ * the mean-squared displacement of its centre of mass and the cylindrical
+ * shell histogram of the product concentration).  The paper names these
+ * quantities without formulas; the definitions written out here are the
+ * readings stated in the design notes:
+ *   centre of mass R = (m_a X_a + m_b X_b) / (m_a + m_b) of bond (a, b),
+ *   velocity V likewise, axis u = (X_b - X_a) / |X_b - X_a|, directed
+ *   velocity V.u;  relative position r of a solvent particle = minimum image
+ *   of x minus the image of R in the box; z = r.u, rho = |r - z u|;
+ *   bins iz = floor((z + zmax) * nz / (2 zmax)), ir = floor(rho * nr / rmax),
+ *   counted when 0 <= iz < nz and ir < nr, separately for A and B.
+ */
+static double dot3o(const double a[3], const double b[3])
+{
+    return ((a[0] * b[0]) + (a[1] * b[1])) + (a[2] * b[2]);
+}
+
+int orc_dimer_sample(const orc_system* s, int32_t k, double rec[10])
+{
+    if (k < 0 || k >= s->p.n_bonds) return -1;
+    const int a = s->p.bond_a[k], b = s->p.bond_b[k];
+    const double ma = s->p.cmass[a], mb = s->p.cmass[b];
+    double dX[3];
+    for (int d = 0; d < 3; ++d) {
+        rec[d] = (ma * s->X[a][d] + mb * s->X[b][d]) / (ma + mb);
+        rec[3 + d] = (ma * s->V[a][d] + mb * s->V[b][d]) / (ma + mb);
+        dX[d] = s->X[b][d] - s->X[a][d];
+    }
+    const double len = sqrt(dot3o(dX, dX));
+    for (int d = 0; d < 3; ++d) rec[6 + d] = dX[d] / len;
+    rec[9] = dot3o(&rec[3], &rec[6]);
+    return 0;
+}
+
+int orc_cyl_hist(const orc_system* s, int32_t k, int32_t nz, int32_t nr, double zmax, double rmax,
+                 uint64_t* hist)
+{
+    if (k < 0 || k >= s->p.n_bonds || nz < 1 || nr < 1 || !(zmax > 0.0) || !(rmax > 0.0)) return -1;
+    double rec[10];
+    orc_dimer_sample(s, k, rec);
+    const double* u = &rec[6];
+    double Rw[3];
+    for (int d = 0; d < 3; ++d) Rw[d] = wrapX(rec[d], s->Ld[d]);
+    const double inv_dz = (double)nz / (2.0 * zmax), inv_dr = (double)nr / rmax;
+    for (int64_t i = 0; i < s->n; ++i) {
+        double r[3], p[3];
+        for (int d = 0; d < 3; ++d) r[d] = mimg(s->x[d][i] - Rw[d], s->Ld[d], s->halfL[d]);
+        const double z = dot3o(r, u);
+        for (int d = 0; d < 3; ++d) p[d] = r[d] - z * u[d];
+        const double rho = sqrt(dot3o(p, p));
+        const double zs = (z + zmax) * inv_dz, rs = rho * inv_dr;
+        if (!(zs >= 0.0 && zs < (double)nz && rs < (double)nr)) continue;
+        const int64_t iz = (int64_t)floor(zs), ir = (int64_t)floor(rs);
+        hist[((int64_t)(s->st[i] & 1) * nz + iz) * nr + ir] += 1;
+    }
+    return 0;
+}
+
+/* msd[lag] = average over the origins t = 0 .. T-1-lag of |R(t+lag) - R(t)|^2,
+ * summed in order of t; R is [T][3]. */
+void orc_msd(const double* R, int64_t T, int32_t max_lag, double* msd)
+{
+    for (int32_t lag = 0; lag <= max_lag; ++lag) {
+        if (lag >= T) { msd[lag] = 0.0; continue; }
+        double acc = 0.0;
+        for (int64_t t = 0; t + lag < T; ++t) {
+            double d[3];
+            for (int c = 0; c < 3; ++c) d[c] = R[(t + lag) * 3 + c] - R[t * 3 + c];
+            acc += dot3o(d, d);
+        }
+        msd[lag] = acc / (double)(T - lag);
+    }
+}

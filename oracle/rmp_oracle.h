@@ -111,6 +111,13 @@ void        orc_marsaglia(uint64_t seed, int64_t coll_step, int64_t cell, double
 void        orc_rotate(const double n[3], double ca, double sa, const double w[3], double out[3]);
 void        orc_ptable(double bulk_rate, double tau, double* table);
 
+/* dimer analysis of bond k: rec = R_com[3], V_com[3], axis u[3], V_com.u */
+int         orc_dimer_sample(const orc_system* s, int32_t k, double rec[10]);
+/* adds the current species counts per (z, rho) bin to hist[2][nz][nr] */
+int         orc_cyl_hist(const orc_system* s, int32_t k, int32_t nz, int32_t nr,
+                         double zmax, double rmax, uint64_t* hist);
+void        orc_msd(const double* R, int64_t T, int32_t max_lag, double* msd);
+
 #ifdef __cplusplus
 }
 #endif

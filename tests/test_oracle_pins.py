@@ -662,3 +662,185 @@ def test_paper_example_configuration_maps_to_params():
     o.run(5, 2)
     s = o.get_state()
     assert np.linalg.norm(s["X"][0] - s["X"][1]) == pytest.approx(6.5, rel=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Dimer analysis ("Applications of RMPCDMD": directed velocity, centre-of-mass
+# MSD, cylindrical shell histogram of the product species)
+
+def _analysis_system(L=16, rho=1, masses=None):
+    p = W.base_params(L=(L, L, L), rho=rho, dt=0.01, n_md=5)
+    W.add_dimer(p, (L / 2.0, L / 2.0, L / 2.0), (1.0, 0.0, 0.0))
+    if masses is not None:
+        for c, m in zip(p["colloids"], masses):
+            c["mass"] = float(m)
+    return p
+
+
+def _set_colloids(o, p, X, V, seed=1):
+    s = W.random_state(p, seed)
+    s["X"] = np.asarray(X, dtype=float)
+    s["V"] = np.asarray(V, dtype=float)
+    o.set_state(s)
+    return s
+
+
+def test_dimer_sample_closed_form():
+    p = _analysis_system(masses=(3.0, 1.0))
+    o = oracle.Oracle(p, 1)
+    a, b, _ = p["bonds"][0]
+    # unwrapped positions far outside the box: the centre of mass is not wrapped
+    Xa = np.array([-20.5, 40.25, 3.0])
+    Xb = Xa + np.array([0.0, 3.0, 4.0])          # |Xb - Xa| = 5
+    u = np.array([0.0, 3.0, 4.0]) / 5.0
+    w = np.array([1.0, 0.0, 0.0])                # perpendicular to u
+    Va = 0.7 * u + 0.25 * w
+    Vb = 0.7 * u - 0.75 * w                      # COM velocity (3 Va + Vb) / 4 = 0.7 u
+    X = np.zeros((2, 3)); V = np.zeros((2, 3))
+    X[a], X[b], V[a], V[b] = Xa, Xb, Va, Vb
+    _set_colloids(o, p, X, V)
+    rec = o.dimer_sample(0)
+    np.testing.assert_allclose(rec[0:3], (3.0 * Xa + Xb) / 4.0, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(rec[3:6], 0.7 * u, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(rec[6:9], [0.0, 0.6, 0.8], rtol=0, atol=1e-16)
+    assert abs(rec[9] - 0.7) < 1e-15
+    # reversing the bond's direction reverses the axis and the directed velocity
+    X[[a, b]] = X[[b, a]]; V[[a, b]] = V[[b, a]]
+    _set_colloids(o, p, X, V)
+    rec2 = o.dimer_sample(0)
+    np.testing.assert_allclose(rec2[6:9], [0.0, -0.6, -0.8], rtol=0, atol=1e-16)
+    # the masses stay with the indices: V_com = (3 Vb + Va) / 4 = 0.7 u - 0.5 w
+    np.testing.assert_allclose(rec2[3:6], 0.7 * u - 0.5 * w, rtol=0, atol=1e-15)
+    assert abs(rec2[9] + 0.7) < 1e-15
+    with pytest.raises(ValueError):
+        o.dimer_sample(1)
+
+
+def test_dimer_sample_reversal_with_equal_masses():
+    p = _analysis_system()
+    o = oracle.Oracle(p, 1)
+    a, b, _ = p["bonds"][0]
+    Xa = np.array([2.0, 3.0, 4.0]); Xb = Xa + np.array([6.0, 0.0, 0.0])
+    Vc = np.array([0.5, 0.125, -0.25])
+    X = np.zeros((2, 3)); V = np.zeros((2, 3))
+    X[a], X[b], V[a], V[b] = Xa, Xb, Vc, Vc
+    _set_colloids(o, p, X, V)
+    rec = o.dimer_sample(0)
+    assert np.array_equal(rec[0:3], [5.0, 3.0, 4.0]) and np.array_equal(rec[3:6], Vc)
+    assert np.array_equal(rec[6:9], [1.0, 0.0, 0.0]) and rec[9] == 0.5
+    X[[a, b]] = X[[b, a]]
+    _set_colloids(o, p, X, V)
+    rec = o.dimer_sample(0)
+    assert np.array_equal(rec[6:9], [-1.0, 0.0, 0.0]) and rec[9] == -0.5
+
+
+def _perp_basis(u):
+    u = np.asarray(u, dtype=float)
+    t = np.array([1.0, 0.0, 0.0]) if abs(u[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(u, t); e1 /= np.linalg.norm(e1)
+    e2 = np.cross(u, e1)
+    return e1, e2
+
+
+@pytest.mark.parametrize("centre", [(8.3, 7.9, 8.1), (0.4, 15.7, 0.2)])
+def test_cyl_hist_places_constructed_particles_in_their_bins(centre):
+    """Particles put at the centre of chosen (z, rho) bins around a dimer with
+    a tilted axis (and, for a centre near a corner, across the periodic
+    boundaries) land in exactly those bins; particles just outside the
+    cylinder and the far-away filler are not counted."""
+    L, nz, nr, zmax, rmax = 16, 10, 8, 5.0, 4.0
+    dz, dr = 2 * zmax / nz, rmax / nr
+    p = _analysis_system(L=L, rho=1)
+    o = oracle.Oracle(p, 2)
+    a, b, _ = p["bonds"][0]
+    u = np.array([1.0, 2.0, -2.0]) / 3.0
+    R = np.asarray(centre) + np.array([3 * L, -L, 0.0])     # unwrapped centre of mass
+    X = np.zeros((2, 3)); V = np.zeros((2, 3))
+    X[a], X[b] = R - 3.35 * u, R + 3.35 * u
+    s = _set_colloids(o, p, X, V)
+    rec = o.dimer_sample(0)
+    np.testing.assert_allclose(rec[6:9], u, atol=1e-15)
+    n = p["n_solvent"]
+    rng = np.random.default_rng(5)
+    Rw = np.mod(rec[0:3], L)
+    # filler: near the point of the box farthest from the centre
+    x = np.mod(Rw[:, None] + 8.0 + rng.uniform(-0.5, 0.5, size=(3, n)), L)
+    st = np.zeros(n, dtype=np.uint8)
+    expect = np.zeros((2, nz, nr), dtype=np.uint64)
+    e1, e2 = _perp_basis(u)
+    m = 600
+    for i in range(m):
+        iz, ir, sp = rng.integers(nz), rng.integers(nr), rng.integers(2)
+        z = -zmax + (iz + rng.uniform(0.1, 0.9)) * dz
+        rho = (ir + rng.uniform(0.1, 0.9)) * dr
+        phi = rng.uniform(0, 2 * np.pi)
+        x[:, i] = np.mod(Rw + z * u + rho * (np.cos(phi) * e1 + np.sin(phi) * e2), L)
+        st[i] = sp | (2 * rng.integers(2))       # the catalysis flag bit is not a species
+        expect[sp, iz, ir] += 1
+    # just outside: beyond either end cap, or beyond the radius
+    for i in range(m, m + 60):
+        kind = i % 3
+        z = (zmax + 0.3 * dz) * (1 if kind == 0 else -1) if kind < 2 else 0.2
+        rho = 0.5 if kind < 2 else rmax + 0.3 * dr
+        x[:, i] = np.mod(Rw + z * u + rho * e1, L)
+    x = np.where(x >= L, 0.0, x)
+    s["x"], s["state"] = np.ascontiguousarray(x), st
+    o.set_state(s)
+    h = o.cyl_hist(0, nz, nr, zmax, rmax)
+    assert np.array_equal(h, expect)
+
+
+def test_cyl_hist_marginals_match_membership_counts():
+    """Random state: per species, the number of particles with z below each
+    bin edge and with rho below each shell edge (computed with a cross
+    product, not by projection) equals the histogram's cumulative sums."""
+    L, nz, nr, zmax, rmax = 12, 6, 5, 4.5, 3.5
+    p = W.dimer_system(L=L, rho=5, n_md=5, seed=3)
+    o = oracle.Oracle(p, 3)
+    s = W.random_state(p, 9, species_B_fraction=0.4, flag_fraction=0.1)
+    o.set_state(s)
+    h = o.cyl_hist(0, nz, nr, zmax, rmax)
+    a, b, _ = p["bonds"][0]
+    X = s["X"]; M = np.array([c["mass"] for c in p["colloids"]])
+    R = (M[a] * X[a] + M[b] * X[b]) / (M[a] + M[b])
+    u = (X[b] - X[a]) / np.linalg.norm(X[b] - X[a])
+    r = s["x"].T - np.mod(R, L)
+    r -= L * np.round(r / L)
+    z = r @ u
+    rho = np.linalg.norm(np.cross(r, u), axis=1)
+    inside = (z >= -zmax) & (z < zmax) & (rho < rmax)
+    for sp in range(2):
+        sel = inside & ((s["state"] & 1) == sp)
+        assert h[sp].sum() == sel.sum() > 0
+        for k in range(nz + 1):
+            assert h[sp][:k].sum() == (sel & (z < -zmax + k * (2 * zmax / nz))).sum()
+        for k in range(nr + 1):
+            assert h[sp][:, :k].sum() == (sel & (rho < k * rmax / nr)).sum()
+
+
+def test_msd_closed_forms():
+    t = np.arange(41, dtype=float)[:, None]
+    v = np.array([0.5, -0.25, 1.0])
+    R = np.array([3.0, -7.5, 100.0]) + t * v           # exact in binary
+    msd = oracle.msd(R, 45)
+    lag = np.arange(46, dtype=float)
+    want = np.where(lag < 41, (v @ v) * lag ** 2, 0.0)
+    assert np.array_equal(msd, want)
+    assert np.array_equal(oracle.msd(np.ones((7, 3)), 6), np.zeros(7))
+    # two samples: lag 1 is the one squared displacement
+    assert oracle.msd([[0, 0, 0], [1, 2, 2]], 1).tolist() == [0.0, 9.0]
+    # alternating series: |d|^2 = 1 for odd lags, 0 for even lags
+    alt = np.zeros((10, 3)); alt[1::2, 0] = 1.0
+    m = oracle.msd(alt, 9)
+    assert np.array_equal(m[1::2], np.ones(5)) and np.array_equal(m[0::2], np.zeros(5))
+
+
+def test_analysis_schedule_and_series_cap():
+    p = W.dimer_system(L=10, rho=3, n_md=4, seed=4)
+    o = oracle.Oracle(p, 4)
+    an = dict(every=2, series_cap=2, hist_nz=4, hist_nr=3, hist_zmax=4.0, hist_rmax=3.0)
+    acc = o.run_analysed(4, 7, an)         # samples after collisions 2, 4, 6
+    assert len(acc["series"]) == 2 and acc["n_dropped"] == 1
+    assert acc["md_step"] == [8, 16]
+    # histogram totals: three samples, each counting the cylinder's members
+    assert acc["hist"].sum() > 0 and acc["hist"].dtype == np.uint64
