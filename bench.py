@@ -52,7 +52,9 @@ def algorithmic_bytes(kernel: str, n: int, ncell: int, tb: int, n_cand: int) -> 
                 starts 4 B per cell.
     scatter     per particle: read key/rank (8), write perm (4); starts 4/cell.
     scan_final  per cell: read count (4), write start (4), clear count (4).
-    chain       per list entry: read and write x, v, state (12 tb + 2)."""
+    chain       per list entry: read and write x, v, state (12 tb + 2).
+    analysis    per particle: read x (3 tb) and state (1); the histogram
+                updates touch only particles inside a dimer's cylinder."""
     nf = max(n - n_cand, 0)
     if kernel == "stream_bin":
         return nf * (9 * tb + 9) + 8 * ncell
@@ -64,6 +66,8 @@ def algorithmic_bytes(kernel: str, n: int, ncell: int, tb: int, n_cand: int) -> 
         return 12 * ncell
     if kernel == "chain":
         return n_cand * (12 * tb + 2)
+    if kernel == "analysis":
+        return n * (3 * tb + 1)
     if kernel in ("chunk_scan", "cand_write"):
         return n * 1 + 8 * math.ceil(n / 1024)
     return 0.0
@@ -267,6 +271,48 @@ def run_single(name, precision, steps, warmup, profile_steps, tun):
     return out
 
 
+ANALYSIS = dict(every=1, hist_nz=64, hist_nr=32, hist_zmax=12.0, hist_rmax=10.0)
+
+
+def run_analysis(name, precision, steps, warmup, tun):
+    """The workload with the dimer analysis sampled after every collision:
+    cost of the analysis kernel per sample and of the whole interval."""
+    import torch
+    import paper_1608_04904_amd as rm
+    p, n_md, seed, _ = workload(name, precision)
+    n = p["n_solvent"]
+    tb = 8 if precision == 64 else 4
+    s = rm.System(p, seed)
+    s.set_tuning(**tun)
+    s.analysis_attach(series_cap=steps + warmup + 8, **ANALYSIS)
+    s.step(n_md, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(n_md, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.profile(True)
+    s.step(n_md, 4)
+    prof = s.profile_read()
+    s.profile(False)
+    res = s.analysis_read()
+    flags = s.observables(raise_on_flags=False)["flags"]
+    ms, cnt = prof["analysis"]
+    avg = ms / max(cnt, 1)
+    gbs = algorithmic_bytes("analysis", n, 0, tb, 0) / (avg * 1e-3) / 1e9
+    msd = s.analysis_msd(min(steps, 16))
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return dict(value=n * n_md * steps / wall, analysis_avg_ms=round(avg, 5),
+                analysis_GBps=round(gbs, 1), analysis_hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+                samples=res["n_samples"], counted_per_sample=int(res["hist"].sum()) // max(
+                    res["n_samples"] + res["n_dropped"], 1),
+                dimers=len(p["bonds"]), bins=f"{ANALYSIS['hist_nz']}x{ANALYSIS['hist_nr']}",
+                directed_velocity_mean=float(res["series"][:, :, 9].mean()),
+                msd_lag1=float(msd[0][1]), flags=flags)
+
+
 def run_batch(precision, ticks, warmup, tun, n_rep=64):
     """64 dimer replicas, box edges from {16,20,24,32}, per-replica seeds,
     one interval (50 MD steps + collision) per replica per tick."""
@@ -398,6 +444,9 @@ def main():
                 value=r["value"], roofline=r["roofline"],
                 kernels={k: r["kernels"][k] for k in ("stream_bin", "collide", "chain")
                          if k in r["kernels"]})
+        for wl, st in (("dimer32", args.steps), ("large128", 6)):
+            _log(f"dimer analysis, {wl}")
+            extras[f"analysis_{wl}_fp64"] = run_analysis(wl, 64, st, 2, tun)
         _log("FP32 against FP64 drift, dimer32")
         extras["fp32_drift"] = fp32_drift(200, 3, not args.no_cpu)
     cpu = None

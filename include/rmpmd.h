@@ -222,6 +222,70 @@ rmp_status rmp_batch_set_tuning(rmp_batch* b, const rmp_tuning* t);
 rmp_status rmp_batch_set_slot_tuning(rmp_batch* b, int32_t slot, const rmp_tuning* t);
 rmp_status rmp_batch_destroy(rmp_batch* b);
 
+/* ------------------------------------------------------- dimer analysis */
+/* On-device analysis of dimer motors, the quantities the paper's analysis
+ * programs report ("Applications of RMPCDMD": laboratory-frame and directed
+ * velocity of the dimer, mean-squared displacement of its centre of mass,
+ * cylindrical shell histogram of the product concentration), accumulated
+ * during the run instead of storing solvent data (pre-averaging, "Overview").
+ *
+ * Every bond (a, b) of the system is one dimer.  A sample is taken at the
+ * end of every interval whose collision count (coll_step) is a multiple of
+ * `every`, from the state after the collision:
+ *   - series record of each dimer (RMP_SERIES_FIELDS doubles): centre of
+ *     mass R = (m_a X_a + m_b X_b) / (m_a + m_b) (unwrapped), its velocity V,
+ *     unit axis u = (X_b - X_a) / |X_b - X_a|, directed velocity V.u;
+ *     stored while fewer than series_cap samples are held, later samples
+ *     are counted in n_dropped;
+ *   - histogram: for every solvent particle, r = minimum image of its
+ *     position minus the image of R in the box, z = r.u, rho = |r - z u|;
+ *     counted per species (A, B) in bin iz = floor((z + zmax) nz / (2 zmax)),
+ *     ir = floor(rho nr / rmax) when 0 <= iz < nz and ir < nr (integer
+ *     counts, added at every sample, including dropped ones).
+ * Memory: the caller provides device memory of rmp_analysis_bytes(), 256-byte
+ * aligned, and keeps it until detach; attach clears it.  Counts and records
+ * do not depend on the launch configuration. */
+#define RMP_SERIES_FIELDS 10   /* R[3], V[3], u[3], V.u */
+
+typedef struct rmp_analysis_params {
+    int32_t every;             /* sample after collisions that are multiples of this (>= 1) */
+    int32_t series_cap;        /* samples of the series kept (>= 1)              */
+    int32_t hist_nz, hist_nr;  /* bins along the axis and across it (>= 1)       */
+    double  hist_zmax;         /* axial range [-zmax, zmax) (> 0)                */
+    double  hist_rmax;         /* radial range [0, rmax) (> 0)                   */
+} rmp_analysis_params;
+
+typedef struct rmp_analysis_out {
+    int64_t   n_samples;       /* samples stored in the series (<= series_cap)   */
+    int64_t   n_dropped;       /* samples taken after the series was full        */
+    int64_t*  md_step;         /* host [series_cap]: MD step of each sample, or NULL */
+    double*   series;          /* host [series_cap][n_bonds][RMP_SERIES_FIELDS], or NULL */
+    uint64_t* hist;            /* host [n_bonds][2][hist_nz][hist_nr], or NULL   */
+} rmp_analysis_out;
+
+/* Device bytes for the analysis of a system with parameters p; 0 and *st
+ * set on invalid arguments (no bonds, non-positive sizes or ranges). */
+size_t     rmp_analysis_bytes(const rmp_params* p, const rmp_analysis_params* a, rmp_status* st);
+/* Start (or restart, clearing the counts) the analysis of a system. */
+rmp_status rmp_analysis_attach(rmp_system* s, const rmp_analysis_params* a, void* d_buf,
+                               size_t bytes);
+/* Stop sampling; waits for queued work, after which d_buf may be freed. */
+rmp_status rmp_analysis_detach(rmp_system* s);
+/* Copy the counts, series and histogram to host memory (synchronous). */
+rmp_status rmp_analysis_read(rmp_system* s, rmp_analysis_out* out);
+/* Mean-squared displacement of each dimer's centre of mass over the stored
+ * series, computed on the device: msd[k][lag] = average over the origins t
+ * of |R(t + lag) - R(t)|^2 (summed in order of t), lag = 0 .. max_lag
+ * (< series_cap; 0 where lag >= n_samples).  msd is host memory of
+ * n_bonds * (max_lag + 1) doubles; synchronous. */
+rmp_status rmp_analysis_msd(rmp_system* s, int32_t max_lag, double* msd);
+/* The same for one slot of a batch. */
+rmp_status rmp_batch_analysis_attach(rmp_batch* b, int32_t slot, const rmp_analysis_params* a,
+                                     void* d_buf, size_t bytes);
+rmp_status rmp_batch_analysis_detach(rmp_batch* b, int32_t slot);
+rmp_status rmp_batch_analysis_read(rmp_batch* b, int32_t slot, rmp_analysis_out* out);
+rmp_status rmp_batch_analysis_msd(rmp_batch* b, int32_t slot, int32_t max_lag, double* msd);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,7 @@ import numpy as np
 from . import _capi
 from ._capi import RmpError, check, make_params, obs_dict
 
-__all__ = ["System", "Batch", "workspace_bytes", "init_system", "RmpError"]
+__all__ = ["System", "Batch", "workspace_bytes", "analysis_bytes", "init_system", "RmpError"]
 
 
 def _torch():
@@ -42,6 +42,38 @@ def _alloc(nbytes: int, device):
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def analysis_bytes(params: dict, analysis: dict) -> int:
+    q, a = make_params(params), _capi.make_analysis_params(analysis)
+    st = C.c_int32(0)
+    n = _capi.lib().rmp_analysis_bytes(C.byref(q), C.byref(a), C.byref(st))
+    check(st.value, "rmp_analysis_bytes")
+    return int(n)
+
+
+class _Analysis:
+    """Host side of one attached dimer analysis: its device buffer and the
+    host arrays it is read into."""
+
+    def __init__(self, params: dict, analysis: dict, device):
+        self.a = _capi.make_analysis_params(analysis)
+        self.nb = len(params["bonds"])
+        self.buf = _alloc(analysis_bytes(params, analysis), device)
+        cap, nz, nr = self.a.series_cap, self.a.hist_nz, self.a.hist_nr
+        self.md_step = np.zeros(cap, dtype=np.int64)
+        self.series = np.zeros((cap, self.nb, _capi.SERIES_FIELDS))
+        self.hist = np.zeros((self.nb, 2, nz, nr), dtype=np.uint64)
+
+    def out(self) -> _capi.AnalysisOut:
+        o = _capi.AnalysisOut()
+        o.md_step, o.series, o.hist = _ptr(self.md_step), _ptr(self.series), _ptr(self.hist)
+        return o
+
+    def result(self, o: _capi.AnalysisOut) -> dict:
+        k = int(o.n_samples)
+        return dict(n_samples=k, n_dropped=int(o.n_dropped), md_step=self.md_step[:k].copy(),
+                    series=self.series[:k].copy(), hist=self.hist.copy())
 
 
 class _StateBuffers:
@@ -98,6 +130,7 @@ class System:
             C.c_void_p(self.stream.cuda_stream), C.byref(h)), "rmp_init_system")
         self.h = h
         self._buf = None
+        self._an = None
 
     def close(self):
         if getattr(self, "h", None):
@@ -142,6 +175,29 @@ class System:
         for k, v in kw.items():
             setattr(t, k, int(v))
         check(_capi.lib().rmp_set_tuning(self.h, C.byref(t)), "rmp_set_tuning")
+
+    # dimer analysis (rmp_analysis_*)
+    def analysis_attach(self, **analysis):
+        an = _Analysis(self.params, analysis, self.device)
+        check(_capi.lib().rmp_analysis_attach(self.h, C.byref(an.a), C.c_void_p(an.buf.data_ptr()),
+                                              an.buf.numel()), "rmp_analysis_attach")
+        self._an = an
+
+    def analysis_detach(self):
+        check(_capi.lib().rmp_analysis_detach(self.h), "rmp_analysis_detach")
+        self._an = None
+
+    def analysis_read(self) -> dict:
+        # nothing attached: the library reports it (null outputs are not written)
+        o = self._an.out() if self._an else _capi.AnalysisOut()
+        check(_capi.lib().rmp_analysis_read(self.h, C.byref(o)), "rmp_analysis_read")
+        return self._an.result(o)
+
+    def analysis_msd(self, max_lag: int) -> np.ndarray:
+        nb = self._an.nb if self._an else len(self.params["bonds"])
+        m = np.zeros((max(nb, 1), int(max_lag) + 1))
+        check(_capi.lib().rmp_analysis_msd(self.h, int(max_lag), _ptr(m)), "rmp_analysis_msd")
+        return m
 
     def get_tuning(self) -> dict:
         t = _capi.Tuning()
@@ -201,7 +257,7 @@ class Batch:
         check(_capi.lib().rmp_batch_set_slot(self.h, int(slot), C.byref(q), int(seed), int(n_md),
                                              C.c_void_p(ws.data_ptr()), ws.numel()),
               "rmp_batch_set_slot")
-        self.slots[slot] = dict(params=params, ws=ws, q=q, buf=None,
+        self.slots[slot] = dict(params=params, ws=ws, q=q, buf=None, an=None,
                                 n=int(params["n_solvent"]), nc=len(params["colloids"]))
 
     def clear_slot(self, slot: int):
@@ -246,3 +302,31 @@ class Batch:
         t = _capi.Tuning(-1, -1, int(collide_cells), -1, -1, -1, -1)
         check(_capi.lib().rmp_batch_set_slot_tuning(self.h, int(slot), C.byref(t)),
               "rmp_batch_set_slot_tuning")
+
+    # dimer analysis of one slot (rmp_batch_analysis_*)
+    def analysis_attach(self, slot: int, **analysis):
+        an = _Analysis(self.slots[slot]["params"], analysis, self.device)
+        check(_capi.lib().rmp_batch_analysis_attach(self.h, int(slot), C.byref(an.a),
+                                                    C.c_void_p(an.buf.data_ptr()), an.buf.numel()),
+              "rmp_batch_analysis_attach")
+        self.slots[slot]["an"] = an
+
+    def analysis_detach(self, slot: int):
+        check(_capi.lib().rmp_batch_analysis_detach(self.h, int(slot)), "rmp_batch_analysis_detach")
+        self.slots[slot]["an"] = None
+
+    def analysis_read(self, slot: int) -> dict:
+        an = self.slots[slot]["an"]
+        o = an.out() if an else _capi.AnalysisOut()
+        check(_capi.lib().rmp_batch_analysis_read(self.h, int(slot), C.byref(o)),
+              "rmp_batch_analysis_read")
+        return an.result(o)
+
+    def analysis_msd(self, slot: int, max_lag: int) -> np.ndarray:
+        an = self.slots[slot]["an"]
+        nb = an.nb if an else len(self.slots[slot]["params"]["bonds"])
+        m = np.zeros((max(nb, 1), int(max_lag) + 1))
+        check(_capi.lib().rmp_batch_analysis_msd(self.h, int(slot), int(max_lag), _ptr(m)),
+              "rmp_batch_analysis_msd")
+        return m
+

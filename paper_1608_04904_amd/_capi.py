@@ -67,6 +67,23 @@ class Tuning(C.Structure):
     ]
 
 
+SERIES_FIELDS = 10   # R_com[3], V_com[3], axis u[3], directed velocity
+
+
+class AnalysisParams(C.Structure):
+    _fields_ = [
+        ("every", C.c_int32), ("series_cap", C.c_int32), ("hist_nz", C.c_int32),
+        ("hist_nr", C.c_int32), ("hist_zmax", C.c_double), ("hist_rmax", C.c_double),
+    ]
+
+
+class AnalysisOut(C.Structure):
+    _fields_ = [
+        ("n_samples", C.c_int64), ("n_dropped", C.c_int64), ("md_step", C.c_void_p),
+        ("series", C.c_void_p), ("hist", C.c_void_p),
+    ]
+
+
 # name -> (restype, argtypes); the full exported surface of include/rmpmd.h
 P, I32, I64, U64, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
 SIGNATURES = {
@@ -95,6 +112,15 @@ SIGNATURES = {
     "rmp_batch_set_tuning": (I32, [P, C.POINTER(Tuning)]),
     "rmp_batch_set_slot_tuning": (I32, [P, I32, C.POINTER(Tuning)]),
     "rmp_batch_destroy": (I32, [P]),
+    "rmp_analysis_bytes": (SZ, [C.POINTER(Params), C.POINTER(AnalysisParams), C.POINTER(I32)]),
+    "rmp_analysis_attach": (I32, [P, C.POINTER(AnalysisParams), P, SZ]),
+    "rmp_analysis_detach": (I32, [P]),
+    "rmp_analysis_read": (I32, [P, C.POINTER(AnalysisOut)]),
+    "rmp_analysis_msd": (I32, [P, I32, P]),
+    "rmp_batch_analysis_attach": (I32, [P, I32, C.POINTER(AnalysisParams), P, SZ]),
+    "rmp_batch_analysis_detach": (I32, [P, I32]),
+    "rmp_batch_analysis_read": (I32, [P, I32, C.POINTER(AnalysisOut)]),
+    "rmp_batch_analysis_msd": (I32, [P, I32, I32, P]),
 }
 
 _lib = None
@@ -171,3 +197,12 @@ def obs_dict(o: Obs, nc: int) -> dict:
     d["colloid_X"] = [[o.colloid_X[c][i] for i in range(3)] for c in range(nc)]
     d["colloid_V"] = [[o.colloid_V[c][i] for i in range(3)] for c in range(nc)]
     return d
+
+
+def make_analysis_params(a: dict) -> AnalysisParams:
+    q = AnalysisParams()
+    q.every, q.series_cap = int(a.get("every", 1)), int(a["series_cap"])
+    q.hist_nz, q.hist_nr = int(a["hist_nz"]), int(a["hist_nr"])
+    q.hist_zmax, q.hist_rmax = float(a["hist_zmax"]), float(a["hist_rmax"])
+    return q
+

@@ -156,9 +156,9 @@ size_t ctl_bytes_for(int32_t nslots)
 }
 
 const char* KNAMES[] = {"stream_bin", "chain", "scan_blocks", "scan_final", "scatter",
-                        "collide", "chunk_scan", "cand_write", "list"};
+                        "collide", "chunk_scan", "cand_write", "list", "analysis"};
 enum { KN_STREAM, KN_CHAIN, KN_SCANB, KN_SCANF, KN_SCATTER, KN_COLLIDE, KN_CHUNKSCAN,
-       KN_CANDW, KN_LIST, KN_COUNT };
+       KN_CANDW, KN_LIST, KN_ANALYSIS, KN_COUNT };
 
 struct Replica {
     bool used = false;
@@ -175,6 +175,8 @@ struct Replica {
     std::vector<uint32_t> order;   // host copy of the cell order tables (rank of cell, cell of rank)
     int32_t ptable_nmd = -1;
     int32_t tile_cells = 0;    // per-replica override of the collision tile size
+    char* an = nullptr;        // dimer-analysis buffer (caller memory), nullptr when off
+    rmp_analysis_params anp{};
 };
 
 }  // namespace
@@ -199,6 +201,7 @@ struct rmp_batch {
     bool dirty = true;
     bool have_rule[2] = {false, false};
     bool multi_scan = false;
+    bool any_analysis = false;
     rmp_tuning tun{256, 1, 0, 1, 1, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -381,6 +384,7 @@ void fill_desc(rmp_batch* b, Replica& r)
     D.obs_part = (double*)(w + L.obs_part);
     D.cp = (ColloidParams*)(w + L.cp);
     D.rs = (RepState*)(w + L.rs);
+    D.an = (Analysis*)r.an;
 }
 
 ColloidParams make_cp(const rmp_params* p)
@@ -494,6 +498,7 @@ rmp_status sync_ctl(rmp_batch* b)
     for (int k = 0; k < 6; ++k) b->hprefix[k].assign(S + 1, 0);
     b->have_rule[0] = b->have_rule[1] = false;
     b->multi_scan = false;
+    b->any_analysis = false;
     for (int r = 0; r < S; ++r) {
         Replica& R = b->reps[r];
         int items[6] = {0, 0, 0, 0, 1, 1};
@@ -505,6 +510,7 @@ rmp_status sync_ctl(rmp_batch* b)
             items[PF_CHAIN] = R.desc.G;
             b->have_rule[R.p.rule] = true;
             if (R.desc.n_scanblk > 1) b->multi_scan = true;
+            if (R.an) b->any_analysis = true;
             b->hdesc[r] = R.desc;
         } else {
             b->hdesc[r] = RepDesc{};
@@ -689,6 +695,10 @@ rmp_status launch_interval(rmp_batch* b, hipStream_t s)
     {
         Timer tm(b, KN_CANDW, s);
         hipLaunchKernelGGL(k_cand_write, dim3(nch), dim3(256), 0, s, work(b, PF_CHUNK));
+    }
+    if (b->any_analysis) {
+        Timer tm(b, KN_ANALYSIS, s);
+        hipLaunchKernelGGL((k_analysis<T>), dim3(nch), dim3(256), 0, s, work(b, PF_CHUNK));
     }
     return last_launch("interval");
 }
@@ -1033,6 +1043,133 @@ rmp_status slot_ok(rmp_batch* b, int32_t slot)
 
 // ===================================================================== ABI
 
+// ------------------------------------------------------------ dimer analysis
+namespace {
+
+struct AnLayout {
+    size_t hist, series, series_t, msd, total;
+};
+
+rmp_status an_validate(const rmp_params* p, const rmp_analysis_params* a)
+{
+    if (!p || !a) return RMP_EINVAL;
+    if (p->n_bonds < 1 || p->n_bonds > RMP_MAX_COLLOIDS) return RMP_EINVAL;
+    if (a->every < 1 || a->series_cap < 1 || a->hist_nz < 1 || a->hist_nr < 1) return RMP_EINVAL;
+    if ((int64_t)a->hist_nz * a->hist_nr > ((int64_t)1 << 24)) return RMP_EINVAL;
+    if (a->series_cap > (1 << 26)) return RMP_EINVAL;
+    if (!(a->hist_zmax > 0.0) || !(a->hist_rmax > 0.0) || !std::isfinite(a->hist_zmax) ||
+        !std::isfinite(a->hist_rmax))
+        return RMP_EINVAL;
+    return RMP_OK;
+}
+
+AnLayout an_layout(const rmp_params* p, const rmp_analysis_params* a)
+{
+    const size_t nb = (size_t)p->n_bonds, cap = (size_t)a->series_cap;
+    AnLayout L{};
+    size_t o = aup(sizeof(Analysis));
+    L.hist = o;
+    o = aup(o + nb * 2 * (size_t)a->hist_nz * (size_t)a->hist_nr * 8);
+    L.series = o;
+    o = aup(o + cap * nb * RMP_SERIES_FIELDS * 8);
+    L.series_t = o;
+    o = aup(o + cap * 8);
+    L.msd = o;
+    o = aup(o + nb * cap * 8);
+    L.total = o;
+    return L;
+}
+
+rmp_status an_attach(rmp_batch* b, int slot, const rmp_analysis_params* a, void* buf, size_t bytes)
+{
+    Replica& R = b->reps[slot];
+    rmp_status st = an_validate(&R.p, a);
+    if (st != RMP_OK) return st;
+    const AnLayout L = an_layout(&R.p, a);
+    if (!buf || bytes < L.total) return RMP_ENOMEM;
+    if (((uintptr_t)buf) % ALIGN) return RMP_EINVAL;
+    char* w = (char*)buf;
+    Analysis h{};
+    h.every = a->every;
+    h.cap = a->series_cap;
+    h.nz = a->hist_nz;
+    h.nr = a->hist_nr;
+    h.nb = R.p.n_bonds;
+    h.zmax = a->hist_zmax;
+    h.rmax = a->hist_rmax;
+    h.inv_dz = (double)a->hist_nz / (2.0 * a->hist_zmax);
+    h.inv_dr = (double)a->hist_nr / a->hist_rmax;
+    // sqrt(rho2) * inv_dr >= nr for every rho2 at or beyond this bound
+    const double rs = a->hist_rmax * (1.0 + 1e-6);
+    h.skip_r2 = rs * rs;
+    // a counted particle has z^2 + rho^2 < zmax^2 + rmax^2 up to rounding
+    h.cull_r = std::sqrt(a->hist_zmax * a->hist_zmax + a->hist_rmax * a->hist_rmax) * (1.0 + 1e-6);
+    h.hist = (uint64_t*)(w + L.hist);
+    h.series = (double*)(w + L.series);
+    h.series_t = (int64_t*)(w + L.series_t);
+    h.msd = (double*)(w + L.msd);
+    // queued intervals may still sample into a previous buffer
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipMemsetAsync(buf, 0, L.total, b->stream));
+    HIPCHK(hipMemcpyAsync(buf, &h, sizeof(h), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    R.an = w;
+    R.anp = *a;
+    b->dirty = true;
+    return RMP_OK;
+}
+
+rmp_status an_detach(rmp_batch* b, int slot)
+{
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->reps[slot].an = nullptr;
+    b->dirty = true;
+    return RMP_OK;
+}
+
+rmp_status an_read(rmp_batch* b, int slot, rmp_analysis_out* out)
+{
+    const Replica& R = b->reps[slot];
+    if (!R.an || !out) return RMP_ESTATE;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    Analysis h{};
+    HIPCHK(hipMemcpy(&h, R.an, sizeof(h), hipMemcpyDeviceToHost));
+    out->n_samples = h.n_samples;
+    out->n_dropped = h.n_dropped;
+    const size_t nb = (size_t)h.nb;
+    if (out->md_step && h.n_samples > 0)
+        HIPCHK(hipMemcpy(out->md_step, h.series_t, (size_t)h.n_samples * 8, hipMemcpyDeviceToHost));
+    if (out->series && h.n_samples > 0)
+        HIPCHK(hipMemcpy(out->series, h.series, (size_t)h.n_samples * nb * RMP_SERIES_FIELDS * 8,
+                         hipMemcpyDeviceToHost));
+    if (out->hist)
+        HIPCHK(hipMemcpy(out->hist, h.hist, nb * 2 * (size_t)h.nz * (size_t)h.nr * 8,
+                         hipMemcpyDeviceToHost));
+    return RMP_OK;
+}
+
+rmp_status an_msd(rmp_batch* b, int slot, int32_t max_lag, double* msd)
+{
+    const Replica& R = b->reps[slot];
+    if (!R.an) return RMP_ESTATE;
+    if (!msd || max_lag < 0 || max_lag >= R.anp.series_cap) return RMP_EINVAL;
+    const int nb = R.p.n_bonds;
+    const int64_t threads = (int64_t)nb * (max_lag + 1);
+    Analysis* A = (Analysis*)R.an;
+    hipLaunchKernelGGL(k_msd, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, b->stream, A, max_lag);
+    rmp_status le = last_launch("k_msd");
+    if (le != RMP_OK) return le;
+    const AnLayout L = an_layout(&R.p, &R.anp);
+    const double* dmsd = (const double*)(R.an + L.msd);
+    for (int k = 0; k < nb; ++k)
+        HIPCHK(hipMemcpyAsync(msd + (size_t)k * (max_lag + 1), dmsd + (size_t)k * R.anp.series_cap,
+                              (size_t)(max_lag + 1) * 8, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return RMP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* rmp_last_error(void) { return g_last_error; }
@@ -1272,6 +1409,69 @@ rmp_status rmp_batch_destroy(rmp_batch* b)
     batch_release(b);
     delete b;
     return RMP_OK;
+}
+
+size_t rmp_analysis_bytes(const rmp_params* p, const rmp_analysis_params* a, rmp_status* st)
+{
+    rmp_status v = validate(p);
+    if (v == RMP_OK) v = an_validate(p, a);
+    if (st) *st = v;
+    if (v != RMP_OK) return 0;
+    return an_layout(p, a).total;
+}
+
+rmp_status rmp_analysis_attach(rmp_system* s, const rmp_analysis_params* a, void* d_buf, size_t bytes)
+{
+    if (!s) return RMP_EINVAL;
+    return an_attach(s->b, 0, a, d_buf, bytes);
+}
+
+rmp_status rmp_analysis_detach(rmp_system* s)
+{
+    if (!s) return RMP_EINVAL;
+    return an_detach(s->b, 0);
+}
+
+rmp_status rmp_analysis_read(rmp_system* s, rmp_analysis_out* out)
+{
+    if (!s || !out) return RMP_EINVAL;
+    return an_read(s->b, 0, out);
+}
+
+rmp_status rmp_analysis_msd(rmp_system* s, int32_t max_lag, double* msd)
+{
+    if (!s) return RMP_EINVAL;
+    return an_msd(s->b, 0, max_lag, msd);
+}
+
+rmp_status rmp_batch_analysis_attach(rmp_batch* b, int32_t slot, const rmp_analysis_params* a,
+                                     void* d_buf, size_t bytes)
+{
+    rmp_status st = slot_ok(b, slot);
+    if (st != RMP_OK) return st;
+    return an_attach(b, slot, a, d_buf, bytes);
+}
+
+rmp_status rmp_batch_analysis_detach(rmp_batch* b, int32_t slot)
+{
+    rmp_status st = slot_ok(b, slot);
+    if (st != RMP_OK) return st;
+    return an_detach(b, slot);
+}
+
+rmp_status rmp_batch_analysis_read(rmp_batch* b, int32_t slot, rmp_analysis_out* out)
+{
+    rmp_status st = slot_ok(b, slot);
+    if (st != RMP_OK) return st;
+    if (!out) return RMP_EINVAL;
+    return an_read(b, slot, out);
+}
+
+rmp_status rmp_batch_analysis_msd(rmp_batch* b, int32_t slot, int32_t max_lag, double* msd)
+{
+    rmp_status st = slot_ok(b, slot);
+    if (st != RMP_OK) return st;
+    return an_msd(b, slot, max_lag, msd);
 }
 
 }  // extern "C"

@@ -49,6 +49,20 @@ struct RepState {
     double X[MAXC][3], V[MAXC][3], F[MAXC][3];
 };
 
+// Dimer-analysis state of one replica, at the start of the caller's
+// analysis buffer (the arrays follow it in the same buffer).
+struct Analysis {
+    int64_t n_samples, n_dropped;
+    int32_t every, cap, nz, nr, nb, pad;
+    double zmax, rmax, inv_dz, inv_dr;
+    double skip_r2;            // rho^2 beyond which rho certainly falls past the last shell
+    double cull_r;             // distance beyond which a point is certainly outside the cylinder
+    uint64_t* hist;            // [nb][2][nz][nr]
+    double* series;            // [cap][nb][RMP_SERIES_FIELDS]
+    int64_t* series_t;         // [cap] MD step of each stored sample
+    double* msd;               // [nb][cap]
+};
+
 // Per-replica descriptor, written by the host.
 struct RepDesc {
     int32_t L[3];
@@ -85,6 +99,7 @@ struct RepDesc {
     double* obs_part;          // [n_chunks][8]
     ColloidParams* cp;
     RepState* rs;
+    Analysis* an;              // dimer analysis, nullptr when off
 };
 
 // Work lists: items of one kind (particle chunks, cell tiles, scan blocks,

@@ -1745,6 +1745,181 @@ __global__ __launch_bounds__(256) void k_observe(Work w)
     }
 }
 
+// ------------------------------------------------------------ dimer analysis
+// Quantities of the paper's dimer analysis programs ("Applications of
+// RMPCDMD"), sampled on the device after a collision: the dimer record
+// (centre of mass, its velocity, unit axis from bond_a to bond_b, directed
+// velocity) and integer counts of A and B in cylindrical shells around the
+// dimer's axis.  The same operations in the same order as the definitions
+// (no contraction), so records and counts are exact, independent of launch
+// shape.
+__device__ __forceinline__ void dimer_record(const ColloidParams* cp, const RepState* rs, int k,
+                                             double rec[RMP_SERIES_FIELDS])
+{
+    const int a = cp->bond_a[k], b = cp->bond_b[k];
+    const double ma = cp->mass[a], mb = cp->mass[b];
+    double dX[3];
+    for (int d = 0; d < 3; ++d) {
+        rec[d] = (ma * rs->X[a][d] + mb * rs->X[b][d]) / (ma + mb);
+        rec[3 + d] = (ma * rs->V[a][d] + mb * rs->V[b][d]) / (ma + mb);
+        dX[d] = rs->X[b][d] - rs->X[a][d];
+    }
+    const double len = sqrt(dot3(dX[0], dX[1], dX[2], dX[0], dX[1], dX[2]));
+    for (int d = 0; d < 3; ++d) rec[6 + d] = dX[d] / len;
+    rec[9] = dot3(rec[3], rec[4], rec[5], rec[6], rec[7], rec[8]);
+}
+
+// One workgroup per particle chunk (after the collision): chunk 0 also
+// stores the series record.  After a collision the arrays are in cell order,
+// so a chunk occupies a small region: its bounding box culls, for the whole
+// workgroup, every dimer whose cylinder cannot reach it (the cylinder lies
+// within a sphere of radius sqrt(zmax^2 + rmax^2) about the centre of mass;
+// the bound carries a relative margin far above the rounding of z and rho,
+// so no counted particle is ever culled).  Hits are sparse, so they go
+// straight to 64-bit device atomics.
+template <class T>
+__global__ __launch_bounds__(256) void k_analysis(Work w)
+{
+    constexpr int PPT = CHUNK / 256;
+    const int item = blockIdx.x;
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int chunk = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    if (!D.active || D.an == nullptr) return;
+    Analysis* A = D.an;
+    const RepState* rs = D.rs;
+    if (rs->coll_step % A->every != 0) return;
+    __shared__ double sR[MAXC][3], sU[MAXC][3];
+    __shared__ double sBox[4][6];
+    __shared__ int sLive[MAXC];
+    const int nb = A->nb;
+    const int t = threadIdx.x;
+    const int cur = (int)(rs->coll_step & 1);
+    const int64_t n = D.n;
+    const int64_t base = (int64_t)chunk * CHUNK;
+    // every load of the chunk first
+    double px[PPT][3];
+    int psp[PPT];
+    bool pv[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int64_t i = base + t + 256 * q;
+        pv[q] = i < n;
+        const int64_t ic = pv[q] ? i : base;
+        px[q][0] = (double)comp<T>(D.x[cur], n, 0)[ic];
+        px[q][1] = (double)comp<T>(D.x[cur], n, 1)[ic];
+        px[q][2] = (double)comp<T>(D.x[cur], n, 2)[ic];
+        psp[q] = D.st[cur][ic] & 1;
+    }
+    if (t < nb) {
+        double rec[RMP_SERIES_FIELDS];
+        dimer_record(D.cp, rs, t, rec);
+        for (int d = 0; d < 3; ++d) {
+            sR[t][d] = colloid_image(rec[d], D.Ld[d]);
+            sU[t][d] = rec[6 + d];
+        }
+        if (chunk == 0) {
+            const int64_t k = A->n_samples;
+            if (k < A->cap) {
+                double* dst = A->series + (k * nb + t) * RMP_SERIES_FIELDS;
+                for (int f = 0; f < RMP_SERIES_FIELDS; ++f) dst[f] = rec[f];
+                if (t == 0) A->series_t[k] = rs->md_step;
+            }
+        }
+    }
+    // bounding box of the chunk's positions
+    double bx[6];
+    for (int d = 0; d < 3; ++d) {
+        bx[d] = INFINITY;
+        bx[3 + d] = -INFINITY;
+    }
+#pragma unroll
+    for (int q = 0; q < PPT; ++q)
+        if (pv[q])
+            for (int d = 0; d < 3; ++d) {
+                bx[d] = fmin(bx[d], px[q][d]);
+                bx[3 + d] = fmax(bx[3 + d], px[q][d]);
+            }
+    for (int m = 1; m < 64; m <<= 1)
+        for (int d = 0; d < 3; ++d) {
+            bx[d] = fmin(bx[d], __shfl_xor(bx[d], m, 64));
+            bx[3 + d] = fmax(bx[3 + d], __shfl_xor(bx[3 + d], m, 64));
+        }
+    if ((t & 63) == 0)
+        for (int k = 0; k < 6; ++k) sBox[t >> 6][k] = bx[k];
+    __syncthreads();
+    if (chunk == 0 && t == 0) {
+        if (A->n_samples < A->cap) A->n_samples += 1;
+        else A->n_dropped += 1;
+    }
+    if (t < nb) {
+        bool live = true;
+        for (int d = 0; d < 3; ++d) {
+            const double lo = fmin(fmin(sBox[0][d], sBox[1][d]), fmin(sBox[2][d], sBox[3][d]));
+            const double hi = fmax(fmax(sBox[0][3 + d], sBox[1][3 + d]), fmax(sBox[2][3 + d], sBox[3][3 + d]));
+            // periodic distance from the centre's images to [lo, hi]
+            double dist = INFINITY;
+            for (int k = -1; k <= 1; ++k) {
+                const double c = sR[t][d] + (double)k * D.Ld[d];
+                dist = fmin(dist, c < lo ? lo - c : (c > hi ? c - hi : 0.0));
+            }
+            if (dist >= A->cull_r) live = false;
+        }
+        sLive[t] = live ? 1 : 0;
+    }
+    __syncthreads();
+    const int nz = A->nz, nr = A->nr;
+    const double zmax = A->zmax, inv_dz = A->inv_dz, inv_dr = A->inv_dr, skip_r2 = A->skip_r2;
+    const double fnz = (double)nz, fnr = (double)nr;
+    uint64_t* hist = A->hist;
+    for (int b = 0; b < nb; ++b) {
+        if (!sLive[b]) continue;
+        const double c0 = sR[b][0], c1 = sR[b][1], c2 = sR[b][2];
+        const double u0 = sU[b][0], u1 = sU[b][1], u2 = sU[b][2];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            if (!pv[q]) continue;
+            const double r0 = min_image(px[q][0] - c0, D.Ld[0], D.halfL[0]);
+            const double r1 = min_image(px[q][1] - c1, D.Ld[1], D.halfL[1]);
+            const double r2 = min_image(px[q][2] - c2, D.Ld[2], D.halfL[2]);
+            const double z = dot3(r0, r1, r2, u0, u1, u2);
+            const double zs = (z + zmax) * inv_dz;
+            if (!(zs >= 0.0 && zs < fnz)) continue;
+            const double p0 = r0 - z * u0, p1 = r1 - z * u1, p2 = r2 - z * u2;
+            const double pp = dot3(p0, p1, p2, p0, p1, p2);
+            if (!(pp < skip_r2)) continue;
+            const double rsc = sqrt(pp) * inv_dr;
+            if (!(rsc < fnr)) continue;
+            const int iz = (int)zs, ir = (int)rsc;
+            atomicAdd((unsigned long long*)&hist[(((int64_t)b * 2 + psp[q]) * nz + iz) * nr + ir], 1ull);
+        }
+    }
+}
+
+// Mean-squared displacement of each dimer's centre of mass over the stored
+// series: one thread per (dimer, lag), origins summed in order.
+__global__ __launch_bounds__(256) void k_msd(Analysis* A, int32_t max_lag)
+{
+    const int nb = A->nb;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= (int64_t)nb * (max_lag + 1)) return;
+    const int b = (int)(g / (max_lag + 1));
+    const int lag = (int)(g % (max_lag + 1));
+    const int64_t T = A->n_samples;
+    double out = 0.0;
+    if (lag < T) {
+        double acc = 0.0;
+        for (int64_t t0 = 0; t0 + lag < T; ++t0) {
+            const double* p = A->series + ((t0 + lag) * nb + b) * RMP_SERIES_FIELDS;
+            const double* q = A->series + (t0 * nb + b) * RMP_SERIES_FIELDS;
+            const double d0 = p[0] - q[0], d1 = p[1] - q[1], d2 = p[2] - q[2];
+            acc += dot3(d0, d1, d2, d0, d1, d2);
+        }
+        out = acc / (double)(T - lag);
+    }
+    A->msd[(int64_t)b * A->cap + lag] = out;
+}
+
 // ----------------------------------------------------- explicit instances
 
 #define RMP_CHAIN_INST(T, K, NT)                                                 \
@@ -1764,7 +1939,8 @@ __global__ __launch_bounds__(256) void k_observe(Work w)
     RMP_CHAIN_INST(T, 1, 512)                                                    \
     template __global__ void k_collide<T, 0>(Work);                              \
     template __global__ void k_collide<T, 1>(Work);                              \
-    template __global__ void k_observe<T>(Work);
+    template __global__ void k_observe<T>(Work);                              \
+    template __global__ void k_analysis<T>(Work);
 
 RMP_INST(double)
 RMP_INST(float)

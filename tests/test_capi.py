@@ -40,6 +40,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(rmp_params), sizeof(rmp_obs), sizeof(rmp_host_state), sizeof(rmp_tuning));
   printf("%zu %zu %zu %zu\n", offsetof(rmp_params, colloid_x), offsetof(rmp_params, bond_d),
          offsetof(rmp_obs, flags), offsetof(rmp_obs, colloid_V));
+  printf("%zu %zu %zu %zu %d\n", sizeof(rmp_analysis_params), sizeof(rmp_analysis_out),
+         offsetof(rmp_analysis_params, hist_rmax), offsetof(rmp_analysis_out, hist), RMP_SERIES_FIELDS);
   return 0;
 }
 '''
@@ -58,6 +60,11 @@ int main(void) {
     assert sizes[5] == _capi.Params.bond_d.offset
     assert sizes[6] == _capi.Obs.flags.offset
     assert sizes[7] == _capi.Obs.colloid_V.offset
+    assert sizes[8] == C.sizeof(_capi.AnalysisParams)
+    assert sizes[9] == C.sizeof(_capi.AnalysisOut)
+    assert sizes[10] == _capi.AnalysisParams.hist_rmax.offset
+    assert sizes[11] == _capi.AnalysisOut.hist.offset
+    assert sizes[12] == _capi.SERIES_FIELDS
 
 
 def test_workspace_bytes_and_validation_on_host():
@@ -80,6 +87,23 @@ def test_workspace_bytes_and_validation_on_host():
     W.add_colloid(small, (3, 3, 3), sigma=4.0)      # reach beyond half the box
     with pytest.raises(_capi.RmpError):
         workspace_bytes(small)
+
+
+def test_analysis_bytes_and_validation_on_host():
+    import workloads as W
+    from paper_1608_04904_amd import _capi, analysis_bytes
+    p = W.dimer32()
+    a = dict(every=1, series_cap=1000, hist_nz=64, hist_nr=32, hist_zmax=10.0, hist_rmax=8.0)
+    n = analysis_bytes(p, a)
+    assert n >= 2 * 64 * 32 * 8 + 1000 * 10 * 8 + 1000 * 8 + 1000 * 8
+    assert analysis_bytes(p, dict(a, series_cap=2000)) > n
+    for bad in (dict(every=0), dict(series_cap=0), dict(hist_nz=0), dict(hist_nr=-1),
+                dict(hist_zmax=0.0), dict(hist_rmax=float("nan")), dict(hist_zmax=float("inf"))):
+        with pytest.raises(_capi.RmpError):
+            analysis_bytes(p, dict(a, **bad))
+    nob = W.sphere10()                                   # no bond: no dimer to analyse
+    with pytest.raises(_capi.RmpError):
+        analysis_bytes(nob, a)
 
 
 def test_product_package_has_no_oracle_dependency():
