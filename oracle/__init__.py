@@ -47,6 +47,7 @@ class Params(C.Structure):
         ("ctype", C.c_int32 * MAXC), ("eps_cc", (C.c_double * 2) * 2),
         ("bond_a", C.c_int32 * MAXC), ("bond_b", C.c_int32 * MAXC),
         ("bond_d", C.c_double * MAXC), ("cell_order", C.c_int32), ("pad", C.c_int32),
+        ("walls", C.c_int32), ("wall_density", C.c_int32), ("accel", C.c_double * 3),
     ]
 
 
@@ -142,6 +143,10 @@ def make_params(p: dict) -> Params:
     q.n_bonds = len(p["bonds"])
     for k, (a, b, dd) in enumerate(p["bonds"]):
         q.bond_a[k], q.bond_b[k], q.bond_d[k] = a, b, dd
+    q.walls = int(p.get("walls", 0))
+    q.wall_density = int(p.get("wall_density", 0))
+    for d, g in enumerate(p.get("accel", (0.0, 0.0, 0.0))):
+        q.accel[d] = float(g)
     return q
 
 

@@ -46,7 +46,7 @@ void orc_philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
 }
 
 enum { TAG_SHIFT = 1, TAG_ROT = 2, TAG_BULK = 3, TAG_CAT = 4, TAG_THERMO = 5,
-       TAG_INIT_POS = 6, TAG_INIT_VEL = 7 };
+       TAG_INIT_POS = 6, TAG_INIT_VEL = 7, TAG_VIRT = 8 };
 
 static void draw(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b, uint64_t c,
                  uint64_t w[4])
@@ -250,11 +250,23 @@ static void hilbert_order(const int32_t L[3], uint32_t* rank_of, uint32_t* cell_
     free(pairs);
 }
 
+static int has_flow(const orc_params* p)
+{
+    return p->walls != 0 || p->accel[0] != 0.0 || p->accel[1] != 0.0 || p->accel[2] != 0.0;
+}
+
 orc_system* orc_create(const orc_params* p, uint64_t seed)
 {
     if (p->L[0] < 1 || p->L[1] < 1 || p->L[2] < 1 || p->n_solvent < 0 ||
         (p->cell_order != 0 && p->cell_order != 1) ||
         p->n_colloids < 0 || p->n_colloids > ORC_MAXC || p->dt <= 0.0 || p->mass <= 0.0)
+        return NULL;
+    /* flows: no colloids; walls with the rotation rule, row-major cells, a
+     * fill density and no acceleration across the plates */
+    if (p->walls != 0 && p->walls != 1) return NULL;
+    if (has_flow(p) && (p->n_colloids != 0 || p->n_bonds != 0)) return NULL;
+    if (p->walls && (p->rule != 0 || p->cell_order != 0 || p->accel[2] != 0.0 ||
+                     p->wall_density < 1 || p->wall_density > 1024))
         return NULL;
     orc_system* s = (orc_system*)xalloc(sizeof(orc_system));
     s->p = *p;
@@ -274,7 +286,8 @@ orc_system* orc_create(const orc_params* p, uint64_t seed)
     s->tid = (uint32_t*)xalloc(sizeof(uint32_t) * s->n);
     s->tst = (uint8_t*)xalloc(s->n);
     s->keys = (uint32_t*)xalloc(sizeof(uint32_t) * s->n);
-    s->ncell = (int64_t)p->L[0] * p->L[1] * p->L[2];
+    /* with walls the shifted grid needs L_z + 1 layers of cells across the channel */
+    s->ncell = (int64_t)p->L[0] * p->L[1] * (p->L[2] + (p->walls ? 1 : 0));
     s->start = (uint32_t*)xalloc(sizeof(uint32_t) * (s->ncell + 1));
     s->rank_of = (uint32_t*)xalloc(sizeof(uint32_t) * s->ncell);
     s->cell_of = (uint32_t*)xalloc(sizeof(uint32_t) * s->ncell);
@@ -619,6 +632,45 @@ static double species_dU(const orc_system* s, int64_t i, int from, int to)
     return du;
 }
 
+/* One streaming step of a solvent particle under the constant acceleration g
+ * ("Algorithms": flows from a constant acceleration on the solvent), as a
+ * velocity-Verlet step with the force m g: half kick, drift, half kick.
+ * With walls (plates at z = 0 and z = L_z, stick boundary by the bounce-back
+ * rule) a drift that leaves the channel is cut at the crossing time t*: the
+ * particle moves to the wall, its velocity is reversed, and it travels the
+ * rest of the step, dt - t*, with the reversed velocity. */
+static void flow_step(const orc_system* s, double x[3], double v[3])
+{
+    const double dt = s->p.dt, hdt = 0.5 * dt;
+    double y[3];
+    for (int d = 0; d < 3; ++d) {
+        v[d] = fma(hdt, s->p.accel[d], v[d]);
+        y[d] = fma(dt, v[d], x[d]);
+    }
+    if (s->p.walls) {
+        const double Lz = s->Ld[2];
+        if (y[2] < 0.0 || y[2] >= Lz) {
+            const double wz = y[2] < 0.0 ? 0.0 : Lz;
+            const double ts = (wz - x[2]) / v[2];
+            const double rem = dt - ts;
+            for (int d = 0; d < 3; ++d) {
+                const double xc = fma(ts, v[d], x[d]);
+                v[d] = -v[d];
+                y[d] = fma(rem, v[d], xc);
+            }
+            /* rounding can leave the reflected point on a plate */
+            if (y[2] >= Lz) y[2] = nextafter(Lz, 0.0);
+            if (y[2] < 0.0) y[2] = 0.0;
+        }
+        x[0] = wrap1(y[0], s->Ld[0]);
+        x[1] = wrap1(y[1], s->Ld[1]);
+        x[2] = y[2];
+    } else {
+        for (int d = 0; d < 3; ++d) x[d] = wrap1(y[d], s->Ld[d]);
+    }
+    for (int d = 0; d < 3; ++d) v[d] = fma(hdt, s->p.accel[d], v[d]);
+}
+
 /* One velocity-Verlet step ("Algorithms": velocity-Verlet for solvent and
  * colloids; Overview: Newton's equations solved with velocity-Verlet), in
  * kick-drift-kick form with fused multiply-adds, followed by the catalytic
@@ -629,6 +681,18 @@ static void md_step(orc_system* s)
 {
     const double dt = s->p.dt;
     const int nc = s->nc;
+    if (has_flow(&s->p)) {
+        /* no colloids: every particle streams under the acceleration */
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < s->n; ++i) {
+            double x[3], v[3];
+            for (int d = 0; d < 3; ++d) { x[d] = s->x[d][i]; v[d] = s->v[d][i]; }
+            flow_step(s, x, v);
+            for (int d = 0; d < 3; ++d) { s->x[d][i] = x[d]; s->v[d][i] = v[d]; }
+        }
+        s->md_step++;
+        return;
+    }
     double Xold[ORC_MAXC][3];
     for (int c = 0; c < nc; ++c)
         for (int d = 0; d < 3; ++d) {
@@ -699,7 +763,9 @@ void orc_shift(const orc_system* s, int64_t coll_step, double shift[3])
 }
 
 /* cell of the shifted position: c_d = floor(x_d - s_d) wrapped to [0, L_d);
- * key = c_x + L_x (c_y + L_y c_z). */
+ * key = c_x + L_x (c_y + L_y c_z).  With walls the z layers are not periodic:
+ * c_z = floor(z - s_z) + 1 in [0, L_z], layer j covering [j - 1 + s_z, j + s_z),
+ * so the first and last layers are cut by the plates. */
 void orc_cell_keys(const orc_system* s, const double shift[3], uint32_t* keys)
 {
     const int32_t* L = s->p.L;
@@ -708,6 +774,10 @@ void orc_cell_keys(const orc_system* s, const double shift[3], uint32_t* keys)
         int64_t c[3];
         for (int d = 0; d < 3; ++d) {
             int64_t q = (int64_t)floor(s->x[d][i] - shift[d]);
+            if (d == 2 && s->p.walls) {
+                c[d] = q + 1;
+                continue;
+            }
             if (q < 0) q += L[d];
             if (q >= L[d]) q -= L[d];
             c[d] = q;
@@ -799,6 +869,9 @@ static void collide(orc_system* s, int32_t n_md)
     double* erx = (double*)xalloc(sizeof(double) * (ncell ? ncell : 1));
     uint8_t* flipped = (uint8_t*)xalloc(ncell ? ncell : 1);
     const double sc = sqrt(s->p.kT / s->p.mass);
+    const int64_t layer = (int64_t)s->p.L[0] * s->p.L[1];
+    const int64_t top = s->p.L[2];
+    uint8_t* virt = (uint8_t*)xalloc(ncell ? ncell : 1);
     /* cells in sort order: rank r holds the particles of cell c = cell_of[r];
      * per-cell random streams are keyed by the cell c */
     #pragma omp parallel for schedule(dynamic, 256)
@@ -807,18 +880,34 @@ static void collide(orc_system* s, int32_t n_md)
         int64_t b = s->start[r], e = s->start[r + 1];
         int64_t nn = e - b;
         tterm[c] = 0.0;
-        if (nn >= 2) {
+        /* Lamura et al. (2001): a cell cut by a wall with fewer particles
+         * than a full cell (n0) is filled with n0 - n virtual particles at
+         * rest on average with Maxwell-Boltzmann velocities; they enter the
+         * cell's mean velocity only, through their summed momentum, a
+         * normal vector of variance (n0 - n) kT / m per component. */
+        const int64_t cz = c / layer;
+        const int64_t n0 = s->p.wall_density;
+        virt[c] = (uint8_t)(s->p.walls && (cz == 0 || cz == top) && nn >= 1 && nn < n0);
+        if (nn >= 2 || virt[c]) {
             double S[3] = { 0.0, 0.0, 0.0 };
             for (int64_t j = b; j < e; ++j)
                 for (int d = 0; d < 3; ++d) S[d] = S[d] + s->v[d][j];
             double u[3];
-            for (int d = 0; d < 3; ++d) u[d] = S[d] / (double)nn;
-            double tsum = 0.0;
-            for (int64_t j = b; j < e; ++j) {
-                double w0 = s->v[0][j] - u[0], w1 = s->v[1][j] - u[1], w2 = s->v[2][j] - u[2];
-                tsum = tsum + (((w0 * w0) + (w1 * w1)) + (w2 * w2));
+            if (virt[c]) {
+                uint64_t w[4]; double z[3];
+                draw(s->seed, TAG_VIRT, (uint64_t)s->coll_step, (uint64_t)c, 0, w);
+                normals3(w, z);
+                const double sd = sqrt((double)(n0 - nn)) * sc;
+                for (int d = 0; d < 3; ++d) u[d] = (S[d] + (sd * z[d])) / (double)n0;
+            } else {
+                for (int d = 0; d < 3; ++d) u[d] = S[d] / (double)nn;
+                double tsum = 0.0;
+                for (int64_t j = b; j < e; ++j) {
+                    double w0 = s->v[0][j] - u[0], w1 = s->v[1][j] - u[1], w2 = s->v[2][j] - u[2];
+                    tsum = tsum + (((w0 * w0) + (w1 * w1)) + (w2 * w2));
+                }
+                tterm[c] = (s->p.mass * tsum) / (double)(nn - 1);
             }
-            tterm[c] = (s->p.mass * tsum) / (double)(nn - 1);
             if (s->p.rule == 0) {
                 double nv[3];
                 orc_marsaglia(s->seed, s->coll_step, c, nv);
@@ -880,12 +969,12 @@ static void collide(orc_system* s, int32_t n_md)
     for (int64_t c = 0; c < ncell; ++c) {
         const int64_t r = s->rank_of[c];
         int64_t nn = (int64_t)s->start[r + 1] - s->start[r];
-        if (nn >= 2) { T = T + tterm[c]; ncT++; }
+        if (nn >= 2 && !virt[c]) { T = T + tterm[c]; ncT++; }
         if (flipped[c]) { s->n_bulk++; s->e_rxn += erx[c]; }
     }
     s->temperature = ncT ? T / (3.0 * (double)ncT) : 0.0;
     s->n_cells_T = ncT;
-    free(tterm); free(erx); free(flipped);
+    free(tterm); free(erx); free(flipped); free(virt);
     s->coll_step++;
 }
 

@@ -57,6 +57,11 @@ typedef struct orc_params {
     double  bond_d[ORC_MAXC];
     int32_t cell_order;      /* 0 row-major cell order, 1 compact Hilbert       */
     int32_t pad;
+    /* flows ("Algorithms": constant acceleration; stick walls by bounce-back
+     * and virtual particles).  Only for systems without colloids.          */
+    int32_t walls;           /* 1: plates at z = 0 and z = L_z              */
+    int32_t wall_density;    /* particles of a full cell (virtual fill)    */
+    double  accel[3];        /* constant acceleration of every solvent particle */
 } orc_params;
 
 typedef struct orc_obs {

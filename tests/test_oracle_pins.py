@@ -844,3 +844,190 @@ def test_analysis_schedule_and_series_cap():
     assert acc["md_step"] == [8, 16]
     # histogram totals: three samples, each counting the cylinder's members
     assert acc["hist"].sum() > 0 and acc["hist"].dtype == np.uint64
+
+
+# --------------------------------------------------------------------------
+# Flows ("Algorithms": constant acceleration on the solvent; stick walls by
+# bounce-back and virtual particles in the collision, Lamura et al. 2001)
+
+def _flow(L=(6, 5, 8), rho=4, g=(0.0, 0.0, 0.0), walls=1, **kw):
+    p = W.base_params(L=L, rho=rho, dt=0.01, n_md=5, **kw)
+    p["walls"] = walls
+    p["wall_density"] = rho
+    p["accel"] = tuple(g)
+    return p
+
+
+def test_flow_validation():
+    bad = [dict(_flow(), rule="at"), dict(_flow(), cell_order="hilbert"),
+           dict(_flow(), wall_density=0), _flow(g=(0.0, 0.0, 0.1))]
+    col = _flow(walls=0, g=(0.1, 0.0, 0.0))
+    W.add_colloid(col, (3, 2.5, 4), sigma=1.0)
+    bad.append(col)
+    for p in bad:
+        with pytest.raises(ValueError):
+            oracle.Oracle(p, 1, init=False)
+
+
+def test_constant_acceleration_free_flight():
+    """Periodic box, no walls: velocity-Verlet with a constant force is exact
+    for a parabola, so x(t) = x0 + v0 t + g t^2 / 2 (wrapped) and v = v0 + g t;
+    collisions conserve momentum, so P grows by N m g per unit time."""
+    g = np.array([0.25, -0.5, 0.125])
+    p = _flow(walls=0, g=g)
+    o = oracle.Oracle(p, 3, init=False)
+    s = W.random_state(p, 4)
+    o.set_state(s)
+    n_md = 7
+    o.interval(n_md, collide=False)
+    t = n_md * p["dt"]
+    st = o.get_state()
+    L = np.array(p["L"], dtype=float)[:, None]
+    want = np.mod(s["x"] + s["v"] * t + 0.5 * g[:, None] * t * t, L)
+    d = st["x"] - want
+    d -= L * np.round(d / L)
+    assert np.abs(d).max() < 1e-12
+    assert np.abs(st["v"] - (s["v"] + g[:, None] * t)).max() < 1e-13
+    P0 = s["v"].sum(1)
+    o.run(n_md, 3)
+    P = o.observables()["momentum"]
+    T = t + 3 * t
+    np.testing.assert_allclose(P, P0 + p["n_solvent"] * g * T, rtol=0, atol=1e-9)
+
+
+def test_bounce_back_at_both_plates():
+    """A particle whose drift crosses a plate is reflected: z -> -z' below
+    the bottom, 2 L_z - z' above the top, the velocity reversed, and the
+    in-plane coordinates move back by the part of the step after the
+    crossing: x -> x0 + v (2 t* - dt)."""
+    p = _flow(L=(6, 5, 8), rho=1)
+    n = p["n_solvent"]
+    o = oracle.Oracle(p, 5, init=False)
+    s = W.random_state(p, 6)
+    rng = np.random.default_rng(7)
+    dt = p["dt"]
+    x, v = s["x"], s["v"]
+    # half the particles just above the bottom plate moving down, half just
+    # below the top moving up, each crossing within the step
+    for i in range(n):
+        vz = rng.uniform(0.5, 2.0)
+        frac = rng.uniform(0.05, 0.95)
+        if i % 2 == 0:
+            v[2, i] = -vz
+            x[2, i] = frac * vz * dt
+        else:
+            v[2, i] = vz
+            x[2, i] = 8.0 - frac * vz * dt
+    o.set_state(s)
+    o.interval(1, collide=False)
+    st = o.get_state()
+    z1 = x[2] + v[2] * dt
+    zw = np.where(v[2] < 0, 0.0, 8.0)
+    ts = (zw - x[2]) / v[2]
+    assert np.all((ts > 0) & (ts < dt))
+    np.testing.assert_allclose(st["x"][2], 2 * zw - z1, rtol=0, atol=1e-13)
+    L = np.array(p["L"], dtype=float)
+    for d in range(2):
+        want = np.mod(x[d] + v[d] * (2 * ts - dt), L[d])
+        diff = st["x"][d] - want
+        diff -= L[d] * np.round(diff / L[d])
+        assert np.abs(diff).max() < 1e-13
+    np.testing.assert_allclose(st["v"], -v, rtol=0, atol=0)
+    assert np.all((st["x"][2] >= 0) & (st["x"][2] < 8.0))
+
+
+def test_wall_cell_layers():
+    """With plates the shifted grid has L_z + 1 layers: layer
+    c_z = floor(z - s_z) + 1 holds z in [c_z - 1 + s_z, c_z + s_z)."""
+    p = _flow(L=(6, 5, 7), rho=6)
+    o = oracle.Oracle(p, 8)
+    s = o.get_state()
+    for step in range(4):
+        sh = o.shift(step)
+        keys = o.cell_keys(sh).astype(np.int64)
+        cz = keys // (6 * 5)
+        assert cz.min() >= 0 and cz.max() <= 7
+        rel = s["x"][2] - sh[2] - (cz - 1)
+        assert np.all((rel >= 0) & (rel < 1))
+        # in-plane coordinates stay periodic
+        cx = keys % 6
+        relx = np.mod(s["x"][0] - sh[0] - cx, 6.0)
+        assert np.all((relx >= 0) & (relx < 1))
+
+
+def test_virtual_particles_in_cut_cells_at_zero_temperature():
+    """kT = 0: the virtual particles of a cut cell carry no momentum, so a
+    cut cell whose nn particles share one velocity V has mean u = nn V / n0
+    and every particle leaves with the same velocity, |v' - u| = |V| (1 - nn/n0).
+    Full cells with a common velocity are left unchanged."""
+    p = _flow(L=(4, 4, 6), rho=5, kT=0.0)
+    n0 = p["wall_density"]
+    o = oracle.Oracle(p, 9, init=False)
+    s = W.random_state(p, 10)
+    V = np.array([0.3, -0.2, 0.1])
+    s["v"][:] = V[:, None]
+    o.set_state(s)
+    sh = o.shift(0)
+    keys = o.cell_keys(sh)
+    o.collide(1)
+    st = o.get_state()
+    by_id = np.argsort(st["id"])
+    v1 = st["v"][:, by_id]
+    k0 = keys[np.argsort(s["id"])]
+    cz = k0 // 16
+    checked = 0
+    for key in np.unique(k0):
+        m = k0 == key
+        nn = int(m.sum())
+        vv = v1[:, m]
+        assert np.abs(vv - vv[:, :1]).max() < 1e-15          # one common velocity
+        cut = cz[m][0] in (0, 6)
+        if cut and nn < n0:
+            u = nn * V / n0
+            assert np.linalg.norm(vv[:, 0] - u) == pytest.approx(np.linalg.norm(V) * (1 - nn / n0),
+                                                                 rel=1e-12)
+            assert np.abs(vv[:, 0] - V).max() > 1e-3
+            checked += 1
+        else:
+            np.testing.assert_allclose(vv[:, 0], V, rtol=0, atol=1e-15)
+    assert checked >= 4
+
+
+def _poiseuille_profile(seed, wall_density=None, h=10, g=0.01, tau=0.1, Lxy=16):
+    p = _flow(L=(Lxy, Lxy, h), rho=10, g=(g, 0.0, 0.0))
+    p["dt"] = tau
+    if wall_density is not None:
+        p["wall_density"] = wall_density
+    o = oracle.Oracle(p, seed)
+    o.run(1, 600)                      # about 5 relaxation times h^2 / (pi^2 nu)
+    prof = np.zeros(h)
+    for _ in range(600):
+        o.run(1, 5)
+        s = o.get_state()
+        k = np.minimum(s["x"][2].astype(int), h - 1)
+        prof += np.bincount(k, weights=s["v"][0], minlength=h) / np.bincount(k, minlength=h)
+    prof /= 600
+    zc = np.arange(h) + 0.5
+    c = np.polyfit(zc, prof, 2)        # slab means of a parabola: same curvature
+    _, nu = _closed_forms(tau)
+    vmax = g * h * h / (8 * nu)
+    return c, nu, vmax, np.abs(np.polyval(c, zc) - prof).max()
+
+
+@pytest.mark.slow
+def test_poiseuille_profile_closed_form():
+    """Steady flow between the plates driven by g along x: a parabola whose
+    curvature is -g / (2 nu) (Stokes flow, with the MPCD kinematic viscosity
+    of the closed form, Kikuchi et al. 2003), vanishing near both plates.
+    The virtual particles are what keeps the slip small: without them (fill
+    density 1, so no cell is ever filled) the wall velocity is a third of the
+    centre's."""
+    g = 0.01
+    c, nu, vmax, resid = _poiseuille_profile(31)
+    assert -c[0] == pytest.approx(g / (2 * nu), rel=0.08)
+    assert resid < 0.04 * vmax
+    slip = [np.polyval(c, 0.0) / vmax, np.polyval(c, 10.0) / vmax]
+    assert max(abs(x) for x in slip) < 0.12, slip
+    c0, _, _, _ = _poiseuille_profile(31, wall_density=1)
+    slip0 = [np.polyval(c0, 0.0) / vmax, np.polyval(c0, 10.0) / vmax]
+    assert min(slip0) > 0.25, slip0

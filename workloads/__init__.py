@@ -140,6 +140,18 @@ def large128(precision=64, seed=None, L=128) -> dict:
     return p
 
 
+def poiseuille(L=(64, 64, 32), rho=10, g=0.001, dt=0.01, n_md=10, precision=64) -> dict:
+    """Flow between plates at z = 0 and z = L_z driven by a constant
+    acceleration g along x, no colloid (the paper's poiseuille_flow setup)."""
+    p = base_params(L=L, rho=rho, dt=dt, n_md=n_md, precision=precision)
+    p["walls"] = 1
+    p["wall_density"] = int(rho)
+    p["accel"] = (float(g), 0.0, 0.0)
+    p["name"] = f"poiseuille{L[0]}x{L[1]}x{L[2]}"
+    p["n_collide"] = 2000
+    return p
+
+
 def batch_replicas(n=64, edges=(16, 20, 24, 32), precision=32, seed=None):
     """Replica parameter list for the batched ensemble (per-replica seeds)."""
     rng = np.random.default_rng(BASE_SEED + 4 if seed is None else seed)
