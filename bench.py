@@ -34,6 +34,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -43,7 +45,8 @@ FP64_PEAK_TFLOPS = 78.6
 FLOPS_PER_LIST_STEP = 120.0
 
 
-def algorithmic_bytes(kernel: str, n: int, ncell: int, tb: int, n_cand: int) -> float:
+def algorithmic_bytes(kernel: str, n: int, ncell: int, tb: int, n_cand: int,
+                      flow: bool = False) -> float:
     """Bytes the method must move per launch (not counting re-reads):
     stream_bin  per free particle: read x, v (6 tb) + list flag (1), write x
                 (3 tb) + key/rank (8); cell counters 8 B per cell.
@@ -52,12 +55,15 @@ def algorithmic_bytes(kernel: str, n: int, ncell: int, tb: int, n_cand: int) -> 
                 starts 4 B per cell.
     scatter     per particle: read key/rank (8), write perm (4); starts 4/cell.
     scan_final  per cell: read count (4), write start (4), clear count (4).
+    stream_bin  with a flow (acceleration, plates) every particle also writes
+                its velocity: read x, v (6 tb) + flag (1), write x, v (6 tb)
+                + key/rank (8).
     chain       per list entry: read and write x, v, state (12 tb + 2).
     analysis    per particle: read x (3 tb) and state (1); the histogram
                 updates touch only particles inside a dimer's cylinder."""
     nf = max(n - n_cand, 0)
     if kernel == "stream_bin":
-        return nf * (9 * tb + 9) + 8 * ncell
+        return nf * ((12 if flow else 9) * tb + 9) + 8 * ncell
     if kernel == "collide":
         return n * (12 * tb + 15) + 4 * ncell
     if kernel == "scatter":
@@ -108,6 +114,11 @@ def workload(name: str, precision: int):
         p = W.sphere10(precision=precision)
         return p, 10, W.BASE_SEED + 1, ("sphere10: 10^3 cells, rho 10, N=10,000, 1 WCA sphere "
                                          "sigma 2, tau 0.1 (10 MD steps/collision)")
+    if name == "poiseuille":
+        p = W.poiseuille(precision=precision)
+        return p, 10, W.BASE_SEED + 5, ("poiseuille: 64 x 64 x 32 cells between plates at z = 0 "
+                                         "and 32, rho 10, N=1,310,720, g = 0.001 along x, "
+                                         "tau 0.1 (10 MD steps/collision), no colloid")
     if name == "large128":
         p = W.large128(precision=precision)
         return p, 50, W.BASE_SEED + 3, ("large128: 128^3 cells, rho 10, N=20,971,520, 8 dimers, "
@@ -224,8 +235,9 @@ def run_single(name, precision, steps, warmup, profile_steps, tun):
     import paper_1608_04904_amd as rm
     p, n_md, seed, desc = workload(name, precision)
     n = p["n_solvent"]
-    ncell = p["L"][0] * p["L"][1] * p["L"][2]
+    ncell = p["L"][0] * p["L"][1] * (p["L"][2] + p.get("walls", 0))
     tb = 8 if precision == 64 else 4
+    flow = bool(p.get("walls", 0)) or any(p.get("accel", (0.0, 0.0, 0.0)))
     _log(f"workload {name} N={n} n_md={n_md} precision={precision}")
     s = rm.System(p, seed)
     s.set_tuning(**tun)
@@ -253,12 +265,12 @@ def run_single(name, precision, steps, warmup, profile_steps, tun):
         roof = dict(bound="alu", achieved=achieved, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=achieved / FP64_PEAK_TFLOPS)
     else:
-        achieved = algorithmic_bytes(dom, n, ncell, tb, n_cand) / (avg_ms * 1e-3) / 1e9
+        achieved = algorithmic_bytes(dom, n, ncell, tb, n_cand, flow) / (avg_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS)
     roof.update(traffic=measured_traffic(name, precision, dom), kernel=dom, avg_launch_ms=avg_ms)
     kernels = {k: dict(avg_ms=round(v[0], 5), launches=v[1],
-                       algorithmic_GBps=round(algorithmic_bytes(k, n, ncell, tb, n_cand)
+                       algorithmic_GBps=round(algorithmic_bytes(k, n, ncell, tb, n_cand, flow)
                                               / (v[0] * 1e-3) / 1e9, 1))
                for k, v in kern.items()}
     _log(f"{name} fp{precision} kernels {json.dumps(kernels)}")
@@ -269,6 +281,46 @@ def run_single(name, precision, steps, warmup, profile_steps, tun):
     del s
     torch.cuda.empty_cache()
     return out
+
+
+def poiseuille_profile(precision, warm_intervals=6000, snapshots=200, every=10):
+    """Steady Poiseuille flow of the benchmark channel on the GPU (6000
+    intervals = 600 time units, five relaxation times h^2 / (pi^2 nu)): the x
+    velocity averaged in slabs of unit width across the channel, a quadratic
+    fit, and its curvature against -g / (2 nu) with the MPCD kinematic
+    viscosity of the closed form (Kikuchi et al. 2003); slip = fitted
+    velocity at a plate over the centre velocity."""
+    import torch
+    import paper_1608_04904_amd as rm
+    p, n_md, seed, _ = workload("poiseuille", precision)
+    h, g = p["L"][2], p["accel"][0]
+    tau = n_md * p["dt"]
+    M, a = p["rho"], p["alpha"]
+    gm = M - 1 + math.exp(-M)
+    nu = tau / 2 * (5 * M / (gm * (2 - math.cos(a) - math.cos(2 * a))) - 1) + \
+        (1 / (18 * tau)) * (gm / M) * (1 - math.cos(a))
+    s = rm.System(p, seed)
+    s.step(n_md, warm_intervals)
+    prof = np.zeros(h)
+    for _ in range(snapshots):
+        s.step(n_md, every)
+        st = s.get_state()
+        k = np.minimum(st["x"][2].astype(int), h - 1)
+        prof += np.bincount(k, weights=st["v"][0], minlength=h) / np.bincount(k, minlength=h)
+    prof /= snapshots
+    ob = s.observables(raise_on_flags=False)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    zc = np.arange(h) + 0.5
+    c = np.polyfit(zc, prof, 2)
+    vmax = g * h * h / (8 * nu)
+    return dict(curvature_over_closed_form=float(-c[0] / (g / (2 * nu))),
+                slip_over_vmax=[float(np.polyval(c, 0.0) / vmax), float(np.polyval(c, float(h)) / vmax)],
+                centre_velocity=float(prof[h // 2 - 1: h // 2 + 1].mean()), closed_form_vmax=vmax,
+                temperature=ob["temperature"],
+                sample=f"{warm_intervals} intervals to steady state, then {snapshots} snapshots "
+                       f"{every} intervals apart")
 
 
 ANALYSIS = dict(every=1, hist_nz=64, hist_nr=32, hist_zmax=12.0, hist_rmax=10.0)
@@ -444,6 +496,13 @@ def main():
                 value=r["value"], roofline=r["roofline"],
                 kernels={k: r["kernels"][k] for k in ("stream_bin", "collide", "chain")
                          if k in r["kernels"]})
+        for prec in (64, 32):
+            _log(f"poiseuille fp{prec}")
+            r = run_single("poiseuille", prec, args.steps, args.warmup, args.profile_steps, tun)
+            extras[f"poiseuille_fp{prec}"] = dict(value=r["value"], roofline=r["roofline"],
+                                                 kernels=r["kernels"])
+        _log("poiseuille steady profile (fp32)")
+        extras["poiseuille_profile_fp32"] = poiseuille_profile(32)
         for wl, st in (("dimer32", args.steps), ("large128", 6)):
             _log(f"dimer analysis, {wl}")
             extras[f"analysis_{wl}_fp64"] = run_analysis(wl, 64, st, 2, tun)

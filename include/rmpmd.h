@@ -96,6 +96,25 @@ typedef struct rmp_params {
                                   enclosing power-of-two cube, "Implementation
                                   and architecture": cell sorting)              */
     int32_t pad_order;
+    /* Flows ("Algorithms": flows from a constant acceleration of the solvent;
+     * stick walls by the bounce-back rule with virtual particles in the
+     * collision, Lamura et al. 2001).  Only for systems without colloids
+     * (n_colloids = 0); then there is no Verlet list. */
+    int32_t walls;             /* 1: plates at z = 0 and z = L[2]; the drift of a
+                                  particle that crosses one is cut at the
+                                  crossing, its velocity reversed and the rest
+                                  of the step travelled back.  The shifted grid
+                                  then has L[2] + 1 layers; cells of the first
+                                  and last layer holding fewer than
+                                  wall_density particles get the summed
+                                  momentum of the missing ones, drawn from
+                                  Maxwell-Boltzmann at rest, in their mean
+                                  velocity.  Needs rule 0, cell_order 0 and
+                                  accel[2] = 0.                                  */
+    int32_t wall_density;      /* particles of a full cell, 1 .. 1024 (walls)  */
+    double  accel[3];          /* constant acceleration of every solvent
+                                  particle, applied as velocity-Verlet half
+                                  kicks around each drift (0: none)             */
 } rmp_params;
 
 /* FP64 observables.  `potential` is the colloid-solvent plus colloid-colloid

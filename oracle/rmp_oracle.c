@@ -177,6 +177,11 @@ static double wrapX(double X, double L)
     return w;
 }
 
+static int has_flow(const orc_params* p)
+{
+    return p->walls != 0 || p->accel[0] != 0.0 || p->accel[1] != 0.0 || p->accel[2] != 0.0;
+}
+
 static void *xalloc(size_t n) { void* q = calloc(n ? n : 1, 1); return q; }
 
 /* Position of the point (x, y, z) along the Hilbert curve through the
@@ -248,11 +253,6 @@ static void hilbert_order(const int32_t L[3], uint32_t* rank_of, uint32_t* cell_
         rank_of[pairs[2 * r + 1]] = (uint32_t)r;
     }
     free(pairs);
-}
-
-static int has_flow(const orc_params* p)
-{
-    return p->walls != 0 || p->accel[0] != 0.0 || p->accel[1] != 0.0 || p->accel[2] != 0.0;
 }
 
 orc_system* orc_create(const orc_params* p, uint64_t seed)
@@ -538,6 +538,11 @@ static void compute_forces(orc_system* s)
 
 int orc_build_list(orc_system* s, int32_t n_md)
 {
+    if (has_flow(&s->p)) {
+        /* flows have no colloids: every particle streams, no list */
+        s->ncand = 0;
+        return 0;
+    }
     double Xw[ORC_MAXC][3];
     wrapped_colloids(s, Xw);
     double tau = (double)n_md * s->p.dt;

@@ -34,6 +34,7 @@ class Params(C.Structure):
         ("eps_cc", (C.c_double * 2) * 2), ("bond_a", C.c_int32 * MAX_COLLOIDS),
         ("bond_b", C.c_int32 * MAX_COLLOIDS), ("bond_d", C.c_double * MAX_COLLOIDS),
         ("cell_order", C.c_int32), ("pad_order", C.c_int32),
+        ("walls", C.c_int32), ("wall_density", C.c_int32), ("accel", C.c_double * 3),
     ]
 
 CELL_ORDERS = {"row": 0, "hilbert": 1}
@@ -171,6 +172,10 @@ def make_params(p: dict) -> Params:
     q.rule = {"srd": 0, "at": 1}[p.get("rule", "srd")]
     q.cand_capacity = int(p.get("cand_capacity", 0))
     q.cell_order = CELL_ORDERS[p.get("cell_order", "row")]
+    q.walls = int(p.get("walls", 0))
+    q.wall_density = int(p.get("wall_density", 0))
+    for d, g in enumerate(p.get("accel", (0.0, 0.0, 0.0))):
+        q.accel[d] = float(g)
     cols = p["colloids"]
     if len(cols) > MAX_COLLOIDS:
         raise ValueError("too many colloids")

@@ -53,6 +53,11 @@ int64_t auto_capacity(const rmp_params* p)
     return c;
 }
 
+bool has_flow(const rmp_params* p)
+{
+    return p->walls != 0 || p->accel[0] != 0.0 || p->accel[1] != 0.0 || p->accel[2] != 0.0;
+}
+
 rmp_status validate(const rmp_params* p)
 {
     if (!p) return RMP_EINVAL;
@@ -69,6 +74,14 @@ rmp_status validate(const rmp_params* p)
     if (p->n_bonds < 0 || p->n_bonds > RMP_MAX_COLLOIDS / 2) return RMP_EINVAL;
     if (p->cell_order != 0 && p->cell_order != 1) return RMP_EINVAL;
     if (p->cand_capacity < 0) return RMP_EINVAL;
+    if (p->walls != 0 && p->walls != 1) return RMP_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(p->accel[d])) return RMP_EINVAL;
+    if (has_flow(p) && (p->n_colloids != 0 || p->n_bonds != 0)) return RMP_EINVAL;
+    if (p->walls && (p->rule != 0 || p->cell_order != 0 || p->accel[2] != 0.0 ||
+                     p->wall_density < 1 || p->wall_density > 1024))
+        return RMP_EINVAL;
+    if ((int64_t)p->L[0] * p->L[1] * (p->L[2] + 1) > (int64_t)1 << 31) return RMP_EINVAL;
     int used[RMP_MAX_COLLOIDS] = {0};
     for (int c = 0; c < p->n_colloids; ++c) {
         if (!(p->sigma[c] > 0.0) || !(p->colloid_mass[c] > 0.0)) return RMP_EINVAL;
@@ -95,7 +108,8 @@ Sizes sizes_of(const rmp_params* p)
 {
     Sizes s;
     s.n = p->n_solvent;
-    s.ncell = (int64_t)p->L[0] * p->L[1] * p->L[2];
+    // with walls the shifted grid needs one layer more across the channel
+    s.ncell = (int64_t)p->L[0] * p->L[1] * (p->L[2] + (p->walls ? 1 : 0));
     s.n_chunks = (int32_t)((s.n + CHUNK - 1) / CHUNK);
     if (s.n_chunks < 1) s.n_chunks = 1;
     s.n_tiles_max = (int32_t)((s.ncell + MIN_TILE_CELLS - 1) / MIN_TILE_CELLS);
@@ -322,6 +336,11 @@ void fill_desc(rmp_batch* b, Replica& r)
         D.Ld[d] = (double)p->L[d];
         D.halfL[d] = 0.5 * D.Ld[d];
     }
+    D.flow = has_flow(p) ? 1 : 0;
+    D.walls = p->walls;
+    D.wall_n0 = p->wall_density;
+    if (p->walls) D.L[2] = p->L[2] + 1;
+    for (int d = 0; d < 3; ++d) D.g[d] = p->accel[d];
     D.active = 1;
     D.n = s.n;
     D.ncell = s.ncell;

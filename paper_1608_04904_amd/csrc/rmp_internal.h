@@ -20,7 +20,7 @@ constexpr int32_t KEY_ROW = -2;                      // row-major: rank = cell i
 // Philox stream tags (key word 1); key word 0 is the replica seed.
 enum : uint64_t {
     TAG_SHIFT = 1, TAG_ROT = 2, TAG_BULK = 3, TAG_CAT = 4, TAG_THERMO = 5,
-    TAG_INIT_POS = 6, TAG_INIT_VEL = 7
+    TAG_INIT_POS = 6, TAG_INIT_VEL = 7, TAG_VIRT = 8
 };
 
 // Per-replica colloid parameters with host-derived constants.
@@ -65,7 +65,7 @@ struct Analysis {
 
 // Per-replica descriptor, written by the host.
 struct RepDesc {
-    int32_t L[3];
+    int32_t L[3];              // cell grid (with walls L[2] is one layer more than the box)
     int32_t active;
     int64_t n, ncell;
     int32_t n_md, rule;
@@ -76,6 +76,11 @@ struct RepDesc {
     double Ld[3], halfL[3];
     double dt, h, tau, vscale, mass, ca, sa, cat_prob, skin_half2;
     int32_t bulk_on, pad1;
+    int32_t flow;              // constant acceleration and/or walls: every particle streams
+    int32_t walls;             // plates at z = 0 and z = Ld[2]
+    int32_t wall_n0;           // particles of a full cell (virtual fill of cut cells)
+    int32_t pad2;
+    double g[3];               // constant acceleration
     uint64_t seed;
     void* x[2];                // [3][n] storage-type arrays, double-buffered
     void* v[2];

@@ -172,6 +172,11 @@ __device__ __forceinline__ uint32_t cell_key(const RepDesc& D, double x0, double
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         double fq = floor(xs[d] - s[d]);
+        if (d == 2 && D.walls) {
+            // plates: layers floor(z - s) + 1 in [0, L_z], not periodic
+            c[d] = (fq >= -1.0 && fq < (double)(D.L[d] - 1)) ? (int64_t)fq + 1 : 0;
+            continue;
+        }
         int64_t q = (fq >= -1.0 && fq < (double)D.L[d]) ? (int64_t)fq : 0;   // NaN-safe
         if (q < 0) q += D.L[d];
         c[d] = q;
@@ -189,6 +194,7 @@ __device__ __forceinline__ bool is_candidate(const RepDesc& D, const ColloidPara
                                              double x0, double x1, double x2,
                                              double v0, double v1, double v2)
 {
+    if (D.flow) return false;     // flows: no colloids, every particle streams
     if (st & 2) return true;
     if (nc == 0) return false;
     double vv = dot3(v0, v1, v2, v0, v1, v2);
@@ -497,7 +503,55 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t* count, uint32_t key, boo
     return base + (uint32_t)(lane - h);
 }
 
-// Particles outside the Verlet list feel no force during the interval: n_md
+// One streaming step under the constant acceleration g, with the plates at
+// z = 0 and z = L_z when present: half kick, drift, half kick; a drift that
+// crosses a plate is cut at the crossing time, the velocity reversed
+// (bounce-back) and the rest of the step travelled back.
+template <class T>
+__device__ __forceinline__ T below(T L);
+template <>
+__device__ __forceinline__ double below<double>(double L) { return nextafter(L, 0.0); }
+template <>
+__device__ __forceinline__ float below<float>(float L) { return nextafterf(L, 0.0f); }
+
+template <class T>
+__device__ __forceinline__ void flow_step(T (&x)[3], T (&v)[3], const T (&g)[3], T dt, T hdt,
+                                          const T (&L)[3], bool walls)
+{
+    T y[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        v[d] = tfma(hdt, g[d], v[d]);
+        y[d] = tfma(dt, v[d], x[d]);
+    }
+    if (walls) {
+        if (y[2] < (T)0 || y[2] >= L[2]) {
+            const T wz = y[2] < (T)0 ? (T)0 : L[2];
+            const T ts = (wz - x[2]) / v[2];
+            const T rem = dt - ts;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T xc = tfma(ts, v[d], x[d]);
+                v[d] = -v[d];
+                y[d] = tfma(rem, v[d], xc);
+            }
+            if (y[2] >= L[2]) y[2] = below<T>(L[2]);
+            if (y[2] < (T)0) y[2] = (T)0;
+        }
+        x[0] = wrap_coord<T>(y[0], L[0]);
+        x[1] = wrap_coord<T>(y[1], L[1]);
+        x[2] = y[2];
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[d] = wrap_coord<T>(y[d], L[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) v[d] = tfma(hdt, g[d], v[d]);
+}
+
+// Flows (constant acceleration, plates) stream every particle with flow_step
+// and write back positions and velocities.  Otherwise:
+// particles outside the Verlet list feel no force during the interval: n_md
 // drifts x <- fma(dt, v, x) with a periodic wrap after each.  The drift of a
 // coordinate is monotone, so if its final value is still inside the box no
 // wrap occurred and the per-step wrap can be skipped; otherwise the drifts
@@ -525,7 +579,10 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
     const T dt = (T)D.dt;
     const T Lt[3] = {(T)D.Ld[0], (T)D.Ld[1], (T)D.Ld[2]};
     T* xs[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
-    const T* vs[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
+    T* vs[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
+    const bool flow = D.flow != 0;
+    const T g[3] = {(T)D.g[0], (T)D.g[1], (T)D.g[2]};
+    const T hdt = (T)(0.5 * D.dt);
     const int span = CHUNK / wg_per_chunk;
     const int64_t base = (int64_t)chunk * CHUNK + (int64_t)sub * span;
     for (int j0 = 0; j0 < span; j0 += blockDim.x) {
@@ -537,17 +594,23 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
             T x[3], v[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) { x[d] = xs[d][i]; v[d] = vs[d][i]; }
+            if (flow) {
+                for (int k = 0; k < nmd; ++k) flow_step<T>(x, v, g, dt, hdt, Lt, D.walls != 0);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                T y = x[d];
-                for (int k = 0; k < nmd; ++k) y = tfma(dt, v[d], y);
-                const bool inside = (v[d] >= (T)0) ? (y < Lt[d]) : (y >= (T)0);
-                if (!inside) {
-                    y = x[d];
-                    for (int k = 0; k < nmd; ++k) y = wrap_coord<T>(tfma(dt, v[d], y), Lt[d]);
+                for (int d = 0; d < 3; ++d) { xs[d][i] = x[d]; vs[d][i] = v[d]; }
+            } else {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    T y = x[d];
+                    for (int k = 0; k < nmd; ++k) y = tfma(dt, v[d], y);
+                    const bool inside = (v[d] >= (T)0) ? (y < Lt[d]) : (y >= (T)0);
+                    if (!inside) {
+                        y = x[d];
+                        for (int k = 0; k < nmd; ++k) y = wrap_coord<T>(tfma(dt, v[d], y), Lt[d]);
+                    }
+                    x[d] = y;
+                    xs[d][i] = y;
                 }
-                x[d] = y;
-                xs[d][i] = y;
             }
             key = cell_key(D, (double)x[0], (double)x[1], (double)x[2], s);
         }
@@ -1419,6 +1482,7 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
     __shared__ uint8_t s_cell[COLL_CAP];
     __shared__ double s_u[COLL_TCMAX][3], s_n[COLL_TCMAX][3];
     __shared__ int32_t s_flip[COLL_TCMAX], s_nn[COLL_TCMAX];
+    __shared__ uint8_t s_go[COLL_TCMAX];
     __shared__ double s_Xw[MAXC][3];
     __shared__ int32_t s_group[2];
     __shared__ double sred[COLL_NT / 64 + 1];
@@ -1614,21 +1678,40 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
             const int nn = ce - cb;
             s_nn[lc] = nn;
             s_flip[lc] = -1;
-            if (nn >= 2) {
+            // Lamura et al. (2001): a cell of the first or last layer (cut by
+            // a plate) with fewer than n0 particles holds n0 - n virtual ones
+            // at rest on average; only their summed momentum enters, a normal
+            // vector of variance (n0 - n) kT / m per component
+            const int64_t cz = cell / ((int64_t)D.L[0] * D.L[1]);
+            const bool virt = D.walls && (cz == 0 || cz == D.L[2] - 1) && nn >= 1 && nn < D.wall_n0;
+            s_go[lc] = (nn >= 2 || virt) ? 1 : 0;
+            if (nn >= 2 || virt) {
                 double S0 = 0.0, S1 = 0.0, S2 = 0.0;
                 for (int q = cb; q < ce; ++q) {
                     S0 = S0 + s_v[0][q];
                     S1 = S1 + s_v[1][q];
                     S2 = S2 + s_v[2][q];
                 }
-                const double u0 = S0 / (double)nn, u1 = S1 / (double)nn, u2 = S2 / (double)nn;
-                double tsum = 0.0;
-                for (int q = cb; q < ce; ++q) {
-                    double w0 = s_v[0][q] - u0, w1 = s_v[1][q] - u1, w2 = s_v[2][q] - u2;
-                    tsum = tsum + dot3(w0, w1, w2, w0, w1, w2);
+                double u0, u1, u2;
+                if (virt) {
+                    uint64_t wv[4]; double z[3];
+                    philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_VIRT, wv);
+                    normals3(wv, z);
+                    const double sd = sqrt((double)(D.wall_n0 - nn)) * D.vscale;
+                    const double n0 = (double)D.wall_n0;
+                    u0 = (S0 + (sd * z[0])) / n0;
+                    u1 = (S1 + (sd * z[1])) / n0;
+                    u2 = (S2 + (sd * z[2])) / n0;
+                } else {
+                    u0 = S0 / (double)nn; u1 = S1 / (double)nn; u2 = S2 / (double)nn;
+                    double tsum = 0.0;
+                    for (int q = cb; q < ce; ++q) {
+                        double w0 = s_v[0][q] - u0, w1 = s_v[1][q] - u1, w2 = s_v[2][q] - u2;
+                        tsum = tsum + dot3(w0, w1, w2, w0, w1, w2);
+                    }
+                    t_sum += (D.mass * tsum) / (double)(nn - 1);
+                    t_cells += 1.0;
                 }
-                t_sum += (D.mass * tsum) / (double)(nn - 1);
-                t_cells += 1.0;
                 s_u[lc][0] = u0; s_u[lc][1] = u1; s_u[lc][2] = u2;
                 if constexpr (RULE == 0) {
                     double nax[3];
@@ -1669,7 +1752,7 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
             const int lc = s_cell[j];
             const uint32_t p = s_src[j];
             double v3[3] = {s_v[0][j], s_v[1][j], s_v[2][j]};
-            if (s_nn[lc] >= 2) {
+            if (s_go[lc]) {
                 const double u0 = s_u[lc][0], u1 = s_u[lc][1], u2 = s_u[lc][2];
                 if constexpr (RULE == 0) {
                     const double nax[3] = {s_n[lc][0], s_n[lc][1], s_n[lc][2]};

@@ -106,6 +106,27 @@ def test_analysis_bytes_and_validation_on_host():
         analysis_bytes(nob, a)
 
 
+def test_flow_parameters_validated_on_host():
+    import workloads as W
+    from paper_1608_04904_amd import _capi, workspace_bytes
+
+    def flow(walls=1, g=(0.0, 0.0, 0.0), **kw):
+        p = W.base_params(L=(6, 6, 6), rho=5, **kw)
+        p.update(walls=walls, wall_density=5, accel=g)
+        return p
+    assert workspace_bytes(flow()) > workspace_bytes(W.base_params(L=(6, 6, 6), rho=5))  # one layer more
+    workspace_bytes(flow(walls=0, g=(0.1, 0.0, 0.2), rule="at"))   # periodic acceleration: any rule
+    bad = [flow(rule="at"), dict(flow(), cell_order="hilbert"), flow(g=(0.0, 0.0, 0.1)),
+           dict(flow(), wall_density=0), dict(flow(), wall_density=2000), dict(flow(), walls=2),
+           flow(walls=0, g=(float("nan"), 0.0, 0.0))]
+    col = flow(walls=0, g=(0.1, 0.0, 0.0))
+    W.add_colloid(col, (3, 3, 3), sigma=1.0)
+    bad.append(col)
+    for p in bad:
+        with pytest.raises(_capi.RmpError):
+            workspace_bytes(p)
+
+
 def test_product_package_has_no_oracle_dependency():
     pkg = os.path.join(ROOT, "paper_1608_04904_amd")
     for dirpath, _, files in os.walk(pkg):
