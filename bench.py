@@ -147,19 +147,22 @@ def cpu_baseline(p, n_md, seed, budget_s: float):
                        f"({p['n_solvent']} particles), {dt:.1f} s")
 
 
-def fp32_drift(intervals: int, oracle_intervals: int, with_oracle: bool):
-    """FP32 state against FP64 from the same initial state (dimer32): total
-    momentum P = sum m v (solvent and colloids, conserved exactly by the
-    method), total energy E = KE + U - e_rxn (e_rxn: potential change booked
-    at species flips), and the dimer centre-of-mass displacement.  The FP64
-    run is checked bit for bit against the CPU oracle over the first
-    `oracle_intervals` intervals, so it stands for the oracle trajectory."""
-    import numpy as np
+def fp32_drift(intervals: int, oracle_intervals: int, with_oracle: bool, name: str = "dimer32"):
+    """FP32 state against FP64 from the same initial state: total momentum
+    P = sum m v (solvent and colloids, conserved exactly by the method), total
+    energy E = KE + U - e_rxn (e_rxn: potential change booked at species
+    flips), and the dimers' centre-of-mass displacements (MSD averaged over
+    the dimers).  The FP64 run is checked bit for bit against the CPU oracle
+    over the first `oracle_intervals` intervals, so it stands for the oracle
+    trajectory."""
     import torch
     import paper_1608_04904_amd as rm
     import workloads as W
-    p64 = W.dimer32(precision=64)
-    p32 = W.dimer32(precision=32)
+    make = W.dimer32 if name == "dimer32" else W.large128
+    p64 = make(precision=64)
+    p32 = make(precision=32)
+    bonds = p64["bonds"]
+    masses = np.array([c["mass"] for c in p64["colloids"]])
     n_md = int(p64["n_md"])
     seed = W.BASE_SEED + 77
     st0 = W.random_state(p64, seed)
@@ -175,7 +178,8 @@ def fp32_drift(intervals: int, oracle_intervals: int, with_oracle: bool):
             P.append(np.array(o["momentum"]))
             E.append(o["ke_solvent"] + o["ke_colloid"] + o["potential"] - o["e_rxn"])
             X = np.array(o["colloid_X"])
-            R.append(X.mean(axis=0))
+            R.append(np.array([(masses[a] * X[a] + masses[b] * X[b]) / (masses[a] + masses[b])
+                               for a, b, _ in bonds]))
         torch.cuda.synchronize()
         runs[prec] = dict(P=np.array(P), E=np.array(E), R=np.array(R), flags=o["flags"])
         if prec == 64 and with_oracle:
@@ -195,19 +199,19 @@ def fp32_drift(intervals: int, oracle_intervals: int, with_oracle: bool):
     n = p64["n_solvent"]
     pscale = float(np.sqrt(n * p64["mass"] * p64["kT"]))     # thermal momentum of the system
     e0 = float(r64["E"][0])
-    msd64 = float(np.sum((r64["R"][-1] - r64["R"][0]) ** 2))
-    msd32 = float(np.sum((r32["R"][-1] - r32["R"][0]) ** 2))
+    msd64 = float(np.mean(np.sum((r64["R"][-1] - r64["R"][0]) ** 2, axis=1)))
+    msd32 = float(np.mean(np.sum((r32["R"][-1] - r32["R"][0]) ** 2, axis=1)))
     out = dict(
-        intervals=intervals, md_steps=intervals * n_md,
+        workload=name, n_dimers=len(bonds), intervals=intervals, md_steps=intervals * n_md,
         momentum_drift_fp64=float(np.max(np.linalg.norm(r64["P"] - r64["P"][0], axis=1)) / pscale),
         momentum_drift_fp32=float(np.max(np.linalg.norm(r32["P"] - r32["P"][0], axis=1)) / pscale),
         energy_drift_fp64=float(np.max(np.abs(r64["E"] - e0)) / abs(e0)),
         energy_drift_fp32=float(np.max(np.abs(r32["E"] - r32["E"][0])) / abs(e0)),
         energy_fp32_vs_fp64=float(np.max(np.abs(r32["E"] - r64["E"])) / abs(e0)),
         dimer_msd_fp64=msd64, dimer_msd_fp32=msd32,
-        # the two trajectories decorrelate (the dynamics is chaotic): distance
-        # between the FP32 and FP64 dimer centres after k intervals
-        dimer_com_diff={str(k): float(np.linalg.norm(r32["R"][k] - r64["R"][k]))
+        # the two trajectories decorrelate (the dynamics is chaotic): rms
+        # distance between the FP32 and FP64 dimer centres after k intervals
+        dimer_com_diff={str(k): float(np.sqrt(np.mean(np.sum((r32["R"][k] - r64["R"][k]) ** 2, axis=1))))
                         for k in (1, 2, 5, 10, 20, 50, 100, 200) if k <= intervals},
         flags=[int(r64["flags"]), int(r32["flags"])],
         note="momentum drifts are max_t |P(t) - P(0)| / sqrt(N m kT); energy drifts max_t |E(t) - E(0)| / E(0)")
@@ -508,6 +512,8 @@ def main():
             extras[f"analysis_{wl}_fp64"] = run_analysis(wl, 64, st, 2, tun)
         _log("FP32 against FP64 drift, dimer32")
         extras["fp32_drift"] = fp32_drift(200, 3, not args.no_cpu)
+        _log("FP32 against FP64 drift, large128")
+        extras["fp32_drift_large128"] = fp32_drift(40, 1, not args.no_cpu, name="large128")
     cpu = None
     if not args.no_cpu:
         _log("timing the CPU oracle")

@@ -1123,6 +1123,18 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     if (Gact < 1) Gact = 1;
     if (Gact > D.G) Gact = D.G;
     if (g >= Gact) return;
+    if (nc == 0 && ncand == 0) {
+        // no colloid and an empty list (flows, bare solvent): nothing moves
+        // in the chain; close the interval's counters as the full path would
+        if (g == 0 && threadIdx.x == 0) {
+            D.epart[0] = 0.0;
+            D.epart[1] = 0.0;
+            rs->U = 0.0;
+            rs->md_step = rs->md_step + D.n_md;
+            rs->n_cand_used = 0;
+        }
+        return;
+    }
     int Gpad = 1;
     while (Gpad < Gact) Gpad <<= 1;
 
