@@ -198,9 +198,10 @@ typedef struct rmp_tuning {
     int32_t chain_resident;    /* chain workgroups taken to fit on the device at
                                   once when raising chain_k (0: the device's
                                   own occupancy figure)                         */
-    int32_t chain_block;       /* MD-chain workgroup size: 256, 512 (one list
-                                  entry per thread), or 0: 512 when a list
-                                  needs more than one entry per thread at 256 */
+    int32_t chain_block;       /* MD-chain workgroup size: 256, 512 (one or two
+                                  list entries per thread), or 0: 512 when a
+                                  list needs more than one entry per thread at
+                                  256 threads                                   */
 } rmp_tuning;
 rmp_status rmp_set_tuning(rmp_system* s, const rmp_tuning* t);
 rmp_status rmp_get_tuning(rmp_system* s, rmp_tuning* t);

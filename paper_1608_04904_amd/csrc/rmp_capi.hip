@@ -206,7 +206,7 @@ struct rmp_batch {
     RepDesc* d_desc = nullptr;
     int32_t* d_prefix[6] = {};
     uint32_t* d_tick = nullptr;     // chain work-list tickets (two counters)
-    int32_t chain_resident[4] = {}; // chain workgroups the device holds at once, per shape
+    int32_t chain_resident[5] = {}; // chain workgroups the device holds at once, per shape
     int32_t nc_common = -1;         // colloid count shared by every occupied slot, -1 if mixed
     std::vector<Replica> reps;
     std::vector<RepDesc> hdesc;
@@ -290,9 +290,11 @@ int chain_resident_of(const rmp_batch* b, int q)
 // system's list fits its workgroups, then raised while the batch's chain
 // workgroups exceed what the device holds at once (past that point they
 // would run in waves, each wave paying the full per-step exchange latency).
-// 512-thread workgroups with one entry per thread are used when asked for,
-// or, by default, when a system's list needs more than one entry per thread
-// at 256 threads and the 512-thread shape still fits on the device.
+// 512-thread workgroups with one or two entries per thread are used when
+// asked for, or, by default, when a system's list needs more than one entry
+// per thread at 256 threads and the 512-thread shape still fits on the
+// device (measured at 128^3 with 8 dimers: 512 x 1 1.95 ms, 256 x 4 2.14 ms,
+// 256 x 2 2.36 ms per 50-step chain launch).
 ChainShape chain_shape_of(const rmp_batch* b)
 {
     int k = b->tun.chain_k;
@@ -306,6 +308,8 @@ ChainShape chain_shape_of(const rmp_batch* b)
                          (b->tun.chain_block <= 0 && cap_max > (int64_t)MAX_G * 256);
     if (want512 && cap_max <= (int64_t)MAX_G * 512 && chain_groups(b, 1, 512) <= chain_resident_of(b, 3))
         return ChainShape{512, 1, 3};
+    if (want512 && cap_max <= (int64_t)MAX_G * 1024 && chain_groups(b, 2, 512) <= chain_resident_of(b, 4))
+        return ChainShape{512, 2, 4};
     return ChainShape{256, k, k == 1 ? 0 : (k == 2 ? 1 : 2)};
 }
 
@@ -639,7 +643,8 @@ rmp_status launch_chain(rmp_batch* b, hipStream_t s)
         case 0: launch_chain_shape<T, 1, 256>(b, s, g, ticket, nc, w); break;
         case 1: launch_chain_shape<T, 2, 256>(b, s, g, ticket, nc, w); break;
         case 2: launch_chain_shape<T, 4, 256>(b, s, g, ticket, nc, w); break;
-        default: launch_chain_shape<T, 1, 512>(b, s, g, ticket, nc, w); break;
+        case 3: launch_chain_shape<T, 1, 512>(b, s, g, ticket, nc, w); break;
+        default: launch_chain_shape<T, 2, 512>(b, s, g, ticket, nc, w); break;
     }
     return last_launch("k_chain");
 }
@@ -883,19 +888,21 @@ rmp_status batch_init(rmp_batch* b, int32_t nslots, int32_t precision, void* ctl
         int dev = 0, ncu = 0;
         HIPCHK(hipGetDevice(&dev));
         HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        int per[4] = {0, 0, 0, 0};
+        int per[5] = {0, 0, 0, 0, 0};
         if (precision == 64) {
             HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<double, 1, false, 0, 256>, 256, 0));
             HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<double, 2, false, 0, 256>, 256, 0));
             HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<double, 4, false, 0, 256>, 256, 0));
             HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[3], k_chain<double, 1, false, 0, 512>, 512, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[4], k_chain<double, 2, false, 0, 512>, 512, 0));
         } else {
             HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<float, 1, false, 0, 256>, 256, 0));
             HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<float, 2, false, 0, 256>, 256, 0));
             HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<float, 4, false, 0, 256>, 256, 0));
             HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[3], k_chain<float, 1, false, 0, 512>, 512, 0));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[4], k_chain<float, 2, false, 0, 512>, 512, 0));
         }
-        for (int q = 0; q < 4; ++q) b->chain_resident[q] = std::max(1, per[q]) * std::max(1, ncu);
+        for (int q = 0; q < 5; ++q) b->chain_resident[q] = std::max(1, per[q]) * std::max(1, ncu);
     }
     b->reps.assign(nslots, Replica{});
     b->hdesc.assign(nslots, RepDesc{});

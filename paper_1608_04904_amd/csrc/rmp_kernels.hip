@@ -110,6 +110,32 @@ __device__ __forceinline__ double block_sum(double v, double* sbuf)
     return r;
 }
 
+// N sums over the workgroup; sbuf holds (NT / 64 + 1) * N doubles.  Every
+// thread receives the totals.
+template <int NT, int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], double* sbuf)
+{
+    constexpr int NW = NT / 64;
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = wave_tree_sum(v[q]);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < N; ++q) sbuf[wave * N + q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double a = 0.0;
+#pragma unroll 4
+        for (int w = 0; w < NW; ++w) a = a + sbuf[w * N + threadIdx.x];
+        sbuf[NW * N + threadIdx.x] = a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = sbuf[NW * N + q];
+    __syncthreads();
+}
+
 template <int NT>
 __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* sbuf)
 {
@@ -377,51 +403,80 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(Work w, int after_collision
     if (!D.active) return;
     RepState* rs = D.rs;
     __shared__ uint32_t sbuf[16];
-    __shared__ double dbuf[32];
+    __shared__ double dbuf[17 * 6];
     const int t = threadIdx.x;
     const int nch = D.n_chunks;
     const int per = (nch + 1023) / 1024;
     uint32_t local = 0;
-    for (int k = 0; k < per; ++k) {
-        int q = t * per + k;
-        if (q < nch) local += D.chunk_cnt[q];
+    // loads in batches of 8 so that they are in flight together (a single
+    // workgroup walks all chunks: latency, not bandwidth, bounds this)
+    constexpr int UB = 4;
+    const int q0 = t * per;
+    int kk = 0;
+    for (; kk + UB <= per; kk += UB) {
+        uint32_t c[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) c[u] = q0 + kk + u < nch ? D.chunk_cnt[q0 + kk + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < UB; ++u) local += c[u];
     }
+    for (; kk < per; ++kk)
+        if (q0 + kk < nch) local += D.chunk_cnt[q0 + kk];
     uint32_t total;
     uint32_t pre = block_exscan_u32<1024>(local, sbuf, &total);
-    for (int k = 0; k < per; ++k) {
-        int q = t * per + k;
+    kk = 0;
+    for (; kk + UB <= per; kk += UB) {
+        uint32_t c[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) c[u] = q0 + kk + u < nch ? D.chunk_cnt[q0 + kk + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            if (q0 + kk + u < nch) D.chunk_off[q0 + kk + u] = pre;
+            pre += c[u];
+        }
+    }
+    for (; kk < per; ++kk) {
+        const int q = q0 + kk;
         if (q < nch) {
             D.chunk_off[q] = pre;
             pre += D.chunk_cnt[q];
         }
     }
     if (after_collision) {
-        double ts = 0.0, tc = 0.0, du = 0.0, nb = 0.0;
-        for (int k = t; k < D.n_tiles; k += 1024) {
-            ts += D.tpart[(int64_t)k * 4 + 0];
-            tc += D.tpart[(int64_t)k * 4 + 1];
-            du += D.tpart[(int64_t)k * 4 + 2];
-            nb += D.tpart[(int64_t)k * 4 + 3];
+        // tile partials (temperature sum and cells, reaction energy, bulk
+        // flips): two independent accumulators keep two 32-byte loads in
+        // flight (more would spill at 1024 threads); the order is fixed for
+        // a given tile count
+        double a[2][4] = {};
+        const double4* tp = reinterpret_cast<const double4*>(D.tpart);
+        int k = t;
+        for (; k + 1024 < D.n_tiles; k += 2 * 1024) {
+            const double4 q0 = tp[k], q1 = tp[k + 1024];
+            a[0][0] += q0.x; a[0][1] += q0.y; a[0][2] += q0.z; a[0][3] += q0.w;
+            a[1][0] += q1.x; a[1][1] += q1.y; a[1][2] += q1.z; a[1][3] += q1.w;
         }
-        double eu = 0.0, ef = 0.0;
-        for (int k = t; k < D.G; k += 1024) {
-            eu += D.epart[(int64_t)k * 2 + 0];
-            ef += D.epart[(int64_t)k * 2 + 1];
-            D.epart[(int64_t)k * 2 + 0] = 0.0;
-            D.epart[(int64_t)k * 2 + 1] = 0.0;
+        if (k < D.n_tiles) {
+            const double4 q = tp[k];
+            a[0][0] += q.x; a[0][1] += q.y; a[0][2] += q.z; a[0][3] += q.w;
         }
-        ts = block_sum<1024>(ts, dbuf);
-        tc = block_sum<1024>(tc, dbuf);
-        du = block_sum<1024>(du, dbuf);
-        nb = block_sum<1024>(nb, dbuf);
-        eu = block_sum<1024>(eu, dbuf);
-        ef = block_sum<1024>(ef, dbuf);
+        double v[6];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = a[0][j] + a[1][j];
+        v[4] = 0.0;
+        v[5] = 0.0;
+        for (int g = t; g < D.G; g += 1024) {
+            v[4] += D.epart[(int64_t)g * 2 + 0];
+            v[5] += D.epart[(int64_t)g * 2 + 1];
+            D.epart[(int64_t)g * 2 + 0] = 0.0;
+            D.epart[(int64_t)g * 2 + 1] = 0.0;
+        }
+        block_sum_n<1024, 6>(v, dbuf);
         if (t == 0) {
-            rs->T_sum = ts;
-            rs->T_cells = tc;
-            rs->e_rxn += du + eu;
-            rs->n_bulk += (int64_t)nb;
-            rs->n_cat += (int64_t)ef;
+            rs->T_sum = v[0];
+            rs->T_cells = v[1];
+            rs->e_rxn += v[2] + v[4];
+            rs->n_bulk += (int64_t)v[3];
+            rs->n_cat += (int64_t)v[5];
             rs->coll_step += 1;
         }
     }
@@ -2032,6 +2087,7 @@ __global__ __launch_bounds__(256) void k_msd(Analysis* A, int32_t max_lag)
     RMP_CHAIN_INST(T, 2, 256)                                                    \
     RMP_CHAIN_INST(T, 4, 256)                                                    \
     RMP_CHAIN_INST(T, 1, 512)                                                    \
+    RMP_CHAIN_INST(T, 2, 512)                                                    \
     template __global__ void k_collide<T, 0>(Work);                              \
     template __global__ void k_collide<T, 1>(Work);                              \
     template __global__ void k_observe<T>(Work);                              \

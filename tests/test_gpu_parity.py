@@ -113,6 +113,16 @@ def test_fp64_gpu_init_matches_oracle_init():
     assert g.observables()["flags"] == 0
 
 
+def test_fp64_chain_512_threads_two_entries_each():
+    """A list capacity beyond 256 workgroups of 512 threads selects the
+    512-thread shape with two entries per thread."""
+    p = dict(W.dimer_system(L=16, rho=6, n_md=10, seed=11, bulk_rate=0.03), cand_capacity=140000)
+    s0 = W.random_state(p, 109, species_B_fraction=0.3, flag_fraction=0.05)
+    g, o = _run_both(p, s0, 17, 10, 3, tuning=dict(chain_block=512))
+    _assert_bitwise(g.get_state(), o.get_state(), "512 x 2")
+    _assert_obs(g.observables(), o.observables())
+
+
 @pytest.mark.parametrize("tuning", [
     dict(chain_k=1, collide_cells=8, stream_block=64, use_graph=0),
     dict(chain_k=2, collide_cells=16, stream_block=128, use_graph=1),
