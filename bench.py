@@ -226,7 +226,7 @@ def _log(msg):
 
 def tuning_from_args(args) -> dict:
     tun = dict(use_graph=args.graph)
-    for k in ("collide_cells", "chain_k", "chain_block", "stream_block", "stream_ppt"):
+    for k in ("collide_cells", "chain_k", "chain_block", "chain_resident", "stream_block", "stream_ppt"):
         if getattr(args, k) > 0:
             tun[k] = getattr(args, k)
     return tun
@@ -432,6 +432,7 @@ def main():
     ap.add_argument("--collide-cells", type=int, default=0)
     ap.add_argument("--chain-k", type=int, default=0)
     ap.add_argument("--chain-block", type=int, default=0)
+    ap.add_argument("--chain-resident", type=int, default=0)
     ap.add_argument("--stream-block", type=int, default=0)
     ap.add_argument("--stream-ppt", type=int, default=0)
     ap.add_argument("--serve-jobs", type=int, default=60)
