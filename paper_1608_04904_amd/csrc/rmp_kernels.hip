@@ -1522,7 +1522,10 @@ __device__ __forceinline__ void count_flag(uint32_t* chunk_cnt, int64_t o, bool 
 }
 
 constexpr int COLL_NT = 256;
-constexpr int COLL_CAP = 1024;       // particles per LDS group
+// Particles per LDS group: 512 keeps the LDS of a collision workgroup near
+// 22 KB, so five workgroups share a compute unit (register-limited); 1024
+// held it to four (LDS-limited), 3 % slower at 128^3.
+constexpr int COLL_CAP = 512;
 constexpr int COLL_TCMAX = 64;       // cells per tile at most
 
 // MPCD collision on one tile of cells of the shifted grid.  Cells of the
