@@ -18,6 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 MAXC = 32
+MAXB = 96
 PTABLE = 1024
 
 F_DISPLACEMENT, F_RATTLE, F_NONFINITE, F_INIT = 1, 2, 4, 8
@@ -45,9 +46,10 @@ class Params(C.Structure):
         ("sigma", C.c_double * MAXC), ("epsA", C.c_double * MAXC),
         ("epsB", C.c_double * MAXC), ("catalytic", C.c_int32 * MAXC),
         ("ctype", C.c_int32 * MAXC), ("eps_cc", (C.c_double * 2) * 2),
-        ("bond_a", C.c_int32 * MAXC), ("bond_b", C.c_int32 * MAXC),
-        ("bond_d", C.c_double * MAXC), ("cell_order", C.c_int32), ("pad", C.c_int32),
+        ("bond_a", C.c_int32 * MAXB), ("bond_b", C.c_int32 * MAXB),
+        ("bond_d", C.c_double * MAXB), ("cell_order", C.c_int32), ("pad", C.c_int32),
         ("walls", C.c_int32), ("wall_density", C.c_int32), ("accel", C.c_double * 3),
+        ("rattle_tol", C.c_double), ("rattle_maxit", C.c_int32), ("rattle_iterative", C.c_int32),
     ]
 
 
@@ -141,8 +143,13 @@ def make_params(p: dict) -> Params:
         for b in range(2):
             q.eps_cc[a][b] = p["eps_cc"][a][b]
     q.n_bonds = len(p["bonds"])
+    if q.n_bonds > MAXB:
+        raise ValueError("too many bonds")
     for k, (a, b, dd) in enumerate(p["bonds"]):
         q.bond_a[k], q.bond_b[k], q.bond_d[k] = a, b, dd
+    q.rattle_tol = float(p.get("rattle_tol", 1e-10))
+    q.rattle_maxit = int(p.get("rattle_maxit", 500))
+    q.rattle_iterative = int(p.get("rattle_iterative", 0))
     q.walls = int(p.get("walls", 0))
     q.wall_density = int(p.get("wall_density", 0))
     for d, g in enumerate(p.get("accel", (0.0, 0.0, 0.0))):

@@ -123,6 +123,8 @@ struct orc_system {
     uint8_t* st;
     /* colloids */
     int nc;
+    int body[ORC_MAXC];       /* rigid body of a colloid: smallest colloid of its bonded group */
+    int iterative;            /* some colloid has two or more bonds: iterative RATTLE */
     double X[ORC_MAXC][3], V[ORC_MAXC][3], F[ORC_MAXC][3], X0[ORC_MAXC][3];
     double hc[ORC_MAXC];      /* 0.5*dt/M */
     double imass[ORC_MAXC];   /* 1/M */
@@ -268,6 +270,21 @@ orc_system* orc_create(const orc_params* p, uint64_t seed)
     if (p->walls && (p->rule != 0 || p->cell_order != 0 || p->accel[2] != 0.0 ||
                      p->wall_density < 1 || p->wall_density > 1024))
         return NULL;
+    if (p->n_bonds < 0 || p->n_bonds > ORC_MAXB) return NULL;
+    int degree[ORC_MAXC] = { 0 };
+    for (int q = 0; q < p->n_bonds; ++q) {
+        const int a = p->bond_a[q], b = p->bond_b[q];
+        if (a < 0 || b < 0 || a >= p->n_colloids || b >= p->n_colloids || a == b || !(p->bond_d[q] > 0.0))
+            return NULL;
+        for (int r = 0; r < q; ++r)
+            if ((p->bond_a[r] == a && p->bond_b[r] == b) || (p->bond_a[r] == b && p->bond_b[r] == a))
+                return NULL;
+        degree[a]++;
+        degree[b]++;
+    }
+    int iterative = p->rattle_iterative != 0 && p->n_bonds > 0;
+    for (int c = 0; c < p->n_colloids; ++c) if (degree[c] > 1) iterative = 1;
+    if (iterative && (!(p->rattle_tol > 0.0) || p->rattle_maxit < 1 || p->rattle_maxit > 100000)) return NULL;
     orc_system* s = (orc_system*)xalloc(sizeof(orc_system));
     s->p = *p;
     s->seed = seed;
@@ -297,6 +314,23 @@ orc_system* orc_create(const orc_params* p, uint64_t seed)
         for (int64_t c = 0; c < s->ncell; ++c) { s->rank_of[c] = (uint32_t)c; s->cell_of[c] = (uint32_t)c; }
     }
     s->nc = p->n_colloids;
+    s->iterative = iterative;
+    /* rigid bodies: connected groups of the bond graph, each named by its
+     * smallest colloid (relabel until no bond joins two labels) */
+    for (int c = 0; c < s->nc; ++c) s->body[c] = c;
+    for (int changed = 1; changed;) {
+        changed = 0;
+        for (int q = 0; q < p->n_bonds; ++q) {
+            const int a = p->bond_a[q], b = p->bond_b[q];
+            const int m = s->body[a] < s->body[b] ? s->body[a] : s->body[b];
+            if (s->body[a] != m || s->body[b] != m) {
+                const int oa = s->body[a], ob = s->body[b];
+                for (int c = 0; c < s->nc; ++c)
+                    if (s->body[c] == oa || s->body[c] == ob) s->body[c] = m;
+                changed = 1;
+            }
+        }
+    }
     s->h = (0.5 * p->dt) / p->mass;
     s->ca = cos(p->alpha);
     s->sa = sin(p->alpha);
@@ -510,11 +544,8 @@ static void compute_forces(orc_system* s)
     double ucc = 0.0;
     for (int a = 0; a < nc; ++a) {
         for (int b = a + 1; b < nc; ++b) {
-            int bonded = 0;
-            for (int q = 0; q < s->p.n_bonds; ++q)
-                if ((s->p.bond_a[q] == a && s->p.bond_b[q] == b) ||
-                    (s->p.bond_a[q] == b && s->p.bond_b[q] == a)) bonded = 1;
-            if (bonded) continue;
+            /* colloids of one rigid body do not interact */
+            if (s->body[a] == s->body[b]) continue;
             double dx = mimg(Xw[a][0] - Xw[b][0], s->Ld[0], s->halfL[0]);
             double dy = mimg(Xw[a][1] - Xw[b][1], s->Ld[1], s->halfL[1]);
             double dz = mimg(Xw[a][2] - Xw[b][2], s->Ld[2], s->halfL[2]);
@@ -594,6 +625,75 @@ static void rattle_pos(orc_system* s, double Xold[][3])
             s->V[b][d] = s->V[b][d] + (gbd * r0[d]);
         }
     }
+}
+
+/* Iterative RATTLE (Andersen 1983), position stage, for bond networks (a
+ * colloid in two or more bonds, as in a composite Janus particle): sweeps
+ * over the bonds in their order; a bond whose squared length s.s misses
+ * d^2 by more than 2 tol d^2 is corrected along its direction before the
+ * drift, r0: both colloids move by g r0 / m (g = (d^2 - s.s) / (2 mu s.r0),
+ * mu = 1/m_a + 1/m_b) and their velocities by the same displacement over dt.
+ * Sweeps repeat until one changes nothing; after rattle_maxit sweeps the
+ * RATTLE flag is raised. */
+static void rattle_pos_iter(orc_system* s, double Xold[][3])
+{
+    const double dt = s->p.dt, tol = s->p.rattle_tol;
+    int sweep = 0, moved = 1;
+    for (; sweep < s->p.rattle_maxit && moved; ++sweep) {
+        moved = 0;
+        for (int q = 0; q < s->p.n_bonds; ++q) {
+            const int a = s->p.bond_a[q], b = s->p.bond_b[q];
+            const double dd2 = s->p.bond_d[q] * s->p.bond_d[q];
+            double sv[3], r0[3];
+            for (int d = 0; d < 3; ++d) { sv[d] = s->X[a][d] - s->X[b][d]; r0[d] = Xold[a][d] - Xold[b][d]; }
+            const double ss = ((sv[0] * sv[0]) + (sv[1] * sv[1])) + (sv[2] * sv[2]);
+            const double diff = dd2 - ss;
+            if (fabs(diff) > (2.0 * tol) * dd2) {
+                const double mu = s->imass[a] + s->imass[b];
+                const double sr0 = ((sv[0] * r0[0]) + (sv[1] * r0[1])) + (sv[2] * r0[2]);
+                const double g = diff / ((2.0 * mu) * sr0);
+                const double ga = g * s->imass[a], gb = g * s->imass[b];
+                const double gad = ga / dt, gbd = gb / dt;
+                for (int d = 0; d < 3; ++d) {
+                    s->X[a][d] = s->X[a][d] + (ga * r0[d]);
+                    s->X[b][d] = s->X[b][d] - (gb * r0[d]);
+                    s->V[a][d] = s->V[a][d] + (gad * r0[d]);
+                    s->V[b][d] = s->V[b][d] - (gbd * r0[d]);
+                }
+                moved = 1;
+            }
+        }
+    }
+    if (moved) s->flags |= ORC_F_RATTLE;
+}
+
+/* Iterative RATTLE, velocity stage: sweeps removing the relative velocity
+ * along each bond, k = (r.v) / (mu d^2), while |r.v| exceeds tol d^2 / dt. */
+static void rattle_vel_iter(orc_system* s)
+{
+    const double tol = s->p.rattle_tol, dt = s->p.dt;
+    int sweep = 0, moved = 1;
+    for (; sweep < s->p.rattle_maxit && moved; ++sweep) {
+        moved = 0;
+        for (int q = 0; q < s->p.n_bonds; ++q) {
+            const int a = s->p.bond_a[q], b = s->p.bond_b[q];
+            const double dd2 = s->p.bond_d[q] * s->p.bond_d[q];
+            double r[3], vr[3];
+            for (int d = 0; d < 3; ++d) { r[d] = s->X[a][d] - s->X[b][d]; vr[d] = s->V[a][d] - s->V[b][d]; }
+            const double rv = ((r[0] * vr[0]) + (r[1] * vr[1])) + (r[2] * vr[2]);
+            if (fabs(rv) > (tol * dd2) / dt) {
+                const double mu = s->imass[a] + s->imass[b];
+                const double k = rv / (mu * dd2);
+                const double ka = k * s->imass[a], kb = k * s->imass[b];
+                for (int d = 0; d < 3; ++d) {
+                    s->V[a][d] = s->V[a][d] - (ka * r[d]);
+                    s->V[b][d] = s->V[b][d] + (kb * r[d]);
+                }
+                moved = 1;
+            }
+        }
+    }
+    if (moved) s->flags |= ORC_F_RATTLE;
 }
 
 /* Velocity stage: remove the relative velocity along the bond. */
@@ -705,7 +805,8 @@ static void md_step(orc_system* s)
             Xold[c][d] = s->X[c][d];
             s->X[c][d] = fma(dt, s->V[c][d], s->X[c][d]);
         }
-    rattle_pos(s, Xold);
+    if (s->iterative) rattle_pos_iter(s, Xold);
+    else rattle_pos(s, Xold);
     const int64_t nl = s->ncand;
     #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < nl; ++k) {
@@ -724,7 +825,8 @@ static void md_step(orc_system* s)
     }
     for (int c = 0; c < nc; ++c)
         for (int d = 0; d < 3; ++d) s->V[c][d] = fma(s->hc[c], s->F[c][d], s->V[c][d]);
-    rattle_vel(s);
+    if (s->iterative) rattle_vel_iter(s);
+    else rattle_vel(s);
     /* catalysis, in list order */
     for (int64_t k = 0; k < nl; ++k) {
         int64_t i = s->idx[k];

@@ -29,6 +29,7 @@ extern "C" {
 #endif
 
 #define ORC_MAXC 32          /* max colloids per system */
+#define ORC_MAXB 96          /* max rigid bonds per system */
 #define ORC_PTABLE 1024      /* bulk-reaction probability table length */
 
 typedef struct orc_params {
@@ -52,9 +53,9 @@ typedef struct orc_params {
     int32_t catalytic[ORC_MAXC];
     int32_t ctype[ORC_MAXC]; /* 0 or 1: row/column of eps_cc                     */
     double  eps_cc[2][2];    /* colloid-colloid epsilon by type                 */
-    int32_t bond_a[ORC_MAXC];
-    int32_t bond_b[ORC_MAXC];
-    double  bond_d[ORC_MAXC];
+    int32_t bond_a[ORC_MAXB];
+    int32_t bond_b[ORC_MAXB];
+    double  bond_d[ORC_MAXB];
     int32_t cell_order;      /* 0 row-major cell order, 1 compact Hilbert       */
     int32_t pad;
     /* flows ("Algorithms": constant acceleration; stick walls by bounce-back
@@ -62,6 +63,11 @@ typedef struct orc_params {
     int32_t walls;           /* 1: plates at z = 0 and z = L_z              */
     int32_t wall_density;    /* particles of a full cell (virtual fill)    */
     double  accel[3];        /* constant acceleration of every solvent particle */
+    /* rigid bodies of several bonded colloids ("Algorithms": RATTLE in its
+     * iterative form for the Janus particle, exact for the dimer)         */
+    double  rattle_tol;      /* relative tolerance of the iterative RATTLE  */
+    int32_t rattle_maxit;    /* sweeps over the bonds at most               */
+    int32_t rattle_iterative;/* 1: iterative RATTLE also for single bonds   */
 } orc_params;
 
 typedef struct orc_obs {

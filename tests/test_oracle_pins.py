@@ -1031,3 +1031,104 @@ def test_poiseuille_profile_closed_form():
     c0, _, _, _ = _poiseuille_profile(31, wall_density=1)
     slip0 = [np.polyval(c0, 0.0) / vmax, np.polyval(c0, 10.0) / vmax]
     assert min(slip0) > 0.25, slip0
+
+
+# --------------------------------------------------------------------------
+# Rigid bodies of several beads: RATTLE in its iterative form (Andersen
+# 1983; "Algorithms": iterative for the Janus particle, exact for the dimer)
+
+def _bond_errors(p, X, V):
+    pos, vel = [], []
+    for a, b, d in p["bonds"]:
+        r = X[a] - X[b]
+        pos.append(abs(r @ r - d * d) / (d * d))
+        vel.append(abs(r @ (V[a] - V[b])) / (d * d))
+    return max(pos), max(vel)
+
+
+def _rigid_velocities(p, rng):
+    """A rigid-body velocity field: V_c = v0 + w x (X_c - R)."""
+    X = np.array([c["x"] for c in p["colloids"]])
+    R = X.mean(axis=0)
+    v0, w = rng.normal(0, 0.05, 3), rng.normal(0, 0.05, 3)
+    return np.array([v0 + np.cross(w, x - R) for x in X])
+
+
+def test_iterative_rattle_holds_janus_rigid_and_conserves_its_invariants():
+    """An isolated composite Janus particle (13 beads, 42 bonds, no solvent)
+    moves freely: every bond keeps its length within the tolerance and has
+    no relative velocity along it, total momentum is conserved to rounding,
+    and kinetic energy and angular momentum of the free rigid body stay
+    constant to the integration error."""
+    p = W.janus_system(L=16, rho=0, n_md=20, seed=3)
+    assert p["n_solvent"] == 0 and len(p["bonds"]) == 42
+    o = oracle.Oracle(p, 5, init=False)
+    s = W.random_state(p, 6)
+    s["V"] = _rigid_velocities(p, np.random.default_rng(7))
+    o.set_state(s)
+    M = np.array([c["mass"] for c in p["colloids"]])
+
+    def invariants(st):
+        X, V = st["X"], st["V"]
+        P = (M[:, None] * V).sum(0)
+        R = (M[:, None] * X).sum(0) / M.sum()
+        Lm = (M[:, None] * np.cross(X - R, V)).sum(0)
+        return P, 0.5 * (M * (V * V).sum(1)).sum(), Lm
+    P0, K0, L0 = invariants(o.get_state())
+    for _ in range(10):
+        o.run(20, 1)
+        st = o.get_state()
+        ep, ev = _bond_errors(p, st["X"], st["V"])
+        assert ep <= 2.1e-10 and ev <= 1e-10 / p["dt"] * 1.01
+        P, K, Lm = invariants(st)
+        assert np.abs(P - P0).max() < 1e-13
+        assert abs(K - K0) / K0 < 1e-6
+        assert np.abs(Lm - L0).max() < 1e-6 * np.abs(L0).max()
+    assert o.observables()["flags"] == 0
+
+
+def test_iterative_rattle_agrees_with_exact_for_the_dimer():
+    """For a single bond the exact RATTLE has a closed form: the iterative
+    one (forced) follows the same trajectory to within its tolerance."""
+    p = W.dimer_system(L=14, rho=5, n_md=10, seed=4, bulk_rate=0.0)
+    s0 = W.random_state(p, 8)
+    outs = []
+    for it in (0, 1):
+        q = dict(p, rattle_iterative=it, rattle_tol=1e-12, rattle_maxit=1000)
+        o = oracle.Oracle(q, 9, init=False)
+        o.set_state(s0)
+        o.interval(10, collide=False)
+        outs.append(o.get_state())
+    assert np.abs(outs[0]["X"] - outs[1]["X"]).max() < 1e-9
+    assert np.abs(outs[0]["V"] - outs[1]["V"]).max() < 1e-7
+    ep, ev = _bond_errors(p, outs[1]["X"], outs[1]["V"])
+    assert ep < 3e-12
+
+
+def test_iterative_rattle_flags_when_it_cannot_converge():
+    p = dict(W.janus_system(L=16, rho=0, n_md=5, seed=3), rattle_maxit=1)
+    o = oracle.Oracle(p, 5, init=False)
+    s = W.random_state(p, 6)
+    s["V"] = _rigid_velocities(p, np.random.default_rng(7)) * 40.0
+    o.set_state(s)
+    o.run(5, 1)
+    assert o.observables()["flags"] & oracle.F_RATTLE
+
+
+def test_rigid_body_validation_and_same_body_exclusion():
+    base = W.janus_system(L=16, rho=2, n_md=5, seed=3)
+    for bad in (dict(base, rattle_tol=0.0), dict(base, rattle_maxit=0),
+                dict(base, bonds=base["bonds"] + [base["bonds"][0]])):
+        with pytest.raises(ValueError):
+            oracle.Oracle(bad, 1, init=False)
+    # beads of one body overlap (spacing 2.5-2.6 < 2^(1/6) 4): no
+    # colloid-colloid force acts inside the body, so a body at rest with no
+    # solvent nearby stays at rest
+    p = dict(base, n_solvent=0)
+    o = oracle.Oracle(p, 2, init=False)
+    s = W.random_state(p, 3)
+    s["V"] = np.zeros_like(s["V"])
+    o.set_state(s)
+    o.run(5, 1)
+    st = o.get_state()
+    assert np.abs(st["V"]).max() == 0.0 and np.abs(st["X"] - s["X"]).max() == 0.0

@@ -140,6 +140,73 @@ def large128(precision=64, seed=None, L=128) -> dict:
     return p
 
 
+def icosahedron(radius: float) -> tuple[np.ndarray, list]:
+    """Vertices of a regular icosahedron of the given circumradius (a vertex
+    on +z) and its 30 edges."""
+    v = [(0.0, 0.0, 1.0), (0.0, 0.0, -1.0)]
+    zr = 1.0 / math.sqrt(5.0)
+    rr = 2.0 / math.sqrt(5.0)
+    for k in range(5):
+        a = 2.0 * math.pi * k / 5.0
+        v.append((rr * math.cos(a), rr * math.sin(a), zr))
+    for k in range(5):
+        a = 2.0 * math.pi * (k + 0.5) / 5.0
+        v.append((rr * math.cos(a), rr * math.sin(a), -zr))
+    V = np.array(v) * radius
+    d = np.linalg.norm(V[:, None, :] - V[None, :, :], axis=2)
+    edge = d[d > 1e-9].min()
+    edges = [(i, j) for i in range(12) for j in range(i + 1, 12) if abs(d[i, j] - edge) < 1e-6 * radius]
+    assert len(edges) == 30
+    return V, edges
+
+
+def random_rotation(rng: np.random.Generator) -> np.ndarray:
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def add_janus(p: dict, centre, rng: np.random.Generator, shell=2.5, sigma=2.0,
+              eps_cat=(1.0, 1.0), eps_non=(1.0, 0.5)):
+    """A composite Janus particle: a central bead and 12 beads on the
+    vertices of an icosahedron, held rigid by 42 bonds (12 spokes, 30 edges);
+    the beads of the upper half (the +z vertex and its ring, in the body
+    frame) are catalytic.  Returns the colloid indices."""
+    V, edges = icosahedron(shell)
+    R = random_rotation(rng)
+    c0 = np.asarray(centre, dtype=float)
+    first = len(p["colloids"])
+    centre_i = add_colloid(p, c0, sigma, eps_non[0], eps_non[1], catalytic=False, ctype=TYPE_N)
+    ids = []
+    for k in range(12):
+        cat = V[k, 2] > 0.0
+        e = eps_cat if cat else eps_non
+        ids.append(add_colloid(p, c0 + R @ V[k], sigma, e[0], e[1], catalytic=bool(cat),
+                               ctype=TYPE_C if cat else TYPE_N))
+    for k in range(12):
+        p["bonds"].append((centre_i, ids[k], float(shell)))
+    for i, j in edges:
+        p["bonds"].append((ids[i], ids[j], float(np.linalg.norm(V[i] - V[j]))))
+    return list(range(first, first + 13))
+
+
+def janus_system(L=24, rho=10, n_md=50, precision=64, seed=None, bulk_rate=0.01,
+                 cat_prob=1.0) -> dict:
+    """One composite Janus motor at the box centre (iterative RATTLE)."""
+    p = base_params(L=(L, L, L), rho=rho, dt=0.01, n_md=n_md, precision=precision)
+    rng = np.random.default_rng(BASE_SEED + 6 if seed is None else seed)
+    add_janus(p, (L / 2.0, L / 2.0, L / 2.0), rng)
+    p["cat_prob"] = float(cat_prob)
+    p["bulk_rate"] = float(bulk_rate)
+    p["rattle_tol"] = 1e-10
+    p["rattle_maxit"] = 500
+    p["name"] = f"janus{L}"
+    return p
+
+
 def poiseuille(L=(64, 64, 32), rho=10, g=0.001, dt=0.01, n_md=10, precision=64) -> dict:
     """Flow between plates at z = 0 and z = L_z driven by a constant
     acceleration g along x, no colloid (the paper's poiseuille_flow setup)."""
@@ -233,7 +300,8 @@ def random_state(p: dict, seed: int, species_B_fraction=0.0, flag_fraction=0.0,
     x = np.where(x >= L, 0.0, x)
     s = math.sqrt(p["kT"] / p["mass"]) if velocity_scale is None else velocity_scale
     v = rng.normal(0.0, s, size=(n, 3))
-    v -= v.mean(axis=0)
+    if n:
+        v -= v.mean(axis=0)
     ids = rng.permutation(n).astype(np.uint32)
     st = np.zeros(n, dtype=np.uint8)
     if species_B_fraction > 0:
