@@ -114,6 +114,11 @@ def workload(name: str, precision: int):
         p = W.sphere10(precision=precision)
         return p, 10, W.BASE_SEED + 1, ("sphere10: 10^3 cells, rho 10, N=10,000, 1 WCA sphere "
                                          "sigma 2, tau 0.1 (10 MD steps/collision)")
+    if name == "janus32":
+        p = W.janus_system(L=32, rho=10, n_md=50, precision=precision)
+        return p, 50, W.BASE_SEED + 6, ("janus32: 32^3 cells, rho 10, N=327,680, one composite Janus "
+                                         "particle (13 beads, 42 rigid bonds, iterative RATTLE), "
+                                         "tau 0.5 (50 MD steps/collision)")
     if name == "poiseuille":
         p = W.poiseuille(precision=precision)
         return p, 10, W.BASE_SEED + 5, ("poiseuille: 64 x 64 x 32 cells between plates at z = 0 "
@@ -422,7 +427,7 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="dimer32",
-                    choices=["dimer32", "sphere10", "large128", "batch", "serve"])
+                    choices=["dimer32", "sphere10", "large128", "poiseuille", "janus32", "batch", "serve"])
     ap.add_argument("--precision", type=int, default=64)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -502,6 +507,11 @@ def main():
                 value=r["value"], roofline=r["roofline"],
                 kernels={k: r["kernels"][k] for k in ("stream_bin", "collide", "chain")
                          if k in r["kernels"]})
+        _log("janus32 fp64")
+        r = run_single("janus32", 64, 10, 2, 3, tun)
+        extras["janus32_fp64"] = dict(value=r["value"], roofline=r["roofline"],
+                                      kernels={k: r["kernels"][k] for k in ("chain", "collide", "stream_bin")
+                                               if k in r["kernels"]}, flags=r["flags"])
         for prec in (64, 32):
             _log(f"poiseuille fp{prec}")
             r = run_single("poiseuille", prec, args.steps, args.warmup, args.profile_steps, tun)

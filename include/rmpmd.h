@@ -37,6 +37,7 @@ extern "C" {
 #endif
 
 #define RMP_MAX_COLLOIDS 32
+#define RMP_MAX_BONDS 96
 #define RMP_PTABLE 1024
 
 typedef enum rmp_status {
@@ -87,9 +88,9 @@ typedef struct rmp_params {
     int32_t catalytic[RMP_MAX_COLLOIDS];      /* 1: converts A to B                */
     int32_t ctype[RMP_MAX_COLLOIDS];          /* 0 or 1, index into eps_cc         */
     double  eps_cc[2][2];
-    int32_t bond_a[RMP_MAX_COLLOIDS];
-    int32_t bond_b[RMP_MAX_COLLOIDS];
-    double  bond_d[RMP_MAX_COLLOIDS];
+    int32_t bond_a[RMP_MAX_BONDS];            /* rigid bonds: colloids bond_a[k] and */
+    int32_t bond_b[RMP_MAX_BONDS];            /* bond_b[k] at distance bond_d[k]      */
+    double  bond_d[RMP_MAX_BONDS];
     int32_t cell_order;        /* order of cells in the sorted particle arrays:
                                   0 row-major (x fastest); 1 compact Hilbert (the
                                   box's cells along the Hilbert curve of the
@@ -115,6 +116,18 @@ typedef struct rmp_params {
     double  accel[3];          /* constant acceleration of every solvent
                                   particle, applied as velocity-Verlet half
                                   kicks around each drift (0: none)             */
+    /* Rigid bodies ("Algorithms": RATTLE, exact for the dimer, iterative for
+     * the Janus particle).  Bonded colloids form rigid bodies whose colloids
+     * do not interact with each other.  A colloid in one bond at most is
+     * constrained by the exact RATTLE; a bond network (a colloid in two or
+     * more bonds) by the iterative RATTLE (Andersen 1983): sweeps over the
+     * bonds in order, correcting a bond whose squared length misses d^2 by
+     * more than 2 rattle_tol d^2 (velocity stage: |r.v| > rattle_tol d^2 / dt),
+     * until a sweep changes nothing; after rattle_maxit sweeps the RATTLE
+     * flag is raised. */
+    double  rattle_tol;        /* > 0 when iterative                            */
+    int32_t rattle_maxit;      /* 1 .. 100000 when iterative                    */
+    int32_t rattle_iterative;  /* 1: iterative also for single bonds            */
 } rmp_params;
 
 /* FP64 observables.  `potential` is the colloid-solvent plus colloid-colloid

@@ -13,6 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librmpmd.so")
 
 MAX_COLLOIDS = 32
+MAX_BONDS = 96
 PTABLE = 1024
 
 OK, EINVAL, ENOMEM, EHIP, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
@@ -31,10 +32,11 @@ class Params(C.Structure):
         ("colloid_mass", C.c_double * MAX_COLLOIDS), ("sigma", C.c_double * MAX_COLLOIDS),
         ("eps_A", C.c_double * MAX_COLLOIDS), ("eps_B", C.c_double * MAX_COLLOIDS),
         ("catalytic", C.c_int32 * MAX_COLLOIDS), ("ctype", C.c_int32 * MAX_COLLOIDS),
-        ("eps_cc", (C.c_double * 2) * 2), ("bond_a", C.c_int32 * MAX_COLLOIDS),
-        ("bond_b", C.c_int32 * MAX_COLLOIDS), ("bond_d", C.c_double * MAX_COLLOIDS),
+        ("eps_cc", (C.c_double * 2) * 2), ("bond_a", C.c_int32 * MAX_BONDS),
+        ("bond_b", C.c_int32 * MAX_BONDS), ("bond_d", C.c_double * MAX_BONDS),
         ("cell_order", C.c_int32), ("pad_order", C.c_int32),
         ("walls", C.c_int32), ("wall_density", C.c_int32), ("accel", C.c_double * 3),
+        ("rattle_tol", C.c_double), ("rattle_maxit", C.c_int32), ("rattle_iterative", C.c_int32),
     ]
 
 CELL_ORDERS = {"row": 0, "hilbert": 1}
@@ -191,8 +193,13 @@ def make_params(p: dict) -> Params:
         for b in range(2):
             q.eps_cc[a][b] = float(p["eps_cc"][a][b])
     q.n_bonds = len(p["bonds"])
+    if q.n_bonds > MAX_BONDS:
+        raise ValueError("too many bonds")
     for k, (a, b, dd) in enumerate(p["bonds"]):
         q.bond_a[k], q.bond_b[k], q.bond_d[k] = int(a), int(b), float(dd)
+    q.rattle_tol = float(p.get("rattle_tol", 1e-10))
+    q.rattle_maxit = int(p.get("rattle_maxit", 500))
+    q.rattle_iterative = int(p.get("rattle_iterative", 0))
     return q
 
 

@@ -58,6 +58,20 @@ bool has_flow(const rmp_params* p)
     return p->walls != 0 || p->accel[0] != 0.0 || p->accel[1] != 0.0 || p->accel[2] != 0.0;
 }
 
+// bond networks (a colloid in two or more bonds) need the iterative RATTLE
+bool iterative_rattle(const rmp_params* p)
+{
+    if (p->n_bonds <= 0) return false;
+    if (p->rattle_iterative) return true;
+    int degree[RMP_MAX_COLLOIDS] = {0};
+    for (int b = 0; b < p->n_bonds && b < RMP_MAX_BONDS; ++b) {
+        const int a0 = p->bond_a[b], a1 = p->bond_b[b];
+        if (a0 >= 0 && a0 < RMP_MAX_COLLOIDS && ++degree[a0] > 1) return true;
+        if (a1 >= 0 && a1 < RMP_MAX_COLLOIDS && ++degree[a1] > 1) return true;
+    }
+    return false;
+}
+
 rmp_status validate(const rmp_params* p)
 {
     if (!p) return RMP_EINVAL;
@@ -71,7 +85,7 @@ rmp_status validate(const rmp_params* p)
     if (!std::isfinite(p->alpha) || !(p->cat_prob >= 0.0) || !(p->bulk_rate >= 0.0)) return RMP_EINVAL;
     if (p->rule != 0 && p->rule != 1) return RMP_EINVAL;
     if (p->n_colloids < 0 || p->n_colloids > RMP_MAX_COLLOIDS) return RMP_EINVAL;
-    if (p->n_bonds < 0 || p->n_bonds > RMP_MAX_COLLOIDS / 2) return RMP_EINVAL;
+    if (p->n_bonds < 0 || p->n_bonds > RMP_MAX_BONDS) return RMP_EINVAL;
     if (p->cell_order != 0 && p->cell_order != 1) return RMP_EINVAL;
     if (p->cand_capacity < 0) return RMP_EINVAL;
     if (p->walls != 0 && p->walls != 1) return RMP_EINVAL;
@@ -82,7 +96,7 @@ rmp_status validate(const rmp_params* p)
                      p->wall_density < 1 || p->wall_density > 1024))
         return RMP_EINVAL;
     if ((int64_t)p->L[0] * p->L[1] * (p->L[2] + 1) > (int64_t)1 << 31) return RMP_EINVAL;
-    int used[RMP_MAX_COLLOIDS] = {0};
+    int degree[RMP_MAX_COLLOIDS] = {0};
     for (int c = 0; c < p->n_colloids; ++c) {
         if (!(p->sigma[c] > 0.0) || !(p->colloid_mass[c] > 0.0)) return RMP_EINVAL;
         if (!(p->eps_A[c] >= 0.0) || !(p->eps_B[c] >= 0.0)) return RMP_EINVAL;
@@ -97,10 +111,17 @@ rmp_status validate(const rmp_params* p)
     for (int b = 0; b < p->n_bonds; ++b) {
         int a0 = p->bond_a[b], a1 = p->bond_b[b];
         if (a0 < 0 || a1 < 0 || a0 >= p->n_colloids || a1 >= p->n_colloids || a0 == a1) return RMP_EINVAL;
-        if (used[a0] || used[a1]) return RMP_EINVAL;
-        used[a0] = used[a1] = 1;
-        if (!(p->bond_d[b] > 0.0)) return RMP_EINVAL;
+        for (int r = 0; r < b; ++r)
+            if ((p->bond_a[r] == a0 && p->bond_b[r] == a1) || (p->bond_a[r] == a1 && p->bond_b[r] == a0))
+                return RMP_EINVAL;
+        degree[a0]++;
+        degree[a1]++;
+        if (!(p->bond_d[b] > 0.0) || !std::isfinite(p->bond_d[b])) return RMP_EINVAL;
     }
+    if (p->rattle_iterative != 0 && p->rattle_iterative != 1) return RMP_EINVAL;
+    if (iterative_rattle(p) && (!(p->rattle_tol > 0.0) || !std::isfinite(p->rattle_tol) ||
+                                p->rattle_maxit < 1 || p->rattle_maxit > 100000))
+        return RMP_EINVAL;
     return RMP_OK;
 }
 
@@ -415,7 +436,7 @@ ColloidParams make_cp(const rmp_params* p)
     ColloidParams c{};
     c.nc = p->n_colloids;
     c.nbonds = p->n_bonds;
-    for (int i = 0; i < RMP_MAX_COLLOIDS; ++i) c.partner[i] = -1;
+    for (int i = 0; i < RMP_MAX_COLLOIDS; ++i) c.body[i] = i;
     for (int i = 0; i < RMP_MAX_COLLOIDS; ++i) c.bond_of[i] = -1;
     for (int i = 0; i < p->n_colloids; ++i) {
         c.catalytic[i] = p->catalytic[i] ? 1 : 0;
@@ -437,10 +458,26 @@ ColloidParams make_cp(const rmp_params* p)
         c.bond_a[b] = p->bond_a[b];
         c.bond_b[b] = p->bond_b[b];
         c.bond_d[b] = p->bond_d[b];
-        c.partner[p->bond_a[b]] = p->bond_b[b];
-        c.partner[p->bond_b[b]] = p->bond_a[b];
         c.bond_of[p->bond_a[b]] = b;
         c.bond_of[p->bond_b[b]] = b;
+    }
+    c.iterative = iterative_rattle(p) ? 1 : 0;
+    c.rattle_maxit = p->rattle_maxit;
+    c.rattle_tol = p->rattle_tol;
+    if (c.iterative)
+        for (int i = 0; i < RMP_MAX_COLLOIDS; ++i) c.bond_of[i] = -1;   // no exact bond stage
+    // rigid bodies: merge the two bodies joined by a bond into the smaller
+    // label until every bond lies inside one body
+    for (bool merged = true; merged;) {
+        merged = false;
+        for (int b = 0; b < p->n_bonds; ++b) {
+            const int la = c.body[p->bond_a[b]], lb = c.body[p->bond_b[b]];
+            if (la == lb) continue;
+            const int keep = la < lb ? la : lb, drop = la < lb ? lb : la;
+            for (int i = 0; i < p->n_colloids; ++i)
+                if (c.body[i] == drop) c.body[i] = keep;
+            merged = true;
+        }
     }
     return c;
 }

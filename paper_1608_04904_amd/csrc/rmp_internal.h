@@ -26,9 +26,13 @@ enum : uint64_t {
 // Per-replica colloid parameters with host-derived constants.
 struct ColloidParams {
     int32_t nc, nbonds;
-    int32_t catalytic[MAXC], ctype[MAXC], partner[MAXC];
-    int32_t bond_a[MAXC], bond_b[MAXC], bond_of[MAXC];   // bond_of: bond of a colloid, -1 if none
-    double bond_d[MAXC];
+    int32_t catalytic[MAXC], ctype[MAXC];
+    int32_t body[MAXC];                                  // rigid body: smallest colloid of its bonded group
+    int32_t bond_of[MAXC];                               // the single bond of a colloid (exact RATTLE), -1 if none
+    int32_t bond_a[RMP_MAX_BONDS], bond_b[RMP_MAX_BONDS];
+    double bond_d[RMP_MAX_BONDS];
+    int32_t iterative, rattle_maxit;                     // iterative RATTLE for bond networks
+    double rattle_tol;
     double sigma[MAXC], sig2[MAXC], rc2[MAXC], reachR[MAXC];
     double epsA[MAXC], epsB[MAXC];
     double mass[MAXC], imass[MAXC], hc[MAXC];

@@ -767,6 +767,82 @@ __device__ __forceinline__ void rattle_pos_lane(const BondLane& L, double dt, do
     }
 }
 
+// Iterative RATTLE (Andersen 1983) for bond networks, run by one lane on
+// the colloid state staged in LDS.  Position stage: sweeps over the bonds in
+// order; a bond whose squared length s.s misses d^2 by more than 2 tol d^2 is
+// corrected along its direction before the drift, r0: both colloids move by
+// g r0 / m, g = (d^2 - s.s) / (2 mu s.r0), mu = 1/m_a + 1/m_b, and their
+// velocities by the same displacement over dt; until a sweep changes
+// nothing, at most rattle_maxit sweeps (else the RATTLE flag).
+__device__ __noinline__ uint32_t rattle_pos_iter(double (*X)[3], double (*V)[3], const double (*Xo)[3],
+                                                 const ColloidParams* cp, double dt)
+{
+    const double tol = cp->rattle_tol;
+    bool moved = true;
+    for (int sweep = 0; sweep < cp->rattle_maxit && moved; ++sweep) {
+        moved = false;
+        for (int q = 0; q < cp->nbonds; ++q) {
+            const int a = cp->bond_a[q], b = cp->bond_b[q];
+            const double dd2 = cp->bond_d[q] * cp->bond_d[q];
+            double sv[3], r0[3];
+            for (int d = 0; d < 3; ++d) {
+                sv[d] = X[a][d] - X[b][d];
+                r0[d] = Xo[a][d] - Xo[b][d];
+            }
+            const double ss = dot3(sv[0], sv[1], sv[2], sv[0], sv[1], sv[2]);
+            const double diff = dd2 - ss;
+            if (fabs(diff) > (2.0 * tol) * dd2) {
+                const double mu = cp->imass[a] + cp->imass[b];
+                const double sr0 = dot3(sv[0], sv[1], sv[2], r0[0], r0[1], r0[2]);
+                const double g = diff / ((2.0 * mu) * sr0);
+                const double ga = g * cp->imass[a], gb = g * cp->imass[b];
+                const double gad = ga / dt, gbd = gb / dt;
+                for (int d = 0; d < 3; ++d) {
+                    X[a][d] = X[a][d] + (ga * r0[d]);
+                    X[b][d] = X[b][d] - (gb * r0[d]);
+                    V[a][d] = V[a][d] + (gad * r0[d]);
+                    V[b][d] = V[b][d] - (gbd * r0[d]);
+                }
+                moved = true;
+            }
+        }
+    }
+    return moved ? RMP_FLAG_RATTLE : 0u;
+}
+
+// Iterative RATTLE, velocity stage: sweeps removing the relative velocity
+// along each bond, k = (r.v) / (mu d^2), while |r.v| exceeds tol d^2 / dt.
+__device__ __noinline__ uint32_t rattle_vel_iter(const double (*X)[3], double (*V)[3], const ColloidParams* cp,
+                                                 double dt)
+{
+    const double tol = cp->rattle_tol;
+    bool moved = true;
+    for (int sweep = 0; sweep < cp->rattle_maxit && moved; ++sweep) {
+        moved = false;
+        for (int q = 0; q < cp->nbonds; ++q) {
+            const int a = cp->bond_a[q], b = cp->bond_b[q];
+            const double dd2 = cp->bond_d[q] * cp->bond_d[q];
+            double r[3], vr[3];
+            for (int d = 0; d < 3; ++d) {
+                r[d] = X[a][d] - X[b][d];
+                vr[d] = V[a][d] - V[b][d];
+            }
+            const double rv = dot3(r[0], r[1], r[2], vr[0], vr[1], vr[2]);
+            if (fabs(rv) > (tol * dd2) / dt) {
+                const double mu = cp->imass[a] + cp->imass[b];
+                const double k = rv / (mu * dd2);
+                const double ka = k * cp->imass[a], kb = k * cp->imass[b];
+                for (int d = 0; d < 3; ++d) {
+                    V[a][d] = V[a][d] - (ka * r[d]);
+                    V[b][d] = V[b][d] + (kb * r[d]);
+                }
+                moved = true;
+            }
+        }
+    }
+    return moved ? RMP_FLAG_RATTLE : 0u;
+}
+
 // RATTLE velocity stage for the colloid of lane t (same conventions)
 __device__ __forceinline__ void rattle_vel_lane(const BondLane& L, const double (&X)[3], double (&V)[3])
 {
@@ -811,6 +887,8 @@ struct ChainCtx {
     double sNode[NVAL_MAX];
     double sU;
     uint32_t sflags;
+    // colloid state staged for the iterative RATTLE (bond networks)
+    double sXc[MAXC][3], sVc[MAXC][3], sXoc[MAXC][3];
 };
 
 // species_dU for an A -> B flip inside the MD chain, with the colloid
@@ -1066,7 +1144,7 @@ __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0
 // Constants of the colloid of lane c (c < nc) used by the pair forces,
 // loaded once per interval
 struct PairLane {
-    int partner, ctype;
+    int body, ctype;           // rigid body of the colloid (no forces inside a body)
     double sigma;
 };
 
@@ -1111,7 +1189,7 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT>& S, const RepDesc& D,
         const int c = t;
         double F[3] = {-S.sNode[3 * c + 0], -S.sNode[3 * c + 1], -S.sNode[3 * c + 2]};
         for (int a = 0; a < nc; ++a) {
-            if (a == c || PL.partner == a) continue;
+            if (a == c || cp->body[a] == PL.body) continue;
             // colloid a's constants by its (uniform) index, this lane's from
             // registers; operands in the pair's (lo, hi) order
             const double sig_a = S.cSigma[a];
@@ -1140,7 +1218,7 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT>& S, const RepDesc& D,
         double ucc = 0.0;
         for (int a = 0; a < nc; ++a)
             for (int b = a + 1; b < nc; ++b) {
-                if (cp->partner[a] == b) continue;
+                if (cp->body[a] == cp->body[b]) continue;
                 double dx = min_image(S.sXw[a][0] - S.sXw[b][0], D.Ld[0], D.halfL[0]);
                 double dy = min_image(S.sXw[a][1] - S.sXw[b][1], D.Ld[1], D.halfL[1]);
                 double dz = min_image(S.sXw[a][2] - S.sXw[b][2], D.Ld[2], D.halfL[2]);
@@ -1201,8 +1279,10 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     double cX[3] = {0.0, 0.0, 0.0}, cV[3] = {0.0, 0.0, 0.0}, cF[3] = {0.0, 0.0, 0.0};
     double cX0[3] = {0.0, 0.0, 0.0};
     const BondLane BL = bond_lane(cp, nc);
+    // iterative RATTLE: bond networks, or asked for (rattle_iterative)
+    const bool iter = NC != 1 && cp->iterative != 0;
     PairLane PL;
-    PL.partner = t < nc ? cp->partner[t] : -1;
+    PL.body = t < nc ? cp->body[t] : -1;
     PL.ctype = t < nc ? cp->ctype[t] : 0;
     PL.sigma = t < nc ? cp->sigma[t] : 0.0;
     const double chc = t < nc ? cp->hc[t] : 0.0;
@@ -1289,7 +1369,26 @@ __device__ __forceinline__ void chain_run(Work w, int item)
                 for (int d = 0; d < 3; ++d) cXo[d] = cX[d];
             }
             uint32_t lflags = 0;
-            rattle_pos_lane(BL, dt, cX, cV, cXo, lflags);
+            if (iter) {
+                // bond network: one lane sweeps over the bonds on the
+                // colloid state staged in LDS
+                if (t < nc)
+                    for (int d = 0; d < 3; ++d) {
+                        S.sXc[t][d] = cX[d];
+                        S.sVc[t][d] = cV[d];
+                        S.sXoc[t][d] = cXo[d];
+                    }
+                wave_sync();
+                if (t == 0) lflags |= rattle_pos_iter(S.sXc, S.sVc, S.sXoc, cp, dt);
+                wave_sync();
+                if (t < nc)
+                    for (int d = 0; d < 3; ++d) {
+                        cX[d] = S.sXc[t][d];
+                        cV[d] = S.sVc[t][d];
+                    }
+            } else {
+                rattle_pos_lane(BL, dt, cX, cV, cXo, lflags);
+            }
             if (lflags) atomicOr(&S.sflags, lflags);
             if (t < nc)
                 for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(cX[d], D.Ld[d]);
@@ -1346,7 +1445,22 @@ __device__ __forceinline__ void chain_run(Work w, int item)
         if (colloid_wave) {
             if (t < nc)
                 for (int d = 0; d < 3; ++d) cV[d] = fma(chc, cF[d], cV[d]);
-            rattle_vel_lane(BL, cX, cV);
+            if (iter) {
+                if (t < nc)
+                    for (int d = 0; d < 3; ++d) {
+                        S.sXc[t][d] = cX[d];
+                        S.sVc[t][d] = cV[d];
+                    }
+                wave_sync();
+                uint32_t vflags = 0;
+                if (t == 0) vflags = rattle_vel_iter(S.sXc, S.sVc, cp, dt);
+                if (vflags) atomicOr(&S.sflags, vflags);
+                wave_sync();
+                if (t < nc)
+                    for (int d = 0; d < 3; ++d) cV[d] = S.sVc[t][d];
+            } else {
+                rattle_vel_lane(BL, cX, cV);
+            }
             if (t < nc) {
                 double dx = cX[0] - cX0[0], dy = cX[1] - cX0[1], dz = cX[2] - cX0[2];
                 if (dot3(dx, dy, dz, dx, dy, dz) >= D.skin_half2)

@@ -127,6 +127,21 @@ def test_flow_parameters_validated_on_host():
             workspace_bytes(p)
 
 
+def test_rigid_body_parameters_validated_on_host():
+    import workloads as W
+    from paper_1608_04904_amd import _capi, workspace_bytes
+    p = W.janus_system(L=16, rho=4, n_md=5, seed=3)
+    assert len(p["bonds"]) == 42
+    workspace_bytes(p)
+    workspace_bytes(dict(W.dimer_system(L=14, rho=4), rattle_iterative=1))
+    for bad in (dict(p, rattle_tol=0.0), dict(p, rattle_maxit=0), dict(p, rattle_maxit=200000),
+                dict(p, bonds=p["bonds"] + [p["bonds"][3]]),
+                dict(p, bonds=p["bonds"][:-1] + [(0, 0, 1.0)]),
+                dict(W.dimer_system(L=14, rho=4), rattle_iterative=2)):
+        with pytest.raises(_capi.RmpError):
+            workspace_bytes(bad)
+
+
 def test_product_package_has_no_oracle_dependency():
     pkg = os.path.join(ROOT, "paper_1608_04904_amd")
     for dirpath, _, files in os.walk(pkg):
