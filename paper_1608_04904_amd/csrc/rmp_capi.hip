@@ -237,6 +237,7 @@ struct rmp_batch {
     bool have_rule[2] = {false, false};
     bool multi_scan = false;
     bool any_analysis = false;
+    bool any_iterative = false;     // some occupied slot uses the iterative RATTLE
     rmp_tuning tun{256, 1, 0, 1, 1, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -559,6 +560,7 @@ rmp_status sync_ctl(rmp_batch* b)
     b->have_rule[0] = b->have_rule[1] = false;
     b->multi_scan = false;
     b->any_analysis = false;
+    b->any_iterative = false;
     for (int r = 0; r < S; ++r) {
         Replica& R = b->reps[r];
         int items[6] = {0, 0, 0, 0, 1, 1};
@@ -571,6 +573,7 @@ rmp_status sync_ctl(rmp_batch* b)
             b->have_rule[R.p.rule] = true;
             if (R.desc.n_scanblk > 1) b->multi_scan = true;
             if (R.an) b->any_analysis = true;
+            if (iterative_rattle(&R.p)) b->any_iterative = true;
             b->hdesc[r] = R.desc;
         } else {
             b->hdesc[r] = RepDesc{};
@@ -673,8 +676,9 @@ rmp_status launch_chain(rmp_batch* b, hipStream_t s)
     // more workgroups than the device holds at once: ticketed work list
     const bool ticket = b->totals[PF_CHAIN] > b->chain_resident[cs.q];
     // colloid count common to every occupied slot: 1 or 2 have unrolled
-    // variants, anything else (or a mix) the generic one
-    const int nc = b->nc_common == 1 || b->nc_common == 2 ? b->nc_common : 0;
+    // variants, anything else (or a mix, or an iterative RATTLE) the
+    // generic one
+    const int nc = !b->any_iterative && (b->nc_common == 1 || b->nc_common == 2) ? b->nc_common : 0;
     const Work w = work(b, PF_CHAIN);
     switch (cs.q) {
         case 0: launch_chain_shape<T, 1, 256>(b, s, g, ticket, nc, w); break;

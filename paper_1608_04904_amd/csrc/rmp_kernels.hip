@@ -1279,8 +1279,9 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     double cX[3] = {0.0, 0.0, 0.0}, cV[3] = {0.0, 0.0, 0.0}, cF[3] = {0.0, 0.0, 0.0};
     double cX0[3] = {0.0, 0.0, 0.0};
     const BondLane BL = bond_lane(cp, nc);
-    // iterative RATTLE: bond networks, or asked for (rattle_iterative)
-    const bool iter = NC != 1 && cp->iterative != 0;
+    // iterative RATTLE (bond networks, or asked for): generic variant only,
+    // the host launches it whenever a system of the launch needs it
+    const bool iter = NC == 0 && cp->iterative != 0;
     PairLane PL;
     PL.body = t < nc ? cp->body[t] : -1;
     PL.ctype = t < nc ? cp->ctype[t] : 0;
