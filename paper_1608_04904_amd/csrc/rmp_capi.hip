@@ -467,6 +467,19 @@ ColloidParams make_cp(const rmp_params* p)
     c.rattle_tol = p->rattle_tol;
     if (c.iterative)
         for (int i = 0; i < RMP_MAX_COLLOIDS; ++i) c.bond_of[i] = -1;   // no exact bond stage
+    // runs of consecutive bonds touching disjoint colloids (greedy, in order)
+    c.n_layers = 0;
+    for (int b = 0; b < p->n_bonds;) {
+        uint32_t used = 0;
+        c.layer_start[c.n_layers++] = b;
+        while (b < p->n_bonds) {
+            const uint32_t m = (1u << p->bond_a[b]) | (1u << p->bond_b[b]);
+            if (used & m) break;
+            used |= m;
+            ++b;
+        }
+    }
+    c.layer_start[c.n_layers] = p->n_bonds;
     // rigid bodies: merge the two bodies joined by a bond into the smaller
     // label until every bond lies inside one body
     for (bool merged = true; merged;) {

@@ -33,6 +33,10 @@ struct ColloidParams {
     double bond_d[RMP_MAX_BONDS];
     int32_t iterative, rattle_maxit;                     // iterative RATTLE for bond networks
     double rattle_tol;
+    // the bond order cut into runs of consecutive bonds with no colloid in
+    // common: within a run the sweep's corrections commute exactly
+    int32_t n_layers;
+    int32_t layer_start[RMP_MAX_BONDS + 1];
     double sigma[MAXC], sig2[MAXC], rc2[MAXC], reachR[MAXC];
     double epsA[MAXC], epsB[MAXC];
     double mass[MAXC], imass[MAXC], hc[MAXC];

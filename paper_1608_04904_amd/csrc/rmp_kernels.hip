@@ -767,78 +767,96 @@ __device__ __forceinline__ void rattle_pos_lane(const BondLane& L, double dt, do
     }
 }
 
-// Iterative RATTLE (Andersen 1983) for bond networks, run by one lane on
-// the colloid state staged in LDS.  Position stage: sweeps over the bonds in
-// order; a bond whose squared length s.s misses d^2 by more than 2 tol d^2 is
-// corrected along its direction before the drift, r0: both colloids move by
-// g r0 / m, g = (d^2 - s.s) / (2 mu s.r0), mu = 1/m_a + 1/m_b, and their
-// velocities by the same displacement over dt; until a sweep changes
-// nothing, at most rattle_maxit sweeps (else the RATTLE flag).
-__device__ __noinline__ uint32_t rattle_pos_iter(double (*X)[3], double (*V)[3], const double (*Xo)[3],
-                                                 const ColloidParams* cp, double dt)
+// Iterative RATTLE (Andersen 1983) for bond networks, by the 64 lanes of
+// wave 0 on the colloid state staged in LDS.  Position stage: sweeps over
+// the bonds in order; a bond whose squared length s.s misses d^2 by more than
+// 2 tol d^2 is corrected along its direction before the drift, r0: both
+// colloids move by g r0 / m, g = (d^2 - s.s) / (2 mu s.r0), mu = 1/m_a +
+// 1/m_b, and their velocities by the same displacement over dt; until a
+// sweep changes nothing, at most rattle_maxit sweeps (else the RATTLE flag).
+// A sweep runs layer by layer, a layer being consecutive bonds with no
+// colloid in common, one lane per bond: the corrections within a layer
+// commute exactly, so the result is that of the bonds one after another.
+template <class Ctx>
+__device__ __forceinline__ uint32_t rattle_pos_iter(Ctx& S, const ColloidParams* cp, double dt)
 {
+    const int lane = threadIdx.x & 63;
     const double tol = cp->rattle_tol;
+    const int nl = cp->n_layers;
     bool moved = true;
     for (int sweep = 0; sweep < cp->rattle_maxit && moved; ++sweep) {
-        moved = false;
-        for (int q = 0; q < cp->nbonds; ++q) {
-            const int a = cp->bond_a[q], b = cp->bond_b[q];
-            const double dd2 = cp->bond_d[q] * cp->bond_d[q];
-            double sv[3], r0[3];
-            for (int d = 0; d < 3; ++d) {
-                sv[d] = X[a][d] - X[b][d];
-                r0[d] = Xo[a][d] - Xo[b][d];
-            }
-            const double ss = dot3(sv[0], sv[1], sv[2], sv[0], sv[1], sv[2]);
-            const double diff = dd2 - ss;
-            if (fabs(diff) > (2.0 * tol) * dd2) {
-                const double mu = cp->imass[a] + cp->imass[b];
-                const double sr0 = dot3(sv[0], sv[1], sv[2], r0[0], r0[1], r0[2]);
-                const double g = diff / ((2.0 * mu) * sr0);
-                const double ga = g * cp->imass[a], gb = g * cp->imass[b];
-                const double gad = ga / dt, gbd = gb / dt;
+        bool m = false;
+        for (int L = 0; L < nl; ++L) {
+            const int q = cp->layer_start[L] + lane;
+            if (q < cp->layer_start[L + 1]) {
+                const int a = cp->bond_a[q], b = cp->bond_b[q];
+                const double dd2 = cp->bond_d[q] * cp->bond_d[q];
+                double sv[3], r0[3];
                 for (int d = 0; d < 3; ++d) {
-                    X[a][d] = X[a][d] + (ga * r0[d]);
-                    X[b][d] = X[b][d] - (gb * r0[d]);
-                    V[a][d] = V[a][d] + (gad * r0[d]);
-                    V[b][d] = V[b][d] - (gbd * r0[d]);
+                    sv[d] = S.sXc[a][d] - S.sXc[b][d];
+                    r0[d] = S.sXoc[a][d] - S.sXoc[b][d];
                 }
-                moved = true;
+                const double ss = dot3(sv[0], sv[1], sv[2], sv[0], sv[1], sv[2]);
+                const double diff = dd2 - ss;
+                if (fabs(diff) > (2.0 * tol) * dd2) {
+                    const double mu = cp->imass[a] + cp->imass[b];
+                    const double sr0 = dot3(sv[0], sv[1], sv[2], r0[0], r0[1], r0[2]);
+                    const double g = diff / ((2.0 * mu) * sr0);
+                    const double ga = g * cp->imass[a], gb = g * cp->imass[b];
+                    const double gad = ga / dt, gbd = gb / dt;
+                    for (int d = 0; d < 3; ++d) {
+                        S.sXc[a][d] = S.sXc[a][d] + (ga * r0[d]);
+                        S.sXc[b][d] = S.sXc[b][d] - (gb * r0[d]);
+                        S.sVc[a][d] = S.sVc[a][d] + (gad * r0[d]);
+                        S.sVc[b][d] = S.sVc[b][d] - (gbd * r0[d]);
+                    }
+                    m = true;
+                }
             }
+            wave_sync();
         }
+        moved = __ballot(m) != 0ull;
     }
     return moved ? RMP_FLAG_RATTLE : 0u;
 }
 
 // Iterative RATTLE, velocity stage: sweeps removing the relative velocity
-// along each bond, k = (r.v) / (mu d^2), while |r.v| exceeds tol d^2 / dt.
-__device__ __noinline__ uint32_t rattle_vel_iter(const double (*X)[3], double (*V)[3], const ColloidParams* cp,
-                                                 double dt)
+// along each bond, k = (r.v) / (mu d^2), while |r.v| exceeds tol d^2 / dt
+// (layer by layer, as above).
+template <class Ctx>
+__device__ __forceinline__ uint32_t rattle_vel_iter(Ctx& S, const ColloidParams* cp, double dt)
 {
+    const int lane = threadIdx.x & 63;
     const double tol = cp->rattle_tol;
+    const int nl = cp->n_layers;
     bool moved = true;
     for (int sweep = 0; sweep < cp->rattle_maxit && moved; ++sweep) {
-        moved = false;
-        for (int q = 0; q < cp->nbonds; ++q) {
-            const int a = cp->bond_a[q], b = cp->bond_b[q];
-            const double dd2 = cp->bond_d[q] * cp->bond_d[q];
-            double r[3], vr[3];
-            for (int d = 0; d < 3; ++d) {
-                r[d] = X[a][d] - X[b][d];
-                vr[d] = V[a][d] - V[b][d];
-            }
-            const double rv = dot3(r[0], r[1], r[2], vr[0], vr[1], vr[2]);
-            if (fabs(rv) > (tol * dd2) / dt) {
-                const double mu = cp->imass[a] + cp->imass[b];
-                const double k = rv / (mu * dd2);
-                const double ka = k * cp->imass[a], kb = k * cp->imass[b];
+        bool m = false;
+        for (int L = 0; L < nl; ++L) {
+            const int q = cp->layer_start[L] + lane;
+            if (q < cp->layer_start[L + 1]) {
+                const int a = cp->bond_a[q], b = cp->bond_b[q];
+                const double dd2 = cp->bond_d[q] * cp->bond_d[q];
+                double r[3], vr[3];
                 for (int d = 0; d < 3; ++d) {
-                    V[a][d] = V[a][d] - (ka * r[d]);
-                    V[b][d] = V[b][d] + (kb * r[d]);
+                    r[d] = S.sXc[a][d] - S.sXc[b][d];
+                    vr[d] = S.sVc[a][d] - S.sVc[b][d];
                 }
-                moved = true;
+                const double rv = dot3(r[0], r[1], r[2], vr[0], vr[1], vr[2]);
+                if (fabs(rv) > (tol * dd2) / dt) {
+                    const double mu = cp->imass[a] + cp->imass[b];
+                    const double k = rv / (mu * dd2);
+                    const double ka = k * cp->imass[a], kb = k * cp->imass[b];
+                    for (int d = 0; d < 3; ++d) {
+                        S.sVc[a][d] = S.sVc[a][d] - (ka * r[d]);
+                        S.sVc[b][d] = S.sVc[b][d] + (kb * r[d]);
+                    }
+                    m = true;
+                }
             }
+            wave_sync();
         }
+        moved = __ballot(m) != 0ull;
     }
     return moved ? RMP_FLAG_RATTLE : 0u;
 }
@@ -1371,7 +1389,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
             }
             uint32_t lflags = 0;
             if (iter) {
-                // bond network: one lane sweeps over the bonds on the
+                // bond network: wave 0 sweeps over the bonds on the
                 // colloid state staged in LDS
                 if (t < nc)
                     for (int d = 0; d < 3; ++d) {
@@ -1380,7 +1398,10 @@ __device__ __forceinline__ void chain_run(Work w, int item)
                         S.sXoc[t][d] = cXo[d];
                     }
                 wave_sync();
-                if (t == 0) lflags |= rattle_pos_iter(S.sXc, S.sVc, S.sXoc, cp, dt);
+                {
+                    const uint32_t f = rattle_pos_iter(S, cp, dt);   // all lanes of wave 0
+                    if (t == 0) lflags |= f;
+                }
                 wave_sync();
                 if (t < nc)
                     for (int d = 0; d < 3; ++d) {
@@ -1454,7 +1475,8 @@ __device__ __forceinline__ void chain_run(Work w, int item)
                     }
                 wave_sync();
                 uint32_t vflags = 0;
-                if (t == 0) vflags = rattle_vel_iter(S.sXc, S.sVc, cp, dt);
+                vflags = rattle_vel_iter(S, cp, dt);
+                if (t != 0) vflags = 0;
                 if (vflags) atomicOr(&S.sflags, vflags);
                 wave_sync();
                 if (t < nc)

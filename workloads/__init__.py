@@ -186,10 +186,18 @@ def add_janus(p: dict, centre, rng: np.random.Generator, shell=2.5, sigma=2.0,
         e = eps_cat if cat else eps_non
         ids.append(add_colloid(p, c0 + R @ V[k], sigma, e[0], e[1], catalytic=bool(cat),
                                ctype=TYPE_C if cat else TYPE_N))
-    for k in range(12):
-        p["bonds"].append((centre_i, ids[k], float(shell)))
-    for i, j in edges:
-        p["bonds"].append((ids[i], ids[j], float(np.linalg.norm(V[i] - V[j]))))
+    bonds = [(centre_i, ids[k], float(shell)) for k in range(12)]
+    bonds += [(ids[i], ids[j], float(np.linalg.norm(V[i] - V[j]))) for i, j in edges]
+    # order the bonds as successive sets with no colloid in common (greedy),
+    # so that a sweep of the iterative RATTLE has few dependent steps
+    while bonds:
+        used, layer = set(), []
+        for bd in bonds:
+            if bd[0] not in used and bd[1] not in used:
+                layer.append(bd)
+                used |= {bd[0], bd[1]}
+        bonds = [bd for bd in bonds if bd not in layer]
+        p["bonds"].extend(layer)
     return list(range(first, first + 13))
 
 
