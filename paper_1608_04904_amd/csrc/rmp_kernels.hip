@@ -1162,7 +1162,8 @@ __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0
 // Constants of the colloid of lane c (c < nc) used by the pair forces,
 // loaded once per interval
 struct PairLane {
-    int body, ctype;           // rigid body of the colloid (no forces inside a body)
+    uint32_t same;             // bit a set: colloid a is in this colloid's rigid body (no force)
+    int ctype;
     double sigma;
 };
 
@@ -1207,7 +1208,7 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT>& S, const RepDesc& D,
         const int c = t;
         double F[3] = {-S.sNode[3 * c + 0], -S.sNode[3 * c + 1], -S.sNode[3 * c + 2]};
         for (int a = 0; a < nc; ++a) {
-            if (a == c || cp->body[a] == PL.body) continue;
+            if ((PL.same >> a) & 1u) continue;      // itself or its own rigid body
             // colloid a's constants by its (uniform) index, this lane's from
             // registers; operands in the pair's (lo, hi) order
             const double sig_a = S.cSigma[a];
@@ -1301,7 +1302,10 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     // the host launches it whenever a system of the launch needs it
     const bool iter = NC == 0 && cp->iterative != 0;
     PairLane PL;
-    PL.body = t < nc ? cp->body[t] : -1;
+    PL.same = 0u;
+    if (t < nc)
+        for (int a = 0; a < nc; ++a)
+            if (cp->body[a] == cp->body[t]) PL.same |= 1u << a;
     PL.ctype = t < nc ? cp->ctype[t] : 0;
     PL.sigma = t < nc ? cp->sigma[t] : 0.0;
     const double chc = t < nc ? cp->hc[t] : 0.0;
