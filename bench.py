@@ -272,7 +272,11 @@ def run_single(name, precision, steps, warmup, profile_steps, tun):
         flops = FLOPS_PER_LIST_STEP * n_cand * n_md
         achieved = flops / (avg_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP64_PEAK_TFLOPS)
+                    frac=achieved / FP64_PEAK_TFLOPS,
+                    # what does bound it: one cross-workgroup exchange per MD step
+                    us_per_md_step=1e3 * avg_ms / n_md,
+                    note="latency-bound: n_md dependent MD steps, each ending in a "
+                         "cross-workgroup exchange of the colloid forces")
     else:
         achieved = algorithmic_bytes(dom, n, ncell, tb, n_cand, flow) / (avg_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
