@@ -787,10 +787,10 @@ __device__ __forceinline__ uint32_t rattle_pos_iter(Ctx& S, const ColloidParams*
     for (int sweep = 0; sweep < cp->rattle_maxit && moved; ++sweep) {
         bool m = false;
         for (int L = 0; L < nl; ++L) {
-            const int q = cp->layer_start[L] + lane;
-            if (q < cp->layer_start[L + 1]) {
-                const int a = cp->bond_a[q], b = cp->bond_b[q];
-                const double dd2 = cp->bond_d[q] * cp->bond_d[q];
+            const int q = S.sLay[L] + lane;
+            if (q < S.sLay[L + 1]) {
+                const int a = S.sBa[q], b = S.sBb[q];
+                const double dd2 = S.sBd2[q];
                 double sv[3], r0[3];
                 for (int d = 0; d < 3; ++d) {
                     sv[d] = S.sXc[a][d] - S.sXc[b][d];
@@ -799,10 +799,11 @@ __device__ __forceinline__ uint32_t rattle_pos_iter(Ctx& S, const ColloidParams*
                 const double ss = dot3(sv[0], sv[1], sv[2], sv[0], sv[1], sv[2]);
                 const double diff = dd2 - ss;
                 if (fabs(diff) > (2.0 * tol) * dd2) {
-                    const double mu = cp->imass[a] + cp->imass[b];
+                    const double ima = S.sIm[a], imb = S.sIm[b];
+                    const double mu = ima + imb;
                     const double sr0 = dot3(sv[0], sv[1], sv[2], r0[0], r0[1], r0[2]);
                     const double g = diff / ((2.0 * mu) * sr0);
-                    const double ga = g * cp->imass[a], gb = g * cp->imass[b];
+                    const double ga = g * ima, gb = g * imb;
                     const double gad = ga / dt, gbd = gb / dt;
                     for (int d = 0; d < 3; ++d) {
                         S.sXc[a][d] = S.sXc[a][d] + (ga * r0[d]);
@@ -833,10 +834,10 @@ __device__ __forceinline__ uint32_t rattle_vel_iter(Ctx& S, const ColloidParams*
     for (int sweep = 0; sweep < cp->rattle_maxit && moved; ++sweep) {
         bool m = false;
         for (int L = 0; L < nl; ++L) {
-            const int q = cp->layer_start[L] + lane;
-            if (q < cp->layer_start[L + 1]) {
-                const int a = cp->bond_a[q], b = cp->bond_b[q];
-                const double dd2 = cp->bond_d[q] * cp->bond_d[q];
+            const int q = S.sLay[L] + lane;
+            if (q < S.sLay[L + 1]) {
+                const int a = S.sBa[q], b = S.sBb[q];
+                const double dd2 = S.sBd2[q];
                 double r[3], vr[3];
                 for (int d = 0; d < 3; ++d) {
                     r[d] = S.sXc[a][d] - S.sXc[b][d];
@@ -844,9 +845,10 @@ __device__ __forceinline__ uint32_t rattle_vel_iter(Ctx& S, const ColloidParams*
                 }
                 const double rv = dot3(r[0], r[1], r[2], vr[0], vr[1], vr[2]);
                 if (fabs(rv) > (tol * dd2) / dt) {
-                    const double mu = cp->imass[a] + cp->imass[b];
+                    const double ima = S.sIm[a], imb = S.sIm[b];
+                    const double mu = ima + imb;
                     const double k = rv / (mu * dd2);
-                    const double ka = k * cp->imass[a], kb = k * cp->imass[b];
+                    const double ka = k * ima, kb = k * imb;
                     for (int d = 0; d < 3; ++d) {
                         S.sVc[a][d] = S.sVc[a][d] - (ka * r[d]);
                         S.sVc[b][d] = S.sVc[b][d] + (kb * r[d]);
@@ -905,8 +907,10 @@ struct ChainCtx {
     double sNode[NVAL_MAX];
     double sU;
     uint32_t sflags;
-    // colloid state staged for the iterative RATTLE (bond networks)
+    // colloid state and bonds staged for the iterative RATTLE (bond networks)
     double sXc[MAXC][3], sVc[MAXC][3], sXoc[MAXC][3];
+    double sIm[MAXC], sBd2[RMP_MAX_BONDS];
+    int32_t sBa[RMP_MAX_BONDS], sBb[RMP_MAX_BONDS], sLay[RMP_MAX_BONDS + 1];
 };
 
 // species_dU for an A -> B flip inside the MD chain, with the colloid
@@ -1323,6 +1327,16 @@ __device__ __forceinline__ void chain_run(Work w, int item)
         S.cSigma[t] = cp->sigma[t];
         S.cCat[t] = cp->catalytic[t];
         S.cType[t] = cp->ctype[t];
+    }
+    if (iter) {
+        // bonds of the iterative RATTLE in LDS for the interval
+        for (int q = t; q < cp->nbonds; q += NT) {
+            S.sBa[q] = cp->bond_a[q];
+            S.sBb[q] = cp->bond_b[q];
+            S.sBd2[q] = cp->bond_d[q] * cp->bond_d[q];
+        }
+        for (int L = t; L <= cp->n_layers; L += NT) S.sLay[L] = cp->layer_start[L];
+        if (t < nc) S.sIm[t] = cp->imass[t];
     }
     const int64_t coll = rs->coll_step;
     const int cur = (int)(coll & 1);
