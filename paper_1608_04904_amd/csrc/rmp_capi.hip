@@ -236,6 +236,7 @@ struct rmp_batch {
     bool dirty = true;
     bool have_rule[2] = {false, false};
     bool multi_scan = false;
+    int32_t max_scanblk = 0;        // most scan blocks of any occupied slot
     bool any_analysis = false;
     bool any_iterative = false;     // some occupied slot uses the iterative RATTLE
     rmp_tuning tun{256, 1, 0, 1, 1, 0, 0};
@@ -572,6 +573,7 @@ rmp_status sync_ctl(rmp_batch* b)
     for (int k = 0; k < 6; ++k) b->hprefix[k].assign(S + 1, 0);
     b->have_rule[0] = b->have_rule[1] = false;
     b->multi_scan = false;
+    b->max_scanblk = 0;
     b->any_analysis = false;
     b->any_iterative = false;
     for (int r = 0; r < S; ++r) {
@@ -585,6 +587,7 @@ rmp_status sync_ctl(rmp_batch* b)
             items[PF_CHAIN] = R.desc.G;
             b->have_rule[R.p.rule] = true;
             if (R.desc.n_scanblk > 1) b->multi_scan = true;
+            b->max_scanblk = std::max(b->max_scanblk, R.desc.n_scanblk);
             if (R.an) b->any_analysis = true;
             if (iterative_rattle(&R.p)) b->any_iterative = true;
             b->hdesc[r] = R.desc;
@@ -747,13 +750,15 @@ rmp_status launch_interval(rmp_batch* b, hipStream_t s)
     }
     HIPCHK(hipEventRecord(b->join, b->side));
     HIPCHK(hipStreamWaitEvent(s, b->join, 0));
-    if (b->multi_scan) {
+    // small grids: each scan block sums the counts before it itself
+    const int direct = b->max_scanblk <= SCAN_DIRECT_BLOCKS ? 1 : 0;
+    if (b->multi_scan && !direct) {
         Timer tm(b, KN_SCANB, s);
         hipLaunchKernelGGL(k_scan_blocks, dim3(b->totals[PF_SCAN]), dim3(1024), 0, s, work(b, PF_SCAN));
     }
     {
         Timer tm(b, KN_SCANF, s);
-        hipLaunchKernelGGL(k_scan_final, dim3(b->totals[PF_SCAN]), dim3(1024), 0, s, work(b, PF_SCAN));
+        hipLaunchKernelGGL(k_scan_final, dim3(b->totals[PF_SCAN]), dim3(1024), 0, s, work(b, PF_SCAN), direct);
     }
     {
         Timer tm(b, KN_SCATTER, s);

@@ -11,6 +11,7 @@ namespace rmp {
 constexpr int MAXC = RMP_MAX_COLLOIDS;
 constexpr int CHUNK = 1024;          // particles per chunk (list compaction, init, observables)
 constexpr int SCAN_BLK = 4096;       // cells per block of the multi-block cell scan
+constexpr int SCAN_DIRECT_BLOCKS = 8; // up to this many blocks, no separate block-sum pass
 constexpr int CHAIN_BLOCK = 256;     // threads per Verlet-list workgroup
 constexpr int NVAL_MAX = 3 * MAXC + 1;  // reduced values per MD step: F per colloid + U
 constexpr uint64_t BARRIER_BUDGET_TICKS = 25000000;  // 0.25 s of the 100 MHz wall clock

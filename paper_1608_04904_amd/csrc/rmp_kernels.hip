@@ -1605,7 +1605,10 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(Work w)
     if (threadIdx.x == 0) D.scanblk[blk] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_final(Work w)
+// `direct`: the launch's grids are small (at most SCAN_DIRECT_BLOCKS blocks
+// each), so a block sums the counts of the blocks before it itself and no
+// k_scan_blocks pass is launched.
+__global__ __launch_bounds__(1024) void k_scan_final(Work w, int direct)
 {
     const int item = blockIdx.x;
     const int rep = find_rep(w.prefix, w.nrep, item);
@@ -1614,7 +1617,18 @@ __global__ __launch_bounds__(1024) void k_scan_final(Work w)
     if (!D.active) return;
     __shared__ uint32_t sbuf[16];
     uint32_t pre = 0;
-    for (int k = threadIdx.x; k < blk; k += 1024) pre += D.scanblk[k];
+    if (direct) {
+        // counts of cells [0, blk * SCAN_BLK): 4 loads in flight per thread
+        const int64_t m = (int64_t)blk * SCAN_BLK;
+        for (int64_t c = threadIdx.x; c < m; c += 4 * 1024) {
+            uint32_t q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = c + u * 1024 < m ? D.count[c + u * 1024] : 0u;
+            pre += (q[0] + q[1]) + (q[2] + q[3]);
+        }
+    } else {
+        for (int k = threadIdx.x; k < blk; k += 1024) pre += D.scanblk[k];
+    }
     pre = block_sum_u32<1024>(pre, sbuf);
     constexpr int PER = SCAN_BLK / 1024;
     const int64_t c0 = (int64_t)blk * SCAN_BLK + (int64_t)threadIdx.x * PER;
@@ -1633,7 +1647,6 @@ __global__ __launch_bounds__(1024) void k_scan_final(Work w)
         int64_t c = c0 + k;
         if (c < D.ncell) {
             D.start[c] = p;
-            D.count[c] = 0;
             p += cnt[k];
         }
     }
@@ -1719,7 +1732,12 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
     const int64_t c0 = (int64_t)tile * TC;
     const int64_t c1 = (c0 + TC < D.ncell) ? c0 + TC : D.ncell;
     const int ncl = (int)(c1 - c0);
-    for (int k = t; k <= ncl; k += COLL_NT) s_start[k] = D.start[c0 + k];
+    for (int k = t; k <= ncl; k += COLL_NT) {
+        s_start[k] = D.start[c0 + k];
+        // the cell counters are read by the scans; zero them for the next
+        // interval's binning (every cell lies in exactly one tile)
+        if (k < ncl) D.count[c0 + k] = 0;
+    }
     if (t < nc)
         for (int d = 0; d < 3; ++d) s_Xw[t][d] = colloid_image(rs->X[t][d], D.Ld[d]);
     __syncthreads();
