@@ -51,10 +51,10 @@ def algorithmic_bytes(kernel: str, n: int, ncell: int, tb: int, n_cand: int,
     stream_bin  per free particle: read x, v (6 tb) + list flag (1), write x
                 (3 tb) + key/rank (8); cell counters 8 B per cell.
     collide     per particle: read perm (4), x, v (6 tb), id (4), state (1);
-                write x, v (6 tb), id (4), state (1), list flag (1); cell
-                starts 4 B per cell.
+                write x, v (6 tb), id (4), state (1), list flag (1); per
+                cell: read the start (4), zero the counter (4).
     scatter     per particle: read key/rank (8), write perm (4); starts 4/cell.
-    scan_final  per cell: read count (4), write start (4), clear count (4).
+    scan_final  per cell: read count (4), write start (4).
     stream_bin  with a flow (acceleration, plates) every particle also writes
                 its velocity: read x, v (6 tb) + flag (1), write x, v (6 tb)
                 + key/rank (8).
@@ -65,11 +65,11 @@ def algorithmic_bytes(kernel: str, n: int, ncell: int, tb: int, n_cand: int,
     if kernel == "stream_bin":
         return nf * ((12 if flow else 9) * tb + 9) + 8 * ncell
     if kernel == "collide":
-        return n * (12 * tb + 15) + 4 * ncell
+        return n * (12 * tb + 15) + 8 * ncell
     if kernel == "scatter":
         return n * 12 + 4 * ncell
     if kernel == "scan_final":
-        return 12 * ncell
+        return 8 * ncell
     if kernel == "chain":
         return n_cand * (12 * tb + 2)
     if kernel == "analysis":
