@@ -455,7 +455,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(each replica or job is independent; the design notes describe how a "
               "single large system would shard).", file=sys.stderr)
         sys.exit(2)
