@@ -251,6 +251,37 @@ def test_fp64_full_size_dimer32_one_interval():
     _assert_obs(g.observables(), o.observables())
 
 
+def test_fp64_full_size_sphere10():
+    """The single-sphere configuration at full size (10^3 cells, rho 10,
+    10,000 particles, 10 MD steps per collision), five intervals."""
+    rm = _rm()
+    p = W.sphere10()
+    s0 = W.random_state(p, 110, species_B_fraction=0.1)
+    g, o = _run_both(p, s0, W.BASE_SEED + 1, 10, 5)
+    _assert_bitwise(g.get_state(), o.get_state(), "sphere10")
+    _assert_obs(g.observables(), o.observables())
+
+
+def test_fp64_full_size_batch_of_64_sampled_slots():
+    """The 64-replica ensemble at full size (box edges from {16, 20, 24, 32},
+    8.47 M particles, per-replica seeds) in FP64, one tick: sampled slots
+    equal the oracle run of that replica alone, bit for bit."""
+    rm = _rm()
+    reps = [dict(p, precision=64) for p in W.batch_replicas(n=64, precision=64)]
+    b = rm.Batch(len(reps), precision=64)
+    for i, p in enumerate(reps):
+        b.set_slot(i, p, p["seed"], p["n_md"])
+    states = {i: b.get_state(i) for i in (0, 17, 40, 63)}
+    b.step(1)
+    for i, s0 in states.items():
+        p = reps[i]
+        print(f"[parity] batch slot {i} L={p['L']}", flush=True)
+        o = oracle.Oracle(p, p["seed"], init=False)
+        o.set_state(s0)
+        o.run(p["n_md"], 1)
+        _assert_bitwise(b.get_state(i), o.get_state(), f"slot {i}")
+
+
 def test_fp64_full_size_large128_one_interval():
     """The large single system at full size: 128^3 cells, 20,971,520
     particles, 8 dimers, N_MD = 50, default launch shape (the chain with
