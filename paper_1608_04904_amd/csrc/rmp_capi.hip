@@ -239,6 +239,7 @@ struct rmp_batch {
     int32_t max_scanblk = 0;        // most scan blocks of any occupied slot
     bool any_analysis = false;
     bool any_iterative = false;     // some occupied slot uses the iterative RATTLE
+    int64_t n_total = 0;            // solvent particles over the occupied slots
     rmp_tuning tun{256, 1, 0, 1, 1, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -286,6 +287,8 @@ rmp_status last_launch(const char* what)
     }
     return RMP_OK;
 }
+
+constexpr int64_t CHAIN_PRIO_MAX_PARTICLES = (int64_t)1 << 22;
 
 // Shape of the MD-chain workgroups: NT threads with K list entries each.
 // Shapes 0, 1, 2: 256 threads with K = 1, 2, 4; shape 3: 512 threads, K = 1.
@@ -576,6 +579,7 @@ rmp_status sync_ctl(rmp_batch* b)
     b->max_scanblk = 0;
     b->any_analysis = false;
     b->any_iterative = false;
+    b->n_total = 0;
     for (int r = 0; r < S; ++r) {
         Replica& R = b->reps[r];
         int items[6] = {0, 0, 0, 0, 1, 1};
@@ -590,6 +594,7 @@ rmp_status sync_ctl(rmp_batch* b)
             b->max_scanblk = std::max(b->max_scanblk, R.desc.n_scanblk);
             if (R.an) b->any_analysis = true;
             if (iterative_rattle(&R.p)) b->any_iterative = true;
+            b->n_total += R.p.n_solvent;
             b->hdesc[r] = R.desc;
         } else {
             b->hdesc[r] = RepDesc{};
@@ -623,7 +628,7 @@ Work work(const rmp_batch* b, int kind)
     w.prefix = b->d_prefix[kind];
     w.tick = b->d_tick;
     w.nrep = b->nslots;
-    w.pad = 0;
+    w.flags = 0;
     return w;
 }
 
@@ -695,7 +700,12 @@ rmp_status launch_chain(rmp_batch* b, hipStream_t s)
     // variants, anything else (or a mix, or an iterative RATTLE) the
     // generic one
     const int nc = !b->any_iterative && (b->nc_common == 1 || b->nc_common == 2) ? b->nc_common : 0;
-    const Work w = work(b, PF_CHAIN);
+    Work w = work(b, PF_CHAIN);
+    // small launches: the chain's dependent steps are the whole critical
+    // path, so its waves take issue priority over the streaming kernel that
+    // shares the compute units (measured: 32^3 +2 %; at 128^3, where the
+    // streaming kernel is long, -1.5 %, hence the size limit)
+    if (b->n_total <= CHAIN_PRIO_MAX_PARTICLES) w.flags |= WORK_CHAIN_PRIO;
     switch (cs.q) {
         case 0: launch_chain_shape<T, 1, 256>(b, s, g, ticket, nc, w); break;
         case 1: launch_chain_shape<T, 2, 256>(b, s, g, ticket, nc, w); break;
@@ -997,7 +1007,7 @@ rmp_status observe(rmp_batch* b, int slot, rmp_obs* o)
     w.desc = b->d_desc + slot;
     w.prefix = b->d_prefix[PF_REP];
     w.nrep = 1;
-    w.pad = 0;
+    w.flags = 0;
     hipLaunchKernelGGL((k_observe<T>), dim3(cnt), dim3(256), 0, s, w);
     st = last_launch("k_observe");
     if (st != RMP_OK) return st;

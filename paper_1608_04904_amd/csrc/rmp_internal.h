@@ -116,6 +116,8 @@ struct RepDesc {
     Analysis* an;              // dimer analysis, nullptr when off
 };
 
+constexpr int32_t WORK_CHAIN_PRIO = 1;
+
 // Work lists: items of one kind (particle chunks, cell tiles, scan blocks,
 // chain workgroups) concatenated over replicas.  prefix[r] is the first item
 // of replica r, prefix[nrep] the total.
@@ -124,7 +126,7 @@ struct Work {
     const int32_t* prefix;
     uint32_t* tick;   // [0] next ticket, [1] finished workgroups; zero between launches
     int32_t nrep;
-    int32_t pad;
+    int32_t flags;    // WORK_CHAIN_PRIO: the MD chain raises its waves' issue priority
 };
 
 }  // namespace rmp
