@@ -777,44 +777,87 @@ __device__ __forceinline__ void rattle_pos_lane(const BondLane& L, double dt, do
 // A sweep runs layer by layer, a layer being consecutive bonds with no
 // colloid in common, one lane per bond: the corrections within a layer
 // commute exactly, so the result is that of the bonds one after another.
+//
+// A layer's lane reads both ends of its bond, their velocities and the
+// bond's constants (LDS tables filled once per interval and per stage) in
+// one round trip, and writes the results back together; the ends of the
+// next layer's bonds are read a layer ahead.
 template <class Ctx>
 __device__ __forceinline__ uint32_t rattle_pos_iter(Ctx& S, const ColloidParams* cp, double dt)
 {
     const int lane = threadIdx.x & 63;
-    const double tol = cp->rattle_tol;
-    const int nl = cp->n_layers;
+    const int nl = cp->n_layers, nbond = cp->nbonds;
+    for (int q = lane; q < nbond; q += 64) {
+        const int a = S.sBa[q], b = S.sBb[q];
+        for (int d = 0; d < 3; ++d) S.sBr[q][d] = S.sXoc[a][d] - S.sXoc[b][d];
+    }
+    wave_sync();
     bool moved = true;
     for (int sweep = 0; sweep < cp->rattle_maxit && moved; ++sweep) {
         bool m = false;
+        int s0 = S.sLay[0], s1 = nl > 0 ? S.sLay[1] : s0;
+        int a = 0, b = 0;
+        if (s0 + lane < s1) {
+            a = S.sBa[s0 + lane];
+            b = S.sBb[s0 + lane];
+        }
         for (int L = 0; L < nl; ++L) {
-            const int q = S.sLay[L] + lane;
-            if (q < S.sLay[L + 1]) {
-                const int a = S.sBa[q], b = S.sBb[q];
-                const double dd2 = S.sBd2[q];
-                double sv[3], r0[3];
+            const int q = s0 + lane;
+            const bool act = q < s1;
+            // both ends read at once (a != b) with the bond's constants,
+            // written back at once
+            double xa[3], xb[3], va[3], vb[3], r0[3];
+            double dd2 = 0.0, thr = 0.0, mu2 = 0.0, ima = 0.0, imb = 0.0;
+            if (act) {
                 for (int d = 0; d < 3; ++d) {
-                    sv[d] = S.sXc[a][d] - S.sXc[b][d];
-                    r0[d] = S.sXoc[a][d] - S.sXoc[b][d];
+                    xa[d] = S.sXc[a][d];
+                    xb[d] = S.sXc[b][d];
+                    r0[d] = S.sBr[q][d];
                 }
+                dd2 = S.sBd2[q];
+                thr = S.sBthr[q];
+                mu2 = S.sBmu2[q];
+                ima = S.sBia[q];
+                imb = S.sBib[q];
+                for (int d = 0; d < 3; ++d) {
+                    va[d] = S.sVc[a][d];
+                    vb[d] = S.sVc[b][d];
+                }
+            }
+            // ends of the next layer's bonds (unused past its end)
+            const int s2 = S.sLay[min(L + 2, nl)];
+            const int qn = s1 + lane;
+            int na = 0, nb = 0;
+            if (qn < nbond) {
+                na = S.sBa[qn];
+                nb = S.sBb[qn];
+            }
+            if (act) {
+                double sv[3];
+                for (int d = 0; d < 3; ++d) sv[d] = xa[d] - xb[d];
                 const double ss = dot3(sv[0], sv[1], sv[2], sv[0], sv[1], sv[2]);
                 const double diff = dd2 - ss;
-                if (fabs(diff) > (2.0 * tol) * dd2) {
-                    const double ima = S.sIm[a], imb = S.sIm[b];
-                    const double mu = ima + imb;
+                if (fabs(diff) > thr) {
                     const double sr0 = dot3(sv[0], sv[1], sv[2], r0[0], r0[1], r0[2]);
-                    const double g = diff / ((2.0 * mu) * sr0);
+                    const double g = diff / (mu2 * sr0);
                     const double ga = g * ima, gb = g * imb;
+                    for (int d = 0; d < 3; ++d) {
+                        S.sXc[a][d] = xa[d] + (ga * r0[d]);
+                        S.sXc[b][d] = xb[d] - (gb * r0[d]);
+                    }
                     const double gad = ga / dt, gbd = gb / dt;
                     for (int d = 0; d < 3; ++d) {
-                        S.sXc[a][d] = S.sXc[a][d] + (ga * r0[d]);
-                        S.sXc[b][d] = S.sXc[b][d] - (gb * r0[d]);
-                        S.sVc[a][d] = S.sVc[a][d] + (gad * r0[d]);
-                        S.sVc[b][d] = S.sVc[b][d] - (gbd * r0[d]);
+                        S.sVc[a][d] = va[d] + (gad * r0[d]);
+                        S.sVc[b][d] = vb[d] - (gbd * r0[d]);
                     }
                     m = true;
                 }
             }
             wave_sync();
+            s0 = s1;
+            s1 = s2;
+            a = na;
+            b = nb;
         }
         moved = __ballot(m) != 0ull;
     }
@@ -823,40 +866,69 @@ __device__ __forceinline__ uint32_t rattle_pos_iter(Ctx& S, const ColloidParams*
 
 // Iterative RATTLE, velocity stage: sweeps removing the relative velocity
 // along each bond, k = (r.v) / (mu d^2), while |r.v| exceeds tol d^2 / dt
-// (layer by layer, as above).
+// (layer by layer, as above; the bond vectors r are fixed for the stage).
 template <class Ctx>
 __device__ __forceinline__ uint32_t rattle_vel_iter(Ctx& S, const ColloidParams* cp, double dt)
 {
+    (void)dt;
     const int lane = threadIdx.x & 63;
-    const double tol = cp->rattle_tol;
-    const int nl = cp->n_layers;
+    const int nl = cp->n_layers, nbond = cp->nbonds;
+    for (int q = lane; q < nbond; q += 64) {
+        const int a = S.sBa[q], b = S.sBb[q];
+        for (int d = 0; d < 3; ++d) S.sBr[q][d] = S.sXc[a][d] - S.sXc[b][d];
+    }
+    wave_sync();
     bool moved = true;
     for (int sweep = 0; sweep < cp->rattle_maxit && moved; ++sweep) {
         bool m = false;
+        int s0 = S.sLay[0], s1 = nl > 0 ? S.sLay[1] : s0;
+        int a = 0, b = 0;
+        if (s0 + lane < s1) {
+            a = S.sBa[s0 + lane];
+            b = S.sBb[s0 + lane];
+        }
         for (int L = 0; L < nl; ++L) {
-            const int q = S.sLay[L] + lane;
-            if (q < S.sLay[L + 1]) {
-                const int a = S.sBa[q], b = S.sBb[q];
-                const double dd2 = S.sBd2[q];
-                double r[3], vr[3];
+            const int q = s0 + lane;
+            const bool act = q < s1;
+            double va[3], vb[3], r[3];
+            double thv = 0.0, mud = 0.0, ima = 0.0, imb = 0.0;
+            if (act) {
                 for (int d = 0; d < 3; ++d) {
-                    r[d] = S.sXc[a][d] - S.sXc[b][d];
-                    vr[d] = S.sVc[a][d] - S.sVc[b][d];
+                    va[d] = S.sVc[a][d];
+                    vb[d] = S.sVc[b][d];
+                    r[d] = S.sBr[q][d];
                 }
+                thv = S.sBthv[q];
+                mud = S.sBmud[q];
+                ima = S.sBia[q];
+                imb = S.sBib[q];
+            }
+            const int s2 = S.sLay[min(L + 2, nl)];
+            const int qn = s1 + lane;
+            int na = 0, nb = 0;
+            if (qn < nbond) {
+                na = S.sBa[qn];
+                nb = S.sBb[qn];
+            }
+            if (act) {
+                double vr[3];
+                for (int d = 0; d < 3; ++d) vr[d] = va[d] - vb[d];
                 const double rv = dot3(r[0], r[1], r[2], vr[0], vr[1], vr[2]);
-                if (fabs(rv) > (tol * dd2) / dt) {
-                    const double ima = S.sIm[a], imb = S.sIm[b];
-                    const double mu = ima + imb;
-                    const double k = rv / (mu * dd2);
+                if (fabs(rv) > thv) {
+                    const double k = rv / mud;
                     const double ka = k * ima, kb = k * imb;
                     for (int d = 0; d < 3; ++d) {
-                        S.sVc[a][d] = S.sVc[a][d] - (ka * r[d]);
-                        S.sVc[b][d] = S.sVc[b][d] + (kb * r[d]);
+                        S.sVc[a][d] = va[d] - (ka * r[d]);
+                        S.sVc[b][d] = vb[d] + (kb * r[d]);
                     }
                     m = true;
                 }
             }
             wave_sync();
+            s0 = s1;
+            s1 = s2;
+            a = na;
+            b = nb;
         }
         moved = __ballot(m) != 0ull;
     }
@@ -897,7 +969,9 @@ __device__ __forceinline__ void rattle_vel_lane(const BondLane& L, const double 
 // Chain workgroup g of a replica holds Verlet-list positions
 // [g*B, (g+1)*B), B = NT*K (NT = 256 or 512 threads), K consecutive
 // positions per thread, in registers for the whole interval.
-template <int NT>
+// NB: bond capacity of the iterative-RATTLE tables (1 in the variants
+// unrolled for one or two colloids, which never run it).
+template <int NT, int NB>
 struct ChainCtx {
     double sXw[MAXC][3];       // periodic images of the colloid positions
     // colloid constants read in every MD step, staged once per interval
@@ -908,9 +982,15 @@ struct ChainCtx {
     double sU;
     uint32_t sflags;
     // colloid state and bonds staged for the iterative RATTLE (bond networks)
-    double sXc[MAXC][3], sVc[MAXC][3], sXoc[MAXC][3];
-    double sIm[MAXC], sBd2[RMP_MAX_BONDS];
-    int32_t sBa[RMP_MAX_BONDS], sBb[RMP_MAX_BONDS], sLay[RMP_MAX_BONDS + 1];
+    static constexpr int NCI = NB > 1 ? MAXC : 1;
+    double sXc[NCI][3], sVc[NCI][3], sXoc[NCI][3];
+    int32_t sBa[NB], sBb[NB], sLay[NB + 1];
+    // per bond, for the interval: d^2, the two thresholds, the two mass
+    // factors and the inverse masses of its ends; for the stage under way:
+    // the bond vector that the stage holds fixed
+    double sBd2[NB], sBthr[NB], sBthv[NB];
+    double sBmu2[NB], sBmud[NB], sBia[NB], sBib[NB];
+    double sBr[NB][3];
 };
 
 // species_dU for an A -> B flip inside the MD chain, with the colloid
@@ -941,8 +1021,8 @@ __device__ __forceinline__ double species_dU_lds(const Ctx& S, const RepDesc& D,
 // binary tree (within a thread over K, over the lanes of a wave, over the
 // waves).  With several workgroups the node values are then published for
 // the others (chain_collect completes the tree over workgroups).
-template <class T, int K, int NT>
-__device__ __forceinline__ void chain_compute(ChainCtx<NT>& S, const RepDesc& D, const ColloidParams* cp,
+template <class T, int K, int NT, int NB>
+__device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const RepDesc& D, const ColloidParams* cp,
                               int nc, const bool* valid, const T (*x)[3], const uint8_t* st,
                               double (*f)[3], bool* inside, int g, int Gact,
                               uint32_t& nbar, uint32_t epoch0)
@@ -1171,8 +1251,8 @@ struct PairLane {
     double sigma;
 };
 
-template <class T, int K, int NT>
-__device__ __forceinline__ void chain_collect(ChainCtx<NT>& S, const RepDesc& D, const ColloidParams* cp,
+template <class T, int K, int NT, int NB>
+__device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const RepDesc& D, const ColloidParams* cp,
                               int nc, int Gact, int Gpad, uint32_t nbar, uint32_t epoch0,
                               bool want_potential, double (&cF)[3], const PairLane& PL)
 {
@@ -1294,7 +1374,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     int Gpad = 1;
     while (Gpad < Gact) Gpad <<= 1;
 
-    __shared__ ChainCtx<NT> S;
+    __shared__ ChainCtx<NT, NC == 0 ? RMP_MAX_BONDS : 1> S;
     const int t = threadIdx.x;
     if (t == 0) S.sflags = 0;
     // colloid c lives in registers of thread c (c < nc, wave 0): position,
@@ -1330,13 +1410,23 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     }
     if (iter) {
         // bonds of the iterative RATTLE in LDS for the interval
+        const double tol = cp->rattle_tol;
         for (int q = t; q < cp->nbonds; q += NT) {
-            S.sBa[q] = cp->bond_a[q];
-            S.sBb[q] = cp->bond_b[q];
-            S.sBd2[q] = cp->bond_d[q] * cp->bond_d[q];
+            const int a = cp->bond_a[q], b = cp->bond_b[q];
+            const double dd2 = cp->bond_d[q] * cp->bond_d[q];
+            const double ima = cp->imass[a], imb = cp->imass[b];
+            const double mu = ima + imb;
+            S.sBa[q] = a;
+            S.sBb[q] = b;
+            S.sBd2[q] = dd2;
+            S.sBthr[q] = (2.0 * tol) * dd2;
+            S.sBthv[q] = (tol * dd2) / D.dt;
+            S.sBmu2[q] = 2.0 * mu;
+            S.sBmud[q] = mu * dd2;
+            S.sBia[q] = ima;
+            S.sBib[q] = imb;
         }
         for (int L = t; L <= cp->n_layers; L += NT) S.sLay[L] = cp->layer_start[L];
-        if (t < nc) S.sIm[t] = cp->imass[t];
     }
     const int64_t coll = rs->coll_step;
     const int cur = (int)(coll & 1);
