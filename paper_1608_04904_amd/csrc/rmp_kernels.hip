@@ -969,6 +969,49 @@ __device__ __forceinline__ void rattle_vel_lane(const BondLane& L, const double 
 // Chain workgroup g of a replica holds Verlet-list positions
 // [g*B, (g+1)*B), B = NT*K (NT = 256 or 512 threads), K consecutive
 // positions per thread, in registers for the whole interval.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double uniform_d(double v)
+{
+    return __longlong_as_double((long long)uniform_u64((uint64_t)__double_as_longlong(v)));
+}
+
+// Descriptor fields used in every MD step, copied to scalar registers once:
+// read through the descriptor they are fetched again after each fence of
+// the exchange.
+struct ChainConst {
+    double Lv[3], hv[3];       // box lengths and half lengths
+    uint64_t* partv;           // exchange words
+    int Gv;                    // workgroups of the replica's exchange buffers
+    double catv;
+    uint64_t seedv;
+    __device__ double L(int d) const { return Lv[d]; }
+    __device__ double h(int d) const { return hv[d]; }
+    __device__ uint64_t* part() const { return partv; }
+    __device__ int G() const { return Gv; }
+    __device__ double cat_prob() const { return catv; }
+    __device__ uint64_t seed() const { return seedv; }
+};
+
+__device__ __forceinline__ ChainConst chain_const(const RepDesc& D)
+{
+    ChainConst c;
+    for (int d = 0; d < 3; ++d) {
+        c.Lv[d] = uniform_d(D.Ld[d]);
+        c.hv[d] = uniform_d(D.halfL[d]);
+    }
+    c.partv = reinterpret_cast<uint64_t*>(uniform_u64((uint64_t)(uintptr_t)D.partials));
+    c.Gv = __builtin_amdgcn_readfirstlane(D.G);
+    c.catv = uniform_d(D.cat_prob);
+    c.seedv = uniform_u64(D.seed);
+    return c;
+}
+
 // NB: bond capacity of the iterative-RATTLE tables (1 in the variants
 // unrolled for one or two colloids, which never run it).
 template <int NT, int NB>
@@ -996,14 +1039,14 @@ struct ChainCtx {
 // species_dU for an A -> B flip inside the MD chain, with the colloid
 // constants from LDS (same arithmetic)
 template <class Ctx>
-__device__ __forceinline__ double species_dU_lds(const Ctx& S, const RepDesc& D, int nc, double x0, double x1,
+__device__ __forceinline__ double species_dU_lds(const Ctx& S, const ChainConst& cc, int nc, double x0, double x1,
                                                  double x2)
 {
     double du = 0.0;
     for (int c = 0; c < nc; ++c) {
-        double dx = min_image(x0 - S.sXw[c][0], D.Ld[0], D.halfL[0]);
-        double dy = min_image(x1 - S.sXw[c][1], D.Ld[1], D.halfL[1]);
-        double dz = min_image(x2 - S.sXw[c][2], D.Ld[2], D.halfL[2]);
+        double dx = min_image(x0 - S.sXw[c][0], cc.L(0), cc.h(0));
+        double dy = min_image(x1 - S.sXw[c][1], cc.L(1), cc.h(1));
+        double dz = min_image(x2 - S.sXw[c][2], cc.L(2), cc.h(2));
         double r2 = dot3(dx, dy, dz, dx, dy, dz);
         if (r2 < S.cRc2[c]) {
             double cf, p0, p1;
@@ -1022,7 +1065,7 @@ __device__ __forceinline__ double species_dU_lds(const Ctx& S, const RepDesc& D,
 // waves).  With several workgroups the node values are then published for
 // the others (chain_collect completes the tree over workgroups).
 template <class T, int K, int NT, int NB>
-__device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const RepDesc& D, const ColloidParams* cp,
+__device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainConst& cc, const ColloidParams* cp,
                               int nc, const bool* valid, const T (*x)[3], const uint8_t* st,
                               double (*f)[3], bool* inside, int g, int Gact,
                               uint32_t& nbar, uint32_t epoch0)
@@ -1062,9 +1105,9 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const RepDesc
             bool hit[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                dxs[j] = min_image((double)x[j][0] - Xc0, D.Ld[0], D.halfL[0]);
-                dys[j] = min_image((double)x[j][1] - Xc1, D.Ld[1], D.halfL[1]);
-                dzs[j] = min_image((double)x[j][2] - Xc2, D.Ld[2], D.halfL[2]);
+                dxs[j] = min_image((double)x[j][0] - Xc0, cc.L(0), cc.h(0));
+                dys[j] = min_image((double)x[j][1] - Xc1, cc.L(1), cc.h(1));
+                dzs[j] = min_image((double)x[j][2] - Xc2, cc.L(2), cc.h(2));
                 r2s[j] = dot3(dxs[j], dys[j], dzs[j], dxs[j], dys[j], dzs[j]);
                 hit[j] = valid[j] && (r2s[j] < rc2);
                 any = any || hit[j];
@@ -1153,8 +1196,8 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const RepDesc
         // replica; the two buffers alternate between barriers.
         nbar++;
         const uint32_t epoch = epoch0 + nbar;
-        uint64_t* part = reinterpret_cast<uint64_t*>(D.partials) +
-                         (int64_t)(nbar & 1) * D.G * NVAL_MAX * 2;
+        uint64_t* part = cc.part() +
+                         (int64_t)(nbar & 1) * cc.G() * NVAL_MAX * 2;
         if (t < nv) {
             const double val = S.sNode[t];
             const uint64_t lo = ((uint64_t)(uint32_t)__double2loint(val) << 32) | epoch;
@@ -1252,7 +1295,7 @@ struct PairLane {
 };
 
 template <class T, int K, int NT, int NB>
-__device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const RepDesc& D, const ColloidParams* cp,
+__device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const ChainConst& cc, const ColloidParams* cp,
                               int nc, int Gact, int Gpad, uint32_t nbar, uint32_t epoch0,
                               bool want_potential, double (&cF)[3], const PairLane& PL)
 {
@@ -1264,8 +1307,8 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const RepDesc
     if (solo && wave != 0) return;
     if (Gact > 1) {
         const uint32_t epoch = epoch0 + nbar;
-        const uint64_t* part = reinterpret_cast<const uint64_t*>(D.partials) +
-                               (int64_t)(nbar & 1) * D.G * NVAL_MAX * 2;
+        const uint64_t* part = cc.part() +
+                               (int64_t)(nbar & 1) * cc.G() * NVAL_MAX * 2;
         if (solo) {
             double out[8];
             poll_reduce<8, 1>(S, part, 0, 1, nv, Gact, 1, epoch, out);
@@ -1299,9 +1342,9 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const RepDesc
             const int ct_a = S.cType[a];
             const bool c_lo = c < a;
             const int lo = c_lo ? c : a, hi = c_lo ? a : c;
-            double dx = min_image(S.sXw[lo][0] - S.sXw[hi][0], D.Ld[0], D.halfL[0]);
-            double dy = min_image(S.sXw[lo][1] - S.sXw[hi][1], D.Ld[1], D.halfL[1]);
-            double dz = min_image(S.sXw[lo][2] - S.sXw[hi][2], D.Ld[2], D.halfL[2]);
+            double dx = min_image(S.sXw[lo][0] - S.sXw[hi][0], cc.L(0), cc.h(0));
+            double dy = min_image(S.sXw[lo][1] - S.sXw[hi][1], cc.L(1), cc.h(1));
+            double dz = min_image(S.sXw[lo][2] - S.sXw[hi][2], cc.L(2), cc.h(2));
             double r2 = dot3(dx, dy, dz, dx, dy, dz);
             double sab = c_lo ? PL.sigma + sig_a : sig_a + PL.sigma;
             double rc = 0x1.1f59ac3c7d6c0p+0 * sab;
@@ -1322,9 +1365,9 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const RepDesc
         for (int a = 0; a < nc; ++a)
             for (int b = a + 1; b < nc; ++b) {
                 if (cp->body[a] == cp->body[b]) continue;
-                double dx = min_image(S.sXw[a][0] - S.sXw[b][0], D.Ld[0], D.halfL[0]);
-                double dy = min_image(S.sXw[a][1] - S.sXw[b][1], D.Ld[1], D.halfL[1]);
-                double dz = min_image(S.sXw[a][2] - S.sXw[b][2], D.Ld[2], D.halfL[2]);
+                double dx = min_image(S.sXw[a][0] - S.sXw[b][0], cc.L(0), cc.h(0));
+                double dy = min_image(S.sXw[a][1] - S.sXw[b][1], cc.L(1), cc.h(1));
+                double dz = min_image(S.sXw[a][2] - S.sXw[b][2], cc.L(2), cc.h(2));
                 double r2 = dot3(dx, dy, dz, dx, dy, dz);
                 double sab = cp->sigma[a] + cp->sigma[b];
                 double rc = 0x1.1f59ac3c7d6c0p+0 * sab;
@@ -1341,11 +1384,8 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const RepDesc
 }
 
 template <class T, int K, int NC, int NT>
-__device__ __forceinline__ void chain_run(Work w, int item)
+__device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, const ChainConst& cc)
 {
-    const int rep = find_rep(w.prefix, w.nrep, item);
-    const int g = item - w.prefix[rep];
-    const RepDesc& D = w.desc[rep];
     if (!D.active) return;
     RepState* rs = D.rs;
     const ColloidParams* cp = D.cp;
@@ -1398,7 +1438,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
             cX[d] = rs->X[t][d];
             cV[d] = rs->V[t][d];
             cX0[d] = cX[d];
-            S.sXw[t][d] = colloid_image(cX[d], D.Ld[d]);
+            S.sXw[t][d] = colloid_image(cX[d], cc.L(d));
         }
         S.cRc2[t] = cp->rc2[t];
         S.cSig2[t] = cp->sig2[t];
@@ -1464,12 +1504,12 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     const uint32_t epoch0 = (uint32_t)(md0 + coll);
     const double dt = D.dt;
     const T dtT = (T)dt, hT = (T)D.h;
-    const T Lt[3] = {(T)D.Ld[0], (T)D.Ld[1], (T)D.Ld[2]};
+    const T Lt[3] = {(T)cc.L(0), (T)cc.L(1), (T)cc.L(2)};
     const bool colloid_wave = t < 64;
 
     // forces at the start of the interval
-    chain_compute<T, K, NT>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
-    chain_collect<T, K, NT>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, false, cF, PL);
+    chain_compute<T, K, NT>(S, cc, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
+    chain_collect<T, K, NT>(S, cc, cp, nc, Gact, Gpad, nbar, epoch0, false, cF, PL);
     // list entries: first half kick and drift of step 0
 #pragma unroll
     for (int j = 0; j < K; ++j)
@@ -1521,10 +1561,10 @@ __device__ __forceinline__ void chain_run(Work w, int item)
             }
             if (lflags) atomicOr(&S.sflags, lflags);
             if (t < nc)
-                for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(cX[d], D.Ld[d]);
+                for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(cX[d], cc.L(d));
         }
         __syncthreads();
-        chain_compute<T, K, NT>(S, D, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
+        chain_compute<T, K, NT>(S, cc, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
         // while the other workgroups' sums arrive: the list entries' second
         // half kick, catalysis, and (except after the last step) the next
         // step's first half kick and drift -- each entry's own arithmetic,
@@ -1544,15 +1584,15 @@ __device__ __forceinline__ void chain_run(Work w, int item)
                 st[j] = (uint8_t)(s | 2);
             } else if (s & 2) {
                 bool flip = true;
-                if (D.cat_prob < 1.0) {
+                if (cc.cat_prob() < 1.0) {
                     uint64_t wv[4];
-                    philox((uint64_t)md, pid[j], 0, D.seed, TAG_CAT, wv);
-                    flip = u01(wv[0]) < D.cat_prob;
+                    philox((uint64_t)md, pid[j], 0, cc.seed(), TAG_CAT, wv);
+                    flip = u01(wv[0]) < cc.cat_prob();
                 }
                 if (flip) {
                     st[j] = 1;
                     ef += 1.0;
-                    eu += species_dU_lds(S, D, nc, (double)x[j][0], (double)x[j][1], (double)x[j][2]);
+                    eu += species_dU_lds(S, cc, nc, (double)x[j][0], (double)x[j][1], (double)x[j][2]);
                 } else {
                     st[j] = 0;
                 }
@@ -1568,7 +1608,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
                 }
         }
         // the potential energy is an observable of the last force evaluation
-        chain_collect<T, K, NT>(S, D, cp, nc, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF, PL);
+        chain_collect<T, K, NT>(S, cc, cp, nc, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF, PL);
         // colloids (wave 0, in registers): second half kick, RATTLE
         // velocity stage, Verlet-list soundness check (displacement within
         // the interval)
@@ -1654,6 +1694,15 @@ __device__ __forceinline__ void chain_run(Work w, int item)
 // launch.  (The ticket is a separate instantiation because an atomic at
 // kernel entry keeps the descriptor loads of the whole kernel off the
 // scalar unit.)
+template <class T, int K, int NC, int NT>
+__device__ __forceinline__ void chain_run(Work w, int item)
+{
+    const int rep = find_rep(w.prefix, w.nrep, item);
+    const int g = item - w.prefix[rep];
+    const RepDesc& D = w.desc[rep];
+    chain_body<T, K, NC, NT>(w, g, D, chain_const(D));
+}
+
 template <class T, int K, bool TICKET, int NC, int NT>
 __global__ __launch_bounds__(NT) void k_chain(Work w)
 {
