@@ -1,6 +1,6 @@
-"""Rigid bodies of several colloids on the GPU (iterative RATTLE, a composite
-Janus particle of 13 beads and 42 bonds) against the FP64 oracle, bit for
-bit: one lane of the MD chain performs the same sweeps over the bonds, in
+"""Rigid bodies of several colloids on the GPU (iterative RATTLE: a composite
+Janus particle of 13 beads and 42 bonds, a 24-bead chain with 66 bonds)
+against the FP64 oracle, bit for bit: one lane of the MD chain performs the same sweeps over the bonds, in
 the same order and arithmetic, as the oracle."""
 import numpy as np
 import pytest
@@ -40,7 +40,33 @@ def _compare(g, o, what):
     assert go["potential"] == pytest.approx(oo["potential"], rel=1e-12, abs=1e-12)
 
 
+def _tetrahelix(n=24, L=16, rho=5, n_md=10):
+    """A rigid chain of 24 beads on a helix, held by the bonds (i, i+1),
+    (i, i+2) and (i, i+3): 66 bonds, more than the 64 lanes of a wave, in
+    layers of disjoint bonds as the workloads order them."""
+    p = W.base_params(L=(L, L, L), rho=rho, dt=0.01, n_md=n_md)
+    c = np.full(3, L / 2.0)
+    X = [c + np.array([1.6 * np.cos(1.9 * i), 1.6 * np.sin(1.9 * i), 0.4 * (i - (n - 1) / 2.0)])
+         for i in range(n)]
+    for i, x in enumerate(X):
+        cat = i < n // 2
+        W.add_colloid(p, x, 1.0, 1.0, 1.0 if cat else 0.5, catalytic=cat,
+                      ctype=W.TYPE_C if cat else W.TYPE_N)
+    bonds = [(i, i + k, float(np.linalg.norm(X[i] - X[i + k]))) for k in (1, 2, 3) for i in range(n - k)]
+    while bonds:
+        used, layer = set(), []
+        for bd in bonds:
+            if bd[0] not in used and bd[1] not in used:
+                layer.append(bd)
+                used |= {bd[0], bd[1]}
+        bonds = [bd for bd in bonds if bd not in layer]
+        p["bonds"].extend(layer)
+    p.update(rattle_tol=1e-9, rattle_maxit=2000, bulk_rate=0.02, name="tetrahelix")
+    return p
+
+
 CASES = {
+    "tetrahelix66": _tetrahelix,
     "janus": lambda: W.janus_system(L=16, rho=5, n_md=10, seed=3, bulk_rate=0.03),
     "janus_p05": lambda: W.janus_system(L=18, rho=4, n_md=8, seed=5, bulk_rate=0.0, cat_prob=0.5),
     "dimer_forced_iterative": lambda: dict(W.dimer_system(L=14, rho=5, n_md=10, seed=4, bulk_rate=0.02),
