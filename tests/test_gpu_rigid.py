@@ -40,10 +40,11 @@ def _compare(g, o, what):
     assert go["potential"] == pytest.approx(oo["potential"], rel=1e-12, abs=1e-12)
 
 
-def _tetrahelix(n=24, L=16, rho=5, n_md=10):
-    """A rigid chain of 24 beads on a helix, held by the bonds (i, i+1),
-    (i, i+2) and (i, i+3): 66 bonds, more than the 64 lanes of a wave, in
-    layers of disjoint bonds as the workloads order them."""
+def _tetrahelix(n=24, tol=1e-9, L=16, rho=5, n_md=10):
+    """A rigid chain of n beads on a helix, held by the bonds (i, i+1),
+    (i, i+2) and (i, i+3): 3n - 6 bonds (66 for 24 beads, more than the 64
+    lanes of a wave; 90 for 32, the most colloids a system holds), in layers
+    of disjoint bonds as the workloads order them."""
     p = W.base_params(L=(L, L, L), rho=rho, dt=0.01, n_md=n_md)
     c = np.full(3, L / 2.0)
     X = [c + np.array([1.6 * np.cos(1.9 * i), 1.6 * np.sin(1.9 * i), 0.4 * (i - (n - 1) / 2.0)])
@@ -61,12 +62,13 @@ def _tetrahelix(n=24, L=16, rho=5, n_md=10):
                 used |= {bd[0], bd[1]}
         bonds = [bd for bd in bonds if bd not in layer]
         p["bonds"].extend(layer)
-    p.update(rattle_tol=1e-9, rattle_maxit=2000, bulk_rate=0.02, name="tetrahelix")
+    p.update(rattle_tol=tol, rattle_maxit=2000, bulk_rate=0.02, name="tetrahelix")
     return p
 
 
 CASES = {
     "tetrahelix66": _tetrahelix,
+    "tetrahelix90_max_colloids": lambda: _tetrahelix(n=32, tol=1e-6),
     "janus": lambda: W.janus_system(L=16, rho=5, n_md=10, seed=3, bulk_rate=0.03),
     "janus_p05": lambda: W.janus_system(L=18, rho=4, n_md=8, seed=5, bulk_rate=0.0, cat_prob=0.5),
     "dimer_forced_iterative": lambda: dict(W.dimer_system(L=14, rho=5, n_md=10, seed=4, bulk_rate=0.02),
