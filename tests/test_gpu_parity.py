@@ -218,6 +218,31 @@ def test_fp64_many_colloids_with_contacts():
     _assert_obs(g.observables(), o.observables())
 
 
+def test_fp64_most_colloids_free_spheres():
+    """32 free spheres, the most colloids a system holds (one lane and one
+    bit of the pair masks each), half catalytic, eight pairs inside each
+    other's colloid-colloid cut-off."""
+    p = W.base_params(L=(22, 22, 22), rho=5, n_md=10)
+    p["bulk_rate"] = 0.03
+    rng = np.random.default_rng(77)
+    k = 0
+    for ix in range(4):
+        for iy in range(4):
+            for iz in range(2):
+                x = np.array([2.5 + 5.0 * ix, 2.5 + 5.0 * iy, 5.0 + 11.0 * iz]) + rng.uniform(-0.3, 0.3, 3)
+                if k % 4 == 1:
+                    x = prev + np.array([2.1, 0.0, 0.0])     # 2.1 < 2^(1/6) * 2
+                W.add_colloid(p, x, 1.0, 1.0, 0.5, catalytic=k % 2 == 0,
+                              ctype=W.TYPE_C if k % 2 == 0 else W.TYPE_N)
+                prev = x
+                k += 1
+    assert len(p["colloids"]) == 32
+    s0 = W.random_state(p, 113, species_B_fraction=0.3)
+    g, o = _run_both(p, s0, 16, 10, 3)
+    _assert_bitwise(g.get_state(), o.get_state(), "32 colloids")
+    _assert_obs(g.observables(), o.observables())
+
+
 def test_fp64_resume_and_determinism():
     rm = _rm()
     p = W.dimer_system(L=14, rho=6, n_md=10, seed=8, bulk_rate=0.05)
