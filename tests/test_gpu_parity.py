@@ -397,6 +397,29 @@ def test_errors_are_reported():
     assert e.value.flags & 16
 
 
+def test_colloid_displacement_flag_matches_oracle():
+    """A dimer driven across more than half the skin within one interval:
+    the GPU and the oracle raise the displacement flag alike and their
+    trajectories stay equal bit for bit."""
+    rm = _rm()
+    p = W.dimer_system(L=14, rho=5, n_md=10, seed=9, bulk_rate=0.0)
+    s0 = W.random_state(p, 71)
+    s0["V"] = np.tile(np.array([3.0, 0.0, 0.0]), (2, 1))   # 0.3 per interval > skin / 2
+    g = rm.System(p, 5)
+    g.set_state(s0)
+    o = oracle.Oracle(p, 5, init=False)
+    o.set_state(s0)
+    g.step(p["n_md"], 1)
+    o.run(p["n_md"], 1)
+    go, oo = g.observables(raise_on_flags=False), o.observables()
+    assert oo["flags"] & 1
+    assert go["flags"] == oo["flags"]
+    with pytest.raises(rm.RmpError) as e:
+        g.observables()
+    assert e.value.flags & 1
+    _assert_bitwise(g.get_state(), o.get_state(), "displacement flag")
+
+
 # ----------------------------------------------------------------- FP32 ---
 
 def test_fp32_one_interval_close_to_fp64_oracle():
