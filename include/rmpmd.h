@@ -215,6 +215,12 @@ typedef struct rmp_tuning {
                                   list entries per thread), or 0: 512 when a
                                   list needs more than one entry per thread at
                                   256 threads                                   */
+    int32_t barrier_budget_us; /* longest wait of an MD-chain workgroup for the
+                                  other workgroups' values, in microseconds
+                                  (0: the default, 250000; at most 10000000);
+                                  beyond it the workgroup gives up, raises
+                                  RMP_FLAG_BARRIER and waits no more in that
+                                  launch, so the launch always ends          */
 } rmp_tuning;
 rmp_status rmp_set_tuning(rmp_system* s, const rmp_tuning* t);
 rmp_status rmp_get_tuning(rmp_system* s, rmp_tuning* t);

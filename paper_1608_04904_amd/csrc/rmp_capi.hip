@@ -240,7 +240,7 @@ struct rmp_batch {
     bool any_analysis = false;
     bool any_iterative = false;     // some occupied slot uses the iterative RATTLE
     int64_t n_total = 0;            // solvent particles over the occupied slots
-    rmp_tuning tun{256, 1, 0, 1, 1, 0, 0};
+    rmp_tuning tun{256, 1, 0, 1, 1, 0, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
@@ -621,6 +621,11 @@ rmp_status sync_ctl(rmp_batch* b)
     return RMP_OK;
 }
 
+uint64_t barrier_budget(const rmp_batch* b)
+{
+    return b->tun.barrier_budget_us > 0 ? (uint64_t)b->tun.barrier_budget_us * 100u : BARRIER_BUDGET_TICKS;
+}
+
 Work work(const rmp_batch* b, int kind)
 {
     Work w;
@@ -629,6 +634,7 @@ Work work(const rmp_batch* b, int kind)
     w.tick = b->d_tick;
     w.nrep = b->nslots;
     w.flags = 0;
+    w.budget = barrier_budget(b);
     return w;
 }
 
@@ -1008,6 +1014,7 @@ rmp_status observe(rmp_batch* b, int slot, rmp_obs* o)
     w.prefix = b->d_prefix[PF_REP];
     w.nrep = 1;
     w.flags = 0;
+    w.budget = barrier_budget(b);
     hipLaunchKernelGGL((k_observe<T>), dim3(cnt), dim3(256), 0, s, w);
     st = last_launch("k_observe");
     if (st != RMP_OK) return st;
@@ -1477,7 +1484,9 @@ rmp_status rmp_batch_set_tuning(rmp_batch* b, const rmp_tuning* t)
     if (t->use_graph >= 0) n.use_graph = t->use_graph;
     if (t->chain_resident >= 0) n.chain_resident = t->chain_resident;
     if (t->chain_block >= 0) n.chain_block = t->chain_block;
+    if (t->barrier_budget_us >= 0) n.barrier_budget_us = t->barrier_budget_us;
     if (n.chain_block != 0 && n.chain_block != 256 && n.chain_block != 512) return RMP_EINVAL;
+    if (n.barrier_budget_us > BARRIER_BUDGET_MAX_US) return RMP_EINVAL;
     if (n.chain_k != 1 && n.chain_k != 2 && n.chain_k != 4) return RMP_EINVAL;
     if (n.stream_block != 64 && n.stream_block != 128 && n.stream_block != 256) return RMP_EINVAL;
     b->tun = n;

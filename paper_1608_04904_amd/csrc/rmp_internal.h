@@ -14,7 +14,8 @@ constexpr int SCAN_BLK = 4096;       // cells per block of the multi-block cell 
 constexpr int SCAN_DIRECT_BLOCKS = 8; // up to this many blocks, no separate block-sum pass
 constexpr int CHAIN_BLOCK = 256;     // threads per Verlet-list workgroup
 constexpr int NVAL_MAX = 3 * MAXC + 1;  // reduced values per MD step: F per colloid + U
-constexpr uint64_t BARRIER_BUDGET_TICKS = 25000000;  // 0.25 s of the 100 MHz wall clock
+constexpr uint64_t BARRIER_BUDGET_TICKS = 25000000;  // 0.25 s of the 100 MHz wall clock (default)
+constexpr int32_t BARRIER_BUDGET_MAX_US = 10000000;  // largest budget a caller may set (10 s)
 constexpr int32_t KEY_TABLE = -1;                    // cell sort rank from rank_of[]
 constexpr int32_t KEY_ROW = -2;                      // row-major: rank = cell index
 
@@ -127,6 +128,7 @@ struct Work {
     uint32_t* tick;   // [0] next ticket, [1] finished workgroups; zero between launches
     int32_t nrep;
     int32_t flags;    // WORK_CHAIN_PRIO: the MD chain raises its waves' issue priority
+    uint64_t budget;  // MD chain: longest wait for the other workgroups, 100 MHz ticks
 };
 
 }  // namespace rmp

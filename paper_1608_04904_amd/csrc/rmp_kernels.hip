@@ -990,15 +990,17 @@ struct ChainConst {
     int Gv;                    // workgroups of the replica's exchange buffers
     double catv;
     uint64_t seedv;
+    uint64_t budgetv;          // longest wait for the other workgroups (ticks)
     __device__ double L(int d) const { return Lv[d]; }
     __device__ double h(int d) const { return hv[d]; }
     __device__ uint64_t* part() const { return partv; }
     __device__ int G() const { return Gv; }
     __device__ double cat_prob() const { return catv; }
     __device__ uint64_t seed() const { return seedv; }
+    __device__ uint64_t budget() const { return budgetv; }
 };
 
-__device__ __forceinline__ ChainConst chain_const(const RepDesc& D)
+__device__ __forceinline__ ChainConst chain_const(const RepDesc& D, uint64_t budget)
 {
     ChainConst c;
     for (int d = 0; d < 3; ++d) {
@@ -1009,6 +1011,7 @@ __device__ __forceinline__ ChainConst chain_const(const RepDesc& D)
     c.Gv = __builtin_amdgcn_readfirstlane(D.G);
     c.catv = uniform_d(D.cat_prob);
     c.seedv = uniform_u64(D.seed);
+    c.budgetv = uniform_u64(budget);
     return c;
 }
 
@@ -1217,7 +1220,7 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainCo
 // is still computing must not be starved by polling traffic.
 template <int VB, int QM, class Ctx>
 __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0, int vs, int nv, int Gact,
-                                            int Q, uint32_t epoch, double (&out)[VB])
+                                            int Q, uint32_t epoch, uint64_t budget, double (&out)[VB])
 {
     const int lane = threadIdx.x & 63;
     double b4[VB][QM];
@@ -1261,7 +1264,7 @@ __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0
         if (__ballot(!ok) == 0) break;
         if (__hip_atomic_load(&S.sflags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & RMP_FLAG_BARRIER)
             break;
-        if (wall_clock64() - t_start > BARRIER_BUDGET_TICKS) {
+        if (wall_clock64() - t_start > budget) {
             if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
             break;
         }
@@ -1311,7 +1314,7 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const ChainCo
                                (int64_t)(nbar & 1) * cc.G() * NVAL_MAX * 2;
         if (solo) {
             double out[8];
-            poll_reduce<8, 1>(S, part, 0, 1, nv, Gact, 1, epoch, out);
+            poll_reduce<8, 1>(S, part, 0, 1, nv, Gact, 1, epoch, cc.budget(), out);
             if (lane == 0)
 #pragma unroll
                 for (int v = 0; v < 8; ++v)
@@ -1320,7 +1323,7 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const ChainCo
             constexpr int VB = 4;
             for (int v0 = wave; v0 < nv; v0 += NW * VB) {
                 double out[VB];
-                poll_reduce<VB, 4>(S, part, v0, NW, nv, Gact, Q, epoch, out);
+                poll_reduce<VB, 4>(S, part, v0, NW, nv, Gact, Q, epoch, cc.budget(), out);
                 if (lane == 0)
 #pragma unroll
                     for (int vb = 0; vb < VB; ++vb)
@@ -1700,7 +1703,7 @@ __device__ __forceinline__ void chain_run(Work w, int item)
     const int rep = find_rep(w.prefix, w.nrep, item);
     const int g = item - w.prefix[rep];
     const RepDesc& D = w.desc[rep];
-    chain_body<T, K, NC, NT>(w, g, D, chain_const(D));
+    chain_body<T, K, NC, NT>(w, g, D, chain_const(D, w.budget));
 }
 
 template <class T, int K, bool TICKET, int NC, int NT>

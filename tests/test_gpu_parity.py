@@ -397,6 +397,44 @@ def test_errors_are_reported():
     assert e.value.flags & 16
 
 
+def test_chain_wait_budget_exceeded_is_reported():
+    """A chain workgroup that waits longer than its budget for the other
+    workgroups' values gives up, raises RMP_FLAG_BARRIER and waits no more,
+    so the launch ends.  Forced from the host with a budget of 1 us on a
+    list of some thirty workgroups: the interval is then flagged, or (had
+    every wait ended in time) equal to the oracle's.  A new system on the
+    same device, with the default budget, then matches the oracle bit for
+    bit."""
+    rm = _rm()
+    p = W.dimer_system(L=32, rho=10, n_md=10, seed=21, bulk_rate=0.01)
+    s0 = W.random_state(p, 81)
+    o = oracle.Oracle(p, 7, init=False)
+    o.set_state(s0)
+    o.run(p["n_md"], 2)
+    g = rm.System(p, 7)
+    with pytest.raises(rm.RmpError):
+        g.set_tuning(barrier_budget_us=10_000_001)
+    g.set_tuning(barrier_budget_us=1, use_graph=0)
+    assert g.get_tuning()["barrier_budget_us"] == 1
+    g.set_state(s0)
+    print(f"[parity] budget 1 us: N={p['n_solvent']} n_md={p['n_md']}", flush=True)
+    g.step(p["n_md"], 2)
+    flags = g.observables(raise_on_flags=False)["flags"]
+    print(f"[parity] budget 1 us: flags {flags}", flush=True)
+    if flags & 32:
+        with pytest.raises(rm.RmpError) as e:
+            g.observables()
+        assert e.value.flags & 32
+    else:
+        _assert_bitwise(g.get_state(), o.get_state(), "budget 1 us, every wait in time")
+    g.close()
+    h = rm.System(p, 7)
+    h.set_state(s0)
+    h.step(p["n_md"], 2)
+    assert h.observables()["flags"] == 0
+    _assert_bitwise(h.get_state(), o.get_state(), "default budget")
+
+
 def test_colloid_displacement_flag_matches_oracle():
     """A dimer driven across more than half the skin within one interval:
     the GPU and the oracle raise the displacement flag alike and their
