@@ -52,7 +52,8 @@ typedef enum rmp_status {
 /* device flag bits (rmp_observables.flags) */
 #define RMP_FLAG_DISPLACEMENT  1u  /* colloid moved >= skin/2 in one interval     */
 #define RMP_FLAG_RATTLE        2u  /* RATTLE quadratic had no real root           */
-#define RMP_FLAG_NONFINITE     4u  /* non-finite colloid force                    */
+#define RMP_FLAG_NONFINITE     4u  /* non-finite colloid force, or non-finite
+                                      centre-of-mass velocity of a solvent cell */
 #define RMP_FLAG_INIT          8u  /* init rejection sampling hit its cap         */
 #define RMP_FLAG_LIST_OVERFLOW 16u /* Verlet list longer than its capacity        */
 #define RMP_FLAG_BARRIER       32u /* inter-workgroup barrier timed out           */
@@ -190,9 +191,21 @@ rmp_status rmp_step(rmp_system* s, int32_t n_md, int32_t n_collide);
 rmp_status rmp_observables(rmp_system* s, rmp_obs* out);
 
 /* Copy the state to / from caller-owned host buffers (synchronous).  After
- * set_state the next interval rebuilds the Verlet list and forces. */
+ * set_state the next interval rebuilds the Verlet list and forces.
+ * set_state first applies rmp_check_state and uploads nothing on
+ * RMP_EINVAL. */
 rmp_status rmp_get_state(rmp_system* s, rmp_host_state* dst);
 rmp_status rmp_set_state(rmp_system* s, const rmp_host_state* src);
+
+/* Pure host check of a state for parameters p (no device needed): RMP_OK, or
+ * RMP_EINVAL when a solvent position lies outside [0, L), a velocity is not
+ * finite (for precision 32 also after rounding to float), the ids are not a
+ * permutation of 0 .. n_solvent-1, a state byte has bits other than the
+ * species (bit 0) and catalysis flag (bit 1), a colloid position or velocity
+ * is not finite, a solvent particle lies within sigma/2 of a colloid centre
+ * (minimum image; the WCA potential there exceeds 1.6e4 eps, which no
+ * thermal state reaches), or a required pointer is NULL. */
+rmp_status rmp_check_state(const rmp_params* p, const rmp_host_state* src);
 
 /* Release the handle; the workspace is not freed. */
 rmp_status rmp_destroy(rmp_system* s);

@@ -9,6 +9,7 @@ this module only marshals numpy arrays through ctypes.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -68,50 +69,93 @@ class Obs(C.Structure):
 _lib = None
 
 
+def _load(path: str):
+    L = C.CDLL(path)
+    P, D, I64, I32, U64 = C.c_void_p, C.c_double, C.c_int64, C.c_int32, C.c_uint64
+    L.orc_create.restype = P
+    L.orc_create.argtypes = [C.POINTER(Params), U64]
+    L.orc_destroy.argtypes = [P]
+    L.orc_init.argtypes = [P]
+    L.orc_set_state.argtypes = [P, P, P, P, P, P, P, I64, I64]
+    L.orc_get_state.argtypes = [P, P, P, P, P, P, P, P, P, P]
+    L.orc_run.argtypes = [P, I32, I32]
+    L.orc_interval.argtypes = [P, I32, I32]
+    L.orc_collide.argtypes = [P, I32]
+    L.orc_observables.argtypes = [P, C.POINTER(Obs)]
+    L.orc_candidates.restype = I64
+    L.orc_candidates.argtypes = [P, P, I64]
+    L.orc_forces.argtypes = [P, P]
+    L.orc_build_list.argtypes = [P, I32]
+    L.orc_forces_allpairs.argtypes = [P, P, P]
+    L.orc_cell_keys.argtypes = [P, P, P]
+    L.orc_shift.argtypes = [P, I64, P]
+    L.orc_last_cells.restype = I64
+    L.orc_last_cells.argtypes = [P, P, I64]
+    L.orc_cell_ranks.restype = I64
+    L.orc_cell_ranks.argtypes = [P, P, I64]
+    L.orc_hilbert.restype = U64
+    L.orc_hilbert.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
+    L.orc_philox.argtypes = [P, P, P]
+    L.orc_wca.argtypes = [D, D, D, C.POINTER(D), C.POINTER(D)]
+    L.orc_tree_sum.restype = D
+    L.orc_tree_sum.argtypes = [P, I64]
+    L.orc_marsaglia.argtypes = [U64, I64, I64, P]
+    L.orc_rotate.argtypes = [P, D, D, P, P]
+    L.orc_ptable.argtypes = [D, D, P]
+    L.orc_dimer_sample.restype = C.c_int
+    L.orc_dimer_sample.argtypes = [P, I32, P]
+    L.orc_cyl_hist.restype = C.c_int
+    L.orc_cyl_hist.argtypes = [P, I32, I32, I32, D, D, P]
+    L.orc_msd.argtypes = [P, I64, I32, P]
+    return L
+
+
 def lib():
+    """The oracle library: the in-tree build, or the build named by the
+    environment variable RMP_ORACLE_LIB (the sanitizer run of the pins)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
-            build()
-        L = C.CDLL(_SO)
-        P, D, I64, I32, U64 = C.c_void_p, C.c_double, C.c_int64, C.c_int32, C.c_uint64
-        L.orc_create.restype = P
-        L.orc_create.argtypes = [C.POINTER(Params), U64]
-        L.orc_destroy.argtypes = [P]
-        L.orc_init.argtypes = [P]
-        L.orc_set_state.argtypes = [P, P, P, P, P, P, P, I64, I64]
-        L.orc_get_state.argtypes = [P, P, P, P, P, P, P, P, P, P]
-        L.orc_run.argtypes = [P, I32, I32]
-        L.orc_interval.argtypes = [P, I32, I32]
-        L.orc_collide.argtypes = [P, I32]
-        L.orc_observables.argtypes = [P, C.POINTER(Obs)]
-        L.orc_candidates.restype = I64
-        L.orc_candidates.argtypes = [P, P, I64]
-        L.orc_forces.argtypes = [P, P]
-        L.orc_build_list.argtypes = [P, I32]
-        L.orc_forces_allpairs.argtypes = [P, P, P]
-        L.orc_cell_keys.argtypes = [P, P, P]
-        L.orc_shift.argtypes = [P, I64, P]
-        L.orc_last_cells.restype = I64
-        L.orc_last_cells.argtypes = [P, P, I64]
-        L.orc_cell_ranks.restype = I64
-        L.orc_cell_ranks.argtypes = [P, P, I64]
-        L.orc_hilbert.restype = U64
-        L.orc_hilbert.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
-        L.orc_philox.argtypes = [P, P, P]
-        L.orc_wca.argtypes = [D, D, D, C.POINTER(D), C.POINTER(D)]
-        L.orc_tree_sum.restype = D
-        L.orc_tree_sum.argtypes = [P, I64]
-        L.orc_marsaglia.argtypes = [U64, I64, I64, P]
-        L.orc_rotate.argtypes = [P, D, D, P, P]
-        L.orc_ptable.argtypes = [D, D, P]
-        L.orc_dimer_sample.restype = C.c_int
-        L.orc_dimer_sample.argtypes = [P, I32, P]
-        L.orc_cyl_hist.restype = C.c_int
-        L.orc_cyl_hist.argtypes = [P, I32, I32, I32, D, D, P]
-        L.orc_msd.argtypes = [P, I64, I32, P]
-        _lib = L
+        alt = os.environ.get("RMP_ORACLE_LIB")
+        if alt:
+            _lib = _load(alt)
+        else:
+            if not os.path.exists(_SO):
+                build()
+            _lib = _load(_SO)
     return _lib
+
+
+@contextlib.contextmanager
+def using(path: str):
+    """Run the oracle from another build of its source while the block lasts
+    (the mutation tests load copies with planted mistakes).  Oracle objects
+    keep the build that created them."""
+    global _lib
+    saved = lib()
+    _lib = _load(path)
+    try:
+        yield _lib
+    finally:
+        _lib = saved
+
+
+def compile_variant(src_text: str, out_path: str, extra_flags=()) -> str:
+    """Compile C source text of the oracle (a copy of rmp_oracle.c, possibly
+    altered) into a shared library with the oracle's flags."""
+    d = os.path.dirname(os.path.abspath(out_path))
+    c_path = os.path.join(d, os.path.basename(out_path) + ".c")
+    with open(c_path, "w") as f:
+        f.write(src_text)
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-Wno-unused-function", *extra_flags,
+           "-I", _HERE, c_path, "-o", out_path, "-lm"]
+    subprocess.check_call(cmd)
+    return out_path
+
+
+def source() -> str:
+    with open(os.path.join(_HERE, "rmp_oracle.c")) as f:
+        return f.read()
 
 
 def _ptr(a: np.ndarray):
@@ -221,18 +265,19 @@ class Oracle:
         self.params = params
         self._p = make_params(params)
         self.seed = int(seed)
-        self.h = lib().orc_create(C.byref(self._p), self.seed)
+        self._L = lib()            # the build that owns the handle
+        self.h = self._L.orc_create(C.byref(self._p), self.seed)
         if not self.h:
             raise ValueError("oracle rejected the parameters")
         self.n = int(params["n_solvent"])
         self.nc = len(params["colloids"])
         if init:
-            lib().orc_init(self.h)
+            self._L.orc_init(self.h)
 
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
-            lib().orc_destroy(h)
+            self._L.orc_destroy(h)
             self.h = None
 
     def set_state(self, s: dict):
@@ -244,7 +289,7 @@ class Oracle:
         V = np.ascontiguousarray(s["V"], dtype=np.float64).reshape(self.nc, 3) if self.nc else np.zeros((0, 3))
         X = np.ascontiguousarray(X)
         V = np.ascontiguousarray(V)
-        lib().orc_set_state(self.h, _ptr(x), _ptr(v), _ptr(ids), _ptr(st), _ptr(X), _ptr(V),
+        self._L.orc_set_state(self.h, _ptr(x), _ptr(v), _ptr(ids), _ptr(st), _ptr(X), _ptr(V),
                             int(s.get("md_step", 0)), int(s.get("coll_step", 0)))
 
     def get_state(self) -> dict:
@@ -252,87 +297,87 @@ class Oracle:
         ids = np.zeros(self.n, dtype=np.uint32); st = np.zeros(self.n, dtype=np.uint8)
         X = np.zeros((self.nc, 3)); V = np.zeros((self.nc, 3)); F = np.zeros((self.nc, 3))
         md, co = C.c_int64(), C.c_int64()
-        lib().orc_get_state(self.h, _ptr(x), _ptr(v), _ptr(ids), _ptr(st), _ptr(X), _ptr(V),
+        self._L.orc_get_state(self.h, _ptr(x), _ptr(v), _ptr(ids), _ptr(st), _ptr(X), _ptr(V),
                             _ptr(F), C.cast(C.pointer(md), C.c_void_p),
                             C.cast(C.pointer(co), C.c_void_p))
         return dict(x=x, v=v, id=ids, state=st, X=X, V=V, F=F,
                     md_step=md.value, coll_step=co.value)
 
     def run(self, n_md: int, n_collide: int):
-        if lib().orc_run(self.h, int(n_md), int(n_collide)) != 0:
+        if self._L.orc_run(self.h, int(n_md), int(n_collide)) != 0:
             raise ValueError("bad arguments")
 
     def interval(self, n_md: int, collide: bool = True):
-        if lib().orc_interval(self.h, int(n_md), int(bool(collide))) != 0:
+        if self._L.orc_interval(self.h, int(n_md), int(bool(collide))) != 0:
             raise ValueError("bad arguments")
 
     def collide(self, n_md: int):
-        if lib().orc_collide(self.h, int(n_md)) != 0:
+        if self._L.orc_collide(self.h, int(n_md)) != 0:
             raise ValueError("bad arguments")
 
     def build_list(self, n_md: int):
-        lib().orc_build_list(self.h, int(n_md))
+        self._L.orc_build_list(self.h, int(n_md))
 
     def observables(self) -> dict:
         o = Obs()
-        lib().orc_observables(self.h, C.byref(o))
+        self._L.orc_observables(self.h, C.byref(o))
         d = {k: getattr(o, k) for k, _ in Obs._fields_ if k != "pad"}
         d["momentum"] = np.array(list(o.momentum))
         return d
 
     def candidates(self) -> np.ndarray:
-        n = lib().orc_candidates(self.h, None, 0)
+        n = self._L.orc_candidates(self.h, None, 0)
         idx = np.zeros(max(n, 1), dtype=np.int64)
-        lib().orc_candidates(self.h, _ptr(idx), n)
+        self._L.orc_candidates(self.h, _ptr(idx), n)
         return idx[:n]
 
     def forces(self) -> np.ndarray:
         f = np.zeros((3, self.n))
-        lib().orc_forces(self.h, _ptr(f))
+        self._L.orc_forces(self.h, _ptr(f))
         return f
 
     def forces_allpairs(self):
         f = np.zeros((3, self.n)); F = np.zeros((max(self.nc, 1), 3))
-        lib().orc_forces_allpairs(self.h, _ptr(f), _ptr(F))
+        self._L.orc_forces_allpairs(self.h, _ptr(f), _ptr(F))
         return f, F[: self.nc]
 
     def shift(self, coll_step: int) -> np.ndarray:
         s = np.zeros(3)
-        lib().orc_shift(self.h, int(coll_step), _ptr(s))
+        self._L.orc_shift(self.h, int(coll_step), _ptr(s))
         return s
 
     def cell_keys(self, shift) -> np.ndarray:
         sh = np.ascontiguousarray(np.asarray(shift, dtype=np.float64))
         k = np.zeros(self.n, dtype=np.uint32)
-        lib().orc_cell_keys(self.h, _ptr(sh), _ptr(k))
+        self._L.orc_cell_keys(self.h, _ptr(sh), _ptr(k))
         return k
 
     def cell_ranks(self) -> np.ndarray:
         """Sort rank of every cell (linear cell index -> position in the
         Hilbert cell order)."""
-        m = lib().orc_cell_ranks(self.h, None, 0)
+        m = self._L.orc_cell_ranks(self.h, None, 0)
         a = np.zeros(m, dtype=np.uint32)
-        lib().orc_cell_ranks(self.h, _ptr(a), m)
+        self._L.orc_cell_ranks(self.h, _ptr(a), m)
         return a
 
     def last_cells(self) -> np.ndarray:
-        m = lib().orc_last_cells(self.h, None, 0)
+        m = self._L.orc_last_cells(self.h, None, 0)
         a = np.zeros(m, dtype=np.uint32)
-        lib().orc_last_cells(self.h, _ptr(a), m)
+        self._L.orc_last_cells(self.h, _ptr(a), m)
         return a
 
     def dimer_sample(self, k: int) -> np.ndarray:
         """R_com[3], V_com[3], unit axis u[3] (bond_a -> bond_b) and V_com.u
         of bond k."""
         rec = np.zeros(SERIES_FIELDS)
-        if lib().orc_dimer_sample(self.h, int(k), _ptr(rec)) != 0:
+        if self._L.orc_dimer_sample(self.h, int(k), _ptr(rec)) != 0:
             raise ValueError("no such bond")
         return rec
 
     def cyl_hist(self, k: int, nz: int, nr: int, zmax: float, rmax: float) -> np.ndarray:
         """Counts [species A/B][nz][nr] of the current state around bond k."""
         h = np.zeros((2, nz, nr), dtype=np.uint64)
-        if lib().orc_cyl_hist(self.h, int(k), int(nz), int(nr), float(zmax), float(rmax), _ptr(h)) != 0:
+        if self._L.orc_cyl_hist(self.h, int(k), int(nz), int(nr), float(zmax), float(rmax), _ptr(h)) != 0:
             raise ValueError("bad histogram arguments")
         return h
 

@@ -981,7 +981,8 @@ static void collide(orc_system* s, int32_t n_md)
     uint8_t* virt = (uint8_t*)xalloc(ncell ? ncell : 1);
     /* cells in sort order: rank r holds the particles of cell c = cell_of[r];
      * per-cell random streams are keyed by the cell c */
-    #pragma omp parallel for schedule(dynamic, 256)
+    uint32_t nonfinite = 0;
+    #pragma omp parallel for schedule(dynamic, 256) reduction(|:nonfinite)
     for (int64_t r = 0; r < ncell; ++r) {
         const int64_t c = s->cell_of[r];
         int64_t b = s->start[r], e = s->start[r + 1];
@@ -1015,6 +1016,8 @@ static void collide(orc_system* s, int32_t n_md)
                 }
                 tterm[c] = (s->p.mass * tsum) / (double)(nn - 1);
             }
+            /* a non-finite cell velocity would spread through the cell */
+            if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) nonfinite |= ORC_F_NONFINITE;
             if (s->p.rule == 0) {
                 double nv[3];
                 orc_marsaglia(s->seed, s->coll_step, c, nv);
@@ -1071,6 +1074,7 @@ static void collide(orc_system* s, int32_t n_md)
             }
         }
     }
+    s->flags |= nonfinite;
     double T = 0.0;
     int64_t ncT = 0;
     for (int64_t c = 0; c < ncell; ++c) {

@@ -82,7 +82,7 @@ typedef struct orc_obs {
 /* error / warning flags, latched */
 #define ORC_F_DISPLACEMENT 1u   /* a colloid moved >= skin/2 within one interval */
 #define ORC_F_RATTLE       2u   /* RATTLE quadratic had no real root             */
-#define ORC_F_NONFINITE    4u   /* non-finite colloid force                      */
+#define ORC_F_NONFINITE    4u   /* non-finite colloid force or cell velocity     */
 #define ORC_F_INIT         8u   /* init rejection sampling hit its cap           */
 
 typedef struct orc_system orc_system;

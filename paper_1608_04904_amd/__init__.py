@@ -111,6 +111,17 @@ def _fill(buf: _StateBuffers, s: dict):
         buf.V[: buf.nc] = np.asarray(s["V"], dtype=np.float64).reshape(buf.nc, 3)
 
 
+def check_state(params: dict, s: dict) -> int:
+    """rmp_check_state: the library's host-side check of a state for these
+    parameters (no device needed); returns the status (0 = acceptable)."""
+    n, nc = int(params["n_solvent"]), len(params["colloids"])
+    b = _StateBuffers(n, nc)
+    _fill(b, s)
+    h = b.host_state(s.get("md_step", 0), s.get("coll_step", 0))
+    q = _capi.make_params(params)
+    return int(_capi.lib().rmp_check_state(C.byref(q), C.byref(h)))
+
+
 class System:
     """One simulated system (``rmp_init_system`` ... ``rmp_destroy``)."""
 

@@ -98,6 +98,7 @@ SIGNATURES = {
     "rmp_observables": (I32, [P, C.POINTER(Obs)]),
     "rmp_get_state": (I32, [P, C.POINTER(HostState)]),
     "rmp_set_state": (I32, [P, C.POINTER(HostState)]),
+    "rmp_check_state": (I32, [C.POINTER(Params), C.POINTER(HostState)]),
     "rmp_destroy": (I32, [P]),
     "rmp_set_tuning": (I32, [P, C.POINTER(Tuning)]),
     "rmp_get_tuning": (I32, [P, C.POINTER(Tuning)]),

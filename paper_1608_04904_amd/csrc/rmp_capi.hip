@@ -1093,13 +1093,68 @@ rmp_status get_state_t(rmp_batch* b, int slot, rmp_host_state* dst)
     return RMP_OK;
 }
 
+// A state handed in by the caller (pure host check, before any upload):
+// solvent positions inside the box, velocities finite (also once rounded to
+// the storage precision), ids a permutation of 0 .. N-1, state bytes with
+// only the species and catalysis bits, colloid positions and velocities
+// finite, and no solvent particle deep inside a colloid core (r < sigma/2,
+// where the WCA potential exceeds 1.6e4 eps: unreachable by a thermal
+// state, so the input is corrupt).
+rmp_status check_state(const rmp_params* p, const rmp_host_state* src)
+{
+    if (!p || !src) return RMP_EINVAL;
+    if (validate(p) != RMP_OK) return RMP_EINVAL;
+    const int64_t n = p->n_solvent;
+    if (n > 0 && (!src->x || !src->v || !src->id || !src->state)) return RMP_EINVAL;
+    if (p->n_colloids > 0 && (!src->X || !src->V)) return RMP_EINVAL;
+    if (src->md_step < 0 || src->coll_step < 0) return RMP_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        for (int64_t i = 0; i < n; ++i) {
+            const double xv = src->x[d * n + i];
+            if (!(xv >= 0.0 && xv < (double)p->L[d])) return RMP_EINVAL;
+            const double vv = src->v[d * n + i];
+            if (!std::isfinite(vv)) return RMP_EINVAL;
+            if (p->precision == 32 && !std::isfinite((float)vv)) return RMP_EINVAL;
+        }
+    std::vector<uint8_t> seen((size_t)n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t id = src->id[i];
+        if ((int64_t)id >= n || seen[id]) return RMP_EINVAL;
+        seen[id] = 1;
+        if (src->state[i] > 3) return RMP_EINVAL;
+    }
+    double Xw[RMP_MAX_COLLOIDS][3];
+    for (int c = 0; c < p->n_colloids; ++c)
+        for (int d = 0; d < 3; ++d) {
+            if (!std::isfinite(src->X[3 * c + d]) || !std::isfinite(src->V[3 * c + d])) return RMP_EINVAL;
+            const double L = (double)p->L[d];
+            double w = std::fmod(src->X[3 * c + d], L);
+            if (w < 0.0) w += L;
+            Xw[c][d] = w;
+        }
+    for (int c = 0; c < p->n_colloids; ++c) {
+        const double core2 = 0.25 * p->sigma[c] * p->sigma[c];
+        for (int64_t i = 0; i < n; ++i) {
+            double r2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double L = (double)p->L[d];
+                double dd = src->x[d * n + i] - Xw[c][d];
+                if (dd > 0.5 * L) dd -= L;
+                else if (dd < -0.5 * L) dd += L;
+                r2 += dd * dd;
+            }
+            if (r2 < core2) return RMP_EINVAL;
+        }
+    }
+    return RMP_OK;
+}
+
 template <class T>
 rmp_status set_state_t(rmp_batch* b, int slot, const rmp_host_state* src)
 {
     Replica& R = b->reps[slot];
-    if (!src->x || !src->v || !src->id || !src->state) return RMP_EINVAL;
-    if (R.p.n_colloids > 0 && (!src->X || !src->V)) return RMP_EINVAL;
-    if (src->md_step < 0 || src->coll_step < 0) return RMP_EINVAL;
+    rmp_status cst = check_state(&R.p, src);
+    if (cst != RMP_OK) return cst;
     hipStream_t s = b->stream;
     HIPCHK(hipStreamSynchronize(s));
     RepState rs;
@@ -1109,9 +1164,7 @@ rmp_status set_state_t(rmp_batch* b, int slot, const rmp_host_state* src)
     std::vector<T> buf((size_t)3 * n);
     for (int d = 0; d < 3; ++d)
         for (int64_t i = 0; i < n; ++i) {
-            double xv = src->x[d * n + i];
-            if (!(xv >= 0.0 && xv < (double)R.p.L[d])) return RMP_EINVAL;
-            T xt = (T)xv;
+            T xt = (T)src->x[d * n + i];
             if ((double)xt >= (double)R.p.L[d]) xt = (T)0;
             buf[d * n + i] = xt;
         }
@@ -1346,6 +1399,11 @@ rmp_status rmp_get_state(rmp_system* s, rmp_host_state* dst)
 {
     if (!s || !dst) return RMP_EINVAL;
     return s->b->precision == 32 ? get_state_t<float>(s->b, 0, dst) : get_state_t<double>(s->b, 0, dst);
+}
+
+rmp_status rmp_check_state(const rmp_params* p, const rmp_host_state* src)
+{
+    return check_state(p, src);
 }
 
 rmp_status rmp_set_state(rmp_system* s, const rmp_host_state* src)

@@ -1954,6 +1954,7 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
                 }
                 t_sum += (D.mass * tsum) / (double)(nn - 1);
                 t_cells += 1.0;
+                if (!(isfinite(u0) && isfinite(u1) && isfinite(u2))) atomicOr(&rs->flags, RMP_FLAG_NONFINITE);
                 s_u[0][0] = u0; s_u[0][1] = u1; s_u[0][2] = u2;
                 if constexpr (RULE == 0) {
                     double nax[3];
@@ -2102,6 +2103,9 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
                     t_sum += (D.mass * tsum) / (double)(nn - 1);
                     t_cells += 1.0;
                 }
+                // a non-finite centre-of-mass velocity would spread through
+                // its cell: latched for the caller
+                if (!(isfinite(u0) && isfinite(u1) && isfinite(u2))) atomicOr(&rs->flags, RMP_FLAG_NONFINITE);
                 s_u[lc][0] = u0; s_u[lc][1] = u1; s_u[lc][2] = u2;
                 if constexpr (RULE == 0) {
                     double nax[3];

@@ -12,12 +12,21 @@ as capacity frees up, not at batch boundaries).
 
 Replicas never interact and every kernel is deterministic, so a job's final
 state does not depend on what else shares the batch.
+
+A job whose interval lost an inter-workgroup exchange of the MD chain (the
+RMP_FLAG_BARRIER device flag: a bounded wait for other workgroups expired,
+so that interval's results are not to be trusted) is restarted once from its
+own initial state, which reproduces the run it would have had; only a second
+such failure is reported as the job's error.
 """
 from __future__ import annotations
 
 import time
 from collections import deque
 from dataclasses import dataclass, field
+
+FLAG_BARRIER = 32          # rmpmd.h RMP_FLAG_BARRIER
+MAX_RESTARTS = 1
 
 
 @dataclass
@@ -33,6 +42,7 @@ class JobResult:
     observables: dict | None = None
     state: dict | None = None
     error: str | None = None
+    restarts: int = 0
 
     @property
     def latency(self) -> float:
@@ -128,7 +138,8 @@ class Server:
             return False
         res = JobResult(job_id=jid, precision=prec, n_solvent=int(p["n_solvent"]),
                         n_md=int(p["n_md"]), n_collide=int(job["n_collide"]),
-                        arrival=float(job["arrival"]) if self._realtime else 0.0)
+                        arrival=float(job["arrival"]) if self._realtime else 0.0,
+                        restarts=self._restarts.get(jid, 0))
         pool.admit(slot, p, int(job["seed"]), res.n_md)
         res.admitted = now
         self.active[prec][slot] = _Active(res=res, slot=slot, need=need)
@@ -142,6 +153,7 @@ class Server:
         otherwise every job is available at once (arrival = 0).  Returns the
         JobResults in completion order."""
         self._realtime = realtime
+        self._restarts = {}
         order = sorted(range(len(jobs)), key=lambda j: jobs[j]["arrival"])
         pending = deque(order)
         queue: list[int] = []
@@ -177,17 +189,26 @@ class Server:
                 for slot in finished:
                     a = self.active[p].pop(slot)
                     pool = self.pools[p]
+                    restart = False
                     try:
                         a.res.observables = pool.observables(slot)
-                        if a.res.observables.get("flags", 0):
-                            a.res.error = f"device flags {a.res.observables['flags']:#x}"
-                        if self.keep_state:
+                        flags = a.res.observables.get("flags", 0)
+                        if flags & FLAG_BARRIER and a.res.restarts < MAX_RESTARTS:
+                            restart = True
+                        elif flags:
+                            a.res.error = f"device flags {flags:#x}"
+                        if self.keep_state and not restart:
                             a.res.state = pool.state(slot)
                     except Exception as e:        # reported per job; others continue
                         a.res.error = str(e)
-                    a.res.finished = self.clock() - t0
                     pool.retire(slot)
                     self.used -= a.need
+                    if restart:
+                        # rerun from the job's initial state, ahead of the queue
+                        self._restarts[a.res.job_id] = a.res.restarts + 1
+                        queue.insert(0, a.res.job_id)
+                        continue
+                    a.res.finished = self.clock() - t0
                     done.append(a.res)
         return done
 

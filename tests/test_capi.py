@@ -150,3 +150,79 @@ def test_product_package_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "liboracle" not in text, f
                 assert "rmp_oracle" not in text, f
+
+
+# --------------------------------------------------------------------------
+# rmp_check_state: the host-side check every rmp_set_state applies before
+# uploading (a pure host function, so it runs here without a GPU).
+# --------------------------------------------------------------------------
+def _state_case():
+    import workloads as W
+    p = W.dimer_system(L=16, rho=3, n_md=10, seed=3)
+    return p, W.random_state(p, 5, species_B_fraction=0.3, flag_fraction=0.05)
+
+
+def _status(p, s):
+    import paper_1608_04904_amd as rm
+    return rm.check_state(p, s)
+
+
+def test_check_state_accepts_a_valid_state():
+    p, s = _state_case()
+    assert _status(p, s) == 0
+    # FP32 system: a velocity that still rounds to a finite float is fine
+    s["v"][1, 7] = 3.0e38
+    assert _status(dict(p, precision=32), s) == 0
+
+
+@pytest.mark.parametrize("what", [
+    "x_above_L", "x_negative", "x_nan", "v_nan", "v_inf", "v_float_overflow",
+    "id_duplicate", "id_out_of_range", "state_bits", "X_nan", "V_inf", "particle_in_core",
+])
+def test_check_state_rejects(what):
+    import numpy as np
+    from paper_1608_04904_amd import _capi
+    p, s = _state_case()
+    prec = 64
+    if what == "x_above_L":
+        s["x"][0, 3] = 16.0
+    elif what == "x_negative":
+        s["x"][2, 3] = -1e-12
+    elif what == "x_nan":
+        s["x"][1, 3] = np.nan
+    elif what == "v_nan":
+        s["v"][0, 10] = np.nan
+    elif what == "v_inf":
+        s["v"][2, 11] = -np.inf
+    elif what == "v_float_overflow":
+        s["v"][1, 7] = 1.0e39              # finite in FP64, infinite as a float
+        prec = 32
+    elif what == "id_duplicate":
+        s["id"][5] = s["id"][6]
+    elif what == "id_out_of_range":
+        s["id"][5] = p["n_solvent"]
+    elif what == "state_bits":
+        s["state"][9] = 4
+    elif what == "X_nan":
+        s["X"][1, 0] = np.nan
+    elif what == "V_inf":
+        s["V"][0, 2] = np.inf
+    elif what == "particle_in_core":
+        X0 = np.mod(s["X"][0], 16.0)
+        s["x"][:, 4] = X0 + np.array([0.3, -0.2, 0.1]) * p["colloids"][0]["sigma"] / 2
+    assert _status(dict(p, precision=prec), s) == _capi.EINVAL
+
+
+def test_check_state_core_boundary():
+    """Inside sigma/2 of a colloid centre is rejected, just outside accepted
+    (minimum image across the periodic boundary)."""
+    import numpy as np
+    from paper_1608_04904_amd import _capi
+    p, s = _state_case()
+    sig = p["colloids"][0]["sigma"]
+    X0 = np.mod(s["X"][0], 16.0)
+    ax = np.array([1.0, 0.0, 0.0])
+    s["x"][:, 4] = np.mod(X0 + 0.501 * sig * ax, 16.0)
+    assert _status(p, s) == 0
+    s["x"][:, 4] = np.mod(X0 + 0.499 * sig * ax, 16.0)
+    assert _status(p, s) == _capi.EINVAL

@@ -85,6 +85,9 @@ PLATES = {
     "plates_many_bounces": (lambda: _flow((6, 6, 5), 5, (0.1, 0.0, 0.0), 1, n_md=4, dt=0.1), None),
     "plates_bulk_reaction": (lambda: dict(_flow((8, 8, 8), 8, (0.03, 0.0, 0.0), 1), bulk_rate=0.05),
                              dict(use_graph=1)),
+    # virtual particles at kT/m = 0.25: their summed momentum scales with
+    # sqrt((n0 - n) kT / m)
+    "plates_m2_kT05": (lambda: _flow((8, 6, 10), 6, (0.02, 0.0, 0.0), 1, kT=0.5, mass=2.0), None),
 }
 
 

@@ -87,6 +87,11 @@ CASES = {
     "dimer_hilbert_cube": lambda: dict(W.dimer_system(L=16, rho=5, n_md=10, seed=6, bulk_rate=0.03),
                                        cell_order="hilbert"),
     "ragged_hilbert": lambda: dict(W.base_params(L=(7, 5, 9), rho=6, n_md=5), cell_order="hilbert"),
+    # solvent mass and temperature away from 1: the kicks dt f/(2m), the
+    # velocity scale sqrt(kT/m) of the state and the factor m of the
+    # temperature equation enter every step
+    "dimer_react_m2_kT05": lambda: dict(W.dimer_system(L=16, rho=5, n_md=20, seed=3, bulk_rate=0.05),
+                                        mass=2.0, kT=0.5),
 }
 
 
@@ -100,9 +105,10 @@ def test_fp64_trajectory_bitwise(case):
     _assert_obs(g.observables(), o.observables())
 
 
-def test_fp64_gpu_init_matches_oracle_init():
+@pytest.mark.parametrize("mass,kT", [(1.0, 1.0), (2.0, 0.5)])
+def test_fp64_gpu_init_matches_oracle_init(mass, kT):
     rm = _rm()
-    p = W.sphere10()
+    p = dict(W.sphere10(), mass=mass, kT=kT)
     g = rm.System(p, 77)
     o = oracle.Oracle(p, 77)
     gs, os_ = g.get_state(), o.get_state()
@@ -176,8 +182,9 @@ def test_fp64_tiny_and_empty_systems():
         _assert_bitwise(g.get_state(), o.get_state(), f"L={L} n={n}")
 
 
-def test_fp64_anderson_thermostat():
-    p = W.dimer_system(L=14, rho=6, n_md=10, seed=7, bulk_rate=0.0)
+@pytest.mark.parametrize("mass,kT", [(1.0, 1.0), (2.0, 0.5)])
+def test_fp64_anderson_thermostat(mass, kT):
+    p = dict(W.dimer_system(L=14, rho=6, n_md=10, seed=7, bulk_rate=0.0), mass=mass, kT=kT)
     p["rule"] = "at"
     s0 = W.random_state(p, 106)
     g, o = _run_both(p, s0, 13, 10, 1)
@@ -185,6 +192,9 @@ def test_fp64_anderson_thermostat():
     assert np.array_equal(gs["id"], os_["id"])
     assert np.allclose(gs["v"], os_["v"], rtol=0, atol=1e-12)
     assert np.allclose(gs["x"], os_["x"], rtol=0, atol=1e-12)
+    go, oo = g.observables(), o.observables()
+    assert go["temperature"] == pytest.approx(oo["temperature"], rel=1e-12)
+    assert go["n_cells_T"] == oo["n_cells_T"]
 
 
 def test_fp64_many_list_workgroups():
@@ -397,6 +407,42 @@ def test_errors_are_reported():
     assert e.value.flags & 16
 
 
+def test_set_state_rejects_invalid_states_and_nonfinite_cell_is_flagged():
+    """set_state applies the library's state check before uploading (a NaN
+    velocity, a duplicated id, a particle deep in a colloid core are
+    rejected and the system keeps its state); a finite state whose cell
+    velocity overflows in the collision latches the non-finite flag.  The
+    overflowing particles leave the box in one step, so this is a GPU-side
+    check of the flag (the kernels' cell index guards keep every access in
+    bounds); the oracle's flag is pinned on the CPU."""
+    rm = _rm()
+    p = W.dimer_system(L=14, rho=6, n_md=10, seed=9)
+    g = rm.System(p, 1)
+    s = g.get_state()
+    for what in ("v", "id", "core"):
+        bad = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in s.items()}
+        if what == "v":
+            bad["v"][1, 3] = np.nan
+        elif what == "id":
+            bad["id"][4] = bad["id"][5]
+        else:
+            bad["x"][:, 4] = np.mod(s["X"][0], 14.0)
+        with pytest.raises(rm.RmpError):
+            g.set_state(bad)
+    after = g.get_state()
+    for k in ("x", "v", "id", "state"):
+        assert np.array_equal(after[k], s[k]), k
+    q = W.base_params(L=(6, 6, 6), rho=3, n_md=2)
+    h = rm.System(q, 3)
+    st = W.random_state(q, 4)
+    st["x"][:, 1] = st["x"][:, 0]
+    st["v"][:, 0] = st["v"][:, 1] = 1.5e308
+    h.set_state(st)
+    print("[parity] overflowing cell velocity: 6^3 cells, two particles at 1.5e308", flush=True)
+    h.step(2, 1)
+    assert h.observables(raise_on_flags=False)["flags"] & 4
+
+
 def test_chain_wait_budget_exceeded_is_reported():
     """A chain workgroup that waits longer than its budget for the other
     workgroups' values gives up, raises RMP_FLAG_BARRIER and waits no more,
@@ -404,7 +450,9 @@ def test_chain_wait_budget_exceeded_is_reported():
     list of some thirty workgroups: the interval is then flagged, or (had
     every wait ended in time) equal to the oracle's.  A new system on the
     same device, with the default budget, then matches the oracle bit for
-    bit."""
+    bit.  Some 34 workgroups meet at more than 40 barriers per call and one
+    exchange alone takes about 2 us, so under a 1 us budget some wait always
+    expires: the flag is required."""
     rm = _rm()
     p = W.dimer_system(L=32, rho=10, n_md=10, seed=21, bulk_rate=0.01)
     s0 = W.random_state(p, 81)
@@ -420,13 +468,12 @@ def test_chain_wait_budget_exceeded_is_reported():
     print(f"[parity] budget 1 us: N={p['n_solvent']} n_md={p['n_md']}", flush=True)
     g.step(p["n_md"], 2)
     flags = g.observables(raise_on_flags=False)["flags"]
-    print(f"[parity] budget 1 us: flags {flags}", flush=True)
-    if flags & 32:
-        with pytest.raises(rm.RmpError) as e:
-            g.observables()
-        assert e.value.flags & 32
-    else:
-        _assert_bitwise(g.get_state(), o.get_state(), "budget 1 us, every wait in time")
+    print(f"[parity] budget 1 us: flags {flags} (time-out path {'taken' if flags & 32 else 'NOT taken'})",
+          flush=True)
+    assert flags & 32, "a 1 us wait budget expired nowhere: the budget is not honoured"
+    with pytest.raises(rm.RmpError) as e:
+        g.observables()
+    assert e.value.flags & 32
     g.close()
     h = rm.System(p, 7)
     h.set_state(s0)

@@ -1132,3 +1132,171 @@ def test_rigid_body_validation_and_same_body_exclusion():
     o.run(5, 1)
     st = o.get_state()
     assert np.abs(st["V"]).max() == 0.0 and np.abs(st["X"] - s["X"]).max() == 0.0
+
+
+# --------------------------------------------------------------------------
+# Solvent mass m and temperature kT away from 1 ("Algorithms": Maxwellian
+# initial velocities at kT, the velocity-Verlet kicks dt f / (2 m), the
+# cell-frame temperature equation with its factor m, the Anderson thermostat
+# drawing relative velocities from N(0, kT/m), and the virtual particles of
+# cut wall cells, Lamura et al. 2001).  Every pin below runs at m = 2.5 and
+# kT = 0.7 (kT/m = 0.28), so that a factor of m or kT dropped, inverted or
+# taken under the wrong square root moves the checked quantity by far more
+# than its statistical error.
+# --------------------------------------------------------------------------
+MASS, KT = 2.5, 0.7
+
+
+def test_init_maxwellian_at_nonunit_mass_and_temperature():
+    """Initial velocities: each component N(0, kT/m), mean removed; the
+    kinetic energy is (m/2) sum v^2 = (3/2) N kT up to sampling error."""
+    from scipy import stats
+    p = _no_colloid(L=(12, 12, 12), rho=10, kT=KT, mass=MASS)
+    o = oracle.Oracle(p, 101)
+    v = o.get_state()["v"]
+    n = p["n_solvent"]
+    var = (v ** 2).mean()
+    # the pooled variance of 3N normals has relative error sqrt(2 / 3N) ~ 0.6 %
+    assert var == pytest.approx(KT / MASS, rel=0.03)
+    for d in range(3):
+        assert stats.kstest(v[d] / math.sqrt(KT / MASS), "norm").pvalue > 1e-3
+    ke = o.observables()["ke_solvent"]
+    assert ke == pytest.approx(1.5 * n * KT, rel=0.03)
+    assert ke == pytest.approx(0.5 * MASS * (v ** 2).sum(), rel=1e-12)
+
+
+@pytest.mark.parametrize("rule", ["srd", "at"])
+def test_temperature_equation_returns_kT(rule):
+    """The cell-frame estimator T = m sum |v - u|^2 / (3 sum (n_c - 1)) of a
+    Maxwellian state at kT returns kT (not kT/m), for both collision rules."""
+    p = _no_colloid(L=(12, 12, 12), rho=10, kT=KT, mass=MASS, rule=rule)
+    o = oracle.Oracle(p, 102)
+    o.collide(3)
+    ob = o.observables()
+    # about 3 * 15,800 degrees of freedom: relative error ~ 0.7 %
+    assert ob["temperature"] == pytest.approx(KT, rel=0.03)
+    assert ob["n_cells_T"] > 1500
+
+
+def test_anderson_thermostat_draws_relative_velocities_at_kT():
+    """MPC-AT from a state twice as fast (temperature 4 kT): after one
+    collision each particle's velocity relative to its cell mean is
+    g_i - <g>_cell with g_i ~ N(0, kT/m), so a component has variance
+    (kT/m)(n_c - 1)/n_c whatever the state before (the thermostat's noise
+    law), and the cell momenta are unchanged.  The temperature equation is
+    evaluated on the velocities that arrive at the collision (before the
+    rule), so it reads the hot state's 4 kT."""
+    from scipy import stats
+    p = _no_colloid(L=(12, 12, 12), rho=10, kT=KT, mass=MASS, rule="at")
+    o = oracle.Oracle(p, 103)
+    s0 = o.get_state()
+    s0["v"] = s0["v"] * 2.0
+    o.set_state(s0)
+    o.collide(3)
+    s1, start, vb = _cells_by_id(o, s0)
+    va = s1["v"]
+    z = []
+    for c in range(start.size - 1):
+        b, e = int(start[c]), int(start[c + 1])
+        nn = e - b
+        if nn < 2:
+            continue
+        np.testing.assert_allclose(va[:, b:e].sum(1), vb[:, b:e].sum(1), rtol=0,
+                                   atol=1e-12 * (np.abs(vb[:, b:e]).sum() + 1))
+        w = va[:, b:e] - va[:, b:e].mean(1, keepdims=True)
+        z.append((w / math.sqrt(KT / MASS * (nn - 1) / nn)).ravel())
+    z = np.concatenate(z)
+    assert (z ** 2).mean() == pytest.approx(1.0, rel=0.03)
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+    assert o.observables()["temperature"] == pytest.approx(4.0 * KT, rel=0.03)
+
+
+def test_momentum_and_energy_with_colloids_at_nonunit_mass():
+    """Velocity-Verlet with the solvent kick dt f/(2m) and the colloid kick
+    dt F/(2M): total momentum m sum v + sum M V is conserved to rounding
+    through the colloid-solvent forces, and the energy error of the
+    integrator still shrinks as dt^2."""
+    base = W.dimer_system(L=16, rho=6, n_md=1, seed=5, bulk_rate=0.0, cat_prob=0.0)
+    base["mass"], base["kT"] = MASS, KT
+    s0 = W.random_state(base, 104)
+    o = oracle.Oracle(base, 105, init=False)
+    o.set_state(s0)
+    o.build_list(1)
+    P0 = o.observables()["momentum"]
+    for _ in range(200):
+        o.interval(1, collide=False)
+    P1 = o.observables()["momentum"]
+    pscale = math.sqrt(base["n_solvent"] * MASS * KT)
+    assert np.abs(P1 - P0).max() < 1e-11 * pscale
+    # the colloids did feel the solvent: the force was not zero throughout
+    assert np.abs(o.get_state()["V"] - s0["V"]).max() > 1e-4
+    amps = []
+    for dt in (0.01, 0.005):
+        p = dict(base); p["dt"] = dt
+        q = oracle.Oracle(p, 106, init=False)
+        q.set_state(s0)
+        q.build_list(1)
+        e0 = _energy(q)
+        es = []
+        for _ in range(int(round(1.0 / dt))):
+            q.interval(1, collide=False)
+            es.append(_energy(q) - e0)
+        amps.append(np.abs(es).max())
+    assert 3.0 < amps[0] / amps[1] < 5.0
+
+
+def test_virtual_particles_carry_thermal_momentum_at_kT():
+    """Cut wall cells with n < n0 particles, all at rest: the n0 - n virtual
+    particles contribute a summed momentum of variance (n0 - n) kT/m per
+    component, so u = sqrt(n0 - n) sqrt(kT/m) xi / n0 and every particle of
+    the cell leaves with v' = u - R u.  Averaged over the random axis,
+    E|v'|^2 = 4 (1 - cos alpha)(n0 - n) kT / (m n0^2).  Cells away from the
+    plates (u = 0) stay at rest."""
+    p = _flow(L=(16, 16, 4), rho=5, kT=KT, mass=MASS)
+    n0 = 20
+    p["wall_density"] = n0
+    o = oracle.Oracle(p, 107, init=False)
+    s = W.random_state(p, 108)
+    s["v"][:] = 0.0
+    ratio_num, ratio_den, cells = 0.0, 0.0, 0
+    for coll in range(4):
+        s["coll_step"] = coll
+        o.set_state(s)
+        keys = o.cell_keys(o.shift(coll))
+        o.collide(1)
+        st = o.get_state()
+        order = np.argsort(st["id"])
+        v1 = st["v"][:, order]
+        k0 = keys[np.argsort(s["id"])]
+        layer = k0 // (16 * 16)
+        for key in np.unique(k0):
+            m = k0 == key
+            nn = int(m.sum())
+            vv = v1[:, m]
+            assert np.abs(vv - vv[:, :1]).max() < 1e-14 * (1 + np.abs(vv).max())
+            if layer[m][0] in (0, 4) and nn < n0:
+                ratio_num += float((vv[:, 0] ** 2).sum())
+                ratio_den += 4.0 * (1.0 - math.cos(ALPHA)) * (n0 - nn) * KT / (MASS * n0 * n0)
+                cells += 1
+            else:
+                assert np.abs(vv).max() == 0.0
+    assert cells > 1500
+    # about 2,000 cells: the ratio's relative error is about 3 %
+    assert ratio_num / ratio_den == pytest.approx(1.0, rel=0.12)
+
+
+def test_nonfinite_cell_velocity_is_flagged():
+    """A cell whose centre-of-mass velocity is not finite (two velocities
+    that overflow when summed) latches the non-finite flag at the collision;
+    a finite state does not."""
+    p = _no_colloid(L=(4, 4, 4), rho=3)
+    o = oracle.Oracle(p, 109, init=False)
+    s = W.random_state(p, 110)
+    o.set_state(s)
+    o.collide(1)
+    assert o.observables()["flags"] & oracle.F_NONFINITE == 0
+    s["x"][:, 1] = s["x"][:, 0]           # same cell for any shift? same point
+    s["v"][0, 0] = s["v"][0, 1] = 1.5e308
+    o.set_state(s)
+    o.collide(1)
+    assert o.observables()["flags"] & oracle.F_NONFINITE

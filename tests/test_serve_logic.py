@@ -23,7 +23,9 @@ class FakeClock:
 class FakePool:
     """Stands in for a GPU pool: a tick costs `tick_s` of fake time."""
 
-    def __init__(self, precision, n_slots, clock, tick_s=0.01, fail_seeds=()):
+    def __init__(self, precision, n_slots, clock, tick_s=0.01, fail_seeds=(), barrier_fail=None):
+        self.barrier_fail = dict(barrier_fail or {})   # seed -> admissions that time out
+        self.admissions = {}
         self.precision = precision
         self.n_slots = n_slots
         self.clock = clock
@@ -38,7 +40,9 @@ class FakePool:
 
     def admit(self, slot, p, seed, n_md):
         assert slot not in self.slots
-        self.slots[slot] = dict(seed=seed, ticks=0)
+        k = self.admissions.get(seed, 0)
+        self.admissions[seed] = k + 1
+        self.slots[slot] = dict(seed=seed, ticks=0, barrier=k < self.barrier_fail.get(seed, 0))
         self.log.append(("admit", slot, seed, self.clock()))
         self.max_occupied = max(self.max_occupied, len(self.slots))
 
@@ -53,7 +57,8 @@ class FakePool:
 
     def observables(self, slot):
         s = self.slots[slot]
-        return dict(flags=16 if s["seed"] in self.fail_seeds else 0, coll_step=s["ticks"])
+        f = (16 if s["seed"] in self.fail_seeds else 0) | (32 if s["barrier"] else 0)
+        return dict(flags=f, coll_step=s["ticks"])
 
     def state(self, slot):
         return dict(ticks=self.slots[slot]["ticks"])
@@ -157,3 +162,22 @@ def test_autotune_caches_best_per_box_class(tmp_path):
     assert autotune.lookup(q, cache_path=cache) == autotune.DEFAULT
     data = json.load(open(cache))
     assert autotune.box_class(p) in data and len(data[autotune.box_class(p)]["points"]) == 18
+
+
+def test_barrier_timeout_restarts_the_job_once():
+    """A job flagged with RMP_FLAG_BARRIER is rerun once from its initial
+    state (admitted again, ahead of the queue); a second time-out is
+    reported as its error, and the other jobs are unaffected."""
+    clock = FakeClock()
+    pool = FakePool(64, 2, clock, barrier_fail={1: 1, 2: 2})
+    srv = Server(hbm_budget=10**9, pools={64: pool}, clock=clock)
+    jobs = [_job(0.0, 1000, 4, 64, seed=i) for i in range(4)]
+    res = {r.job_id: r for r in srv.run(jobs, realtime=True)}
+    assert len(res) == 4
+    assert res[0].error is None and res[0].restarts == 0
+    assert res[1].error is None and res[1].restarts == 1
+    assert res[1].observables["coll_step"] == 4
+    assert res[2].error is not None and "0x20" in res[2].error and res[2].restarts == 1
+    assert res[3].error is None
+    assert pool.admissions == {0: 1, 1: 2, 2: 2, 3: 1}
+    assert srv.used == 0
