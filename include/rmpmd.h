@@ -211,14 +211,17 @@ rmp_status rmp_check_state(const rmp_params* p, const rmp_host_state* src);
 rmp_status rmp_destroy(rmp_system* s);
 
 /* Per-kernel launch parameters (autotuning).  A negative field keeps its
- * current value; so does 0, except for use_graph, chain_resident and
- * chain_block, where 0 is a value (collide_cells is 0 until set).  Applies to the next rmp_step /
+ * current value; so does 0, except for use_graph, chain_resident,
+ * chain_block, collide_block, collide_ppt, collide_xcd and chain_serial,
+ * where 0 is a value (collide_cells is 0 until set).  Applies to the next rmp_step /
  * rmp_batch_step. */
 typedef struct rmp_tuning {
     int32_t stream_block;      /* threads per workgroup, particle kernels       */
-    int32_t stream_ppt;        /* particles per thread in the streaming kernel  */
-    int32_t collide_cells;     /* cells per collision tile (power of two; 0:
-                                  by box size, the default)                     */
+    int32_t stream_ppt;        /* particles per thread in the streaming kernel
+                                  (1, 2 or 4; default 2)                        */
+    int32_t collide_cells;     /* cells per collision tile, 8 .. 64 (0: sized
+                                  from the density so that a tile fills about
+                                  0.94 of a collision group, the default)      */
     int32_t chain_k;           /* Verlet-list entries per thread (1, 2 or 4)    */
     int32_t use_graph;         /* 1: replay a captured hipGraph per interval    */
     int32_t chain_resident;    /* chain workgroups taken to fit on the device at
@@ -234,6 +237,16 @@ typedef struct rmp_tuning {
                                   beyond it the workgroup gives up, raises
                                   RMP_FLAG_BARRIER and waits no more in that
                                   launch, so the launch always ends          */
+    int32_t collide_block;     /* collision workgroup size: 256 or 512 threads
+                                  (0: 256)                                      */
+    int32_t collide_ppt;       /* particles each collision thread holds: 1 or 2
+                                  (0: 2); a group of cells holds at most
+                                  collide_block * collide_ppt particles         */
+    int32_t collide_xcd;       /* 1: tiles dealt to the eight XCDs in
+                                  contiguous ranges (0: in launch order)        */
+    int32_t chain_serial;      /* 1: the MD chain runs before the streaming
+                                  kernel on the same stream (0: next to it on a
+                                  side stream)                                  */
 } rmp_tuning;
 rmp_status rmp_set_tuning(rmp_system* s, const rmp_tuning* t);
 rmp_status rmp_get_tuning(rmp_system* s, rmp_tuning* t);

@@ -182,7 +182,7 @@ class System:
         check(_capi.lib().rmp_set_state(self.h, C.byref(h)), "rmp_set_state")
 
     def set_tuning(self, **kw):
-        t = _capi.Tuning(-1, -1, -1, -1, -1, -1, -1, -1)
+        t = _capi.Tuning(*([-1] * len(_capi.Tuning._fields_)))
         for k, v in kw.items():
             setattr(t, k, int(v))
         check(_capi.lib().rmp_set_tuning(self.h, C.byref(t)), "rmp_set_tuning")
@@ -304,13 +304,13 @@ class Batch:
         check(_capi.lib().rmp_batch_set_state(self.h, int(slot), C.byref(h)), "rmp_batch_set_state")
 
     def set_tuning(self, **kw):
-        t = _capi.Tuning(-1, -1, -1, -1, -1, -1, -1, -1)
+        t = _capi.Tuning(*([-1] * len(_capi.Tuning._fields_)))
         for k, v in kw.items():
             setattr(t, k, int(v))
         check(_capi.lib().rmp_batch_set_tuning(self.h, C.byref(t)), "rmp_batch_set_tuning")
 
     def set_slot_tuning(self, slot: int, collide_cells: int):
-        t = _capi.Tuning(-1, -1, int(collide_cells), -1, -1, -1, -1, -1)
+        t = _capi.Tuning(-1, -1, int(collide_cells), *([-1] * (len(_capi.Tuning._fields_) - 3)))
         check(_capi.lib().rmp_batch_set_slot_tuning(self.h, int(slot), C.byref(t)),
               "rmp_batch_set_slot_tuning")
 

@@ -67,6 +67,8 @@ class Tuning(C.Structure):
         ("stream_block", C.c_int32), ("stream_ppt", C.c_int32), ("collide_cells", C.c_int32),
         ("chain_k", C.c_int32), ("use_graph", C.c_int32), ("chain_resident", C.c_int32),
         ("chain_block", C.c_int32), ("barrier_budget_us", C.c_int32),
+        ("collide_block", C.c_int32), ("collide_ppt", C.c_int32), ("collide_xcd", C.c_int32),
+        ("chain_serial", C.c_int32),
     ]
 
 

@@ -146,8 +146,8 @@ Sizes sizes_of(const rmp_params* p)
 
 // offsets of every array inside a replica workspace
 struct Layout {
-    size_t cp, rs, x[2], v[2], id[2], st[2], keyrank, perm, cflag, count, start, scanblk,
-        chunk_cnt, chunk_off, cand_idx, order, partials, epart, tpart, ptable, obs_part, mean, total;
+    size_t cp, rs, x[2], v[2], id[2], st[2], keyrank, stage, cflag, count, start, scanblk,
+        chunk_cnt, chunk_off, cand_idx, order, partials, finals, epart, tpart, bigmask, ptable, obs_part, mean, total;
 };
 
 Layout layout_of(const rmp_params* p)
@@ -166,7 +166,7 @@ Layout layout_of(const rmp_params* p)
         L.st[b] = take(s.n);
     }
     L.keyrank = take(8 * s.n);
-    L.perm = take(4 * s.n);
+    L.stage = take((tb == 8 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * s.n);
     L.cflag = take(s.n);
     L.count = take(4 * s.ncell);
     L.start = take(4 * (s.ncell + 1));
@@ -176,8 +176,10 @@ Layout layout_of(const rmp_params* p)
     L.cand_idx = take(4 * (size_t)s.cand_cap);
     L.order = take(2 * 4 * (size_t)s.ncell);
     L.partials = take(2 * (size_t)s.G * NVAL_MAX * 2 * 8);
+    L.finals = take(2 * (size_t)NVAL_MAX * 2 * 8);
     L.epart = take((size_t)s.G * 2 * 8);
     L.tpart = take((size_t)s.n_tiles_max * 4 * 8);
+    L.bigmask = take((size_t)s.n_tiles_max * 8);
     L.ptable = take(RMP_PTABLE * 8);
     L.obs_part = take((size_t)s.n_chunks * 8 * 8);
     L.mean = take(4 * 8);
@@ -240,7 +242,7 @@ struct rmp_batch {
     bool any_analysis = false;
     bool any_iterative = false;     // some occupied slot uses the iterative RATTLE
     int64_t n_total = 0;            // solvent particles over the occupied slots
-    rmp_tuning tun{256, 1, 0, 1, 1, 0, 0, 0};
+    rmp_tuning tun{256, 2, 0, 1, 1, 0, 0, 0, 0, 0, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
@@ -339,18 +341,27 @@ ChainShape chain_shape_of(const rmp_batch* b)
     return ChainShape{256, k, k == 1 ? 0 : (k == 2 ? 1 : 2)};
 }
 
+// Threads and particles per thread of the collision workgroup (a group of
+// cells holds at most their product of particles)
+int collide_nt(const rmp_batch* b) { return b->tun.collide_block == 512 ? 512 : 256; }
+int collide_ppt(const rmp_batch* b) { return b->tun.collide_ppt == 1 ? 1 : 2; }
+
 // Cells per collision tile: the slot's override, else the batch tuning,
-// else by box size (measured: 32 cells for boxes up to 2^20 cells, 64 above,
-// where more particles per workgroup keep more gathers in flight)
-int tile_cells_of(const rmp_batch* b, int override_cells, int64_t ncell)
+// else sized so that the mean tile holds about 0.94 of a group's capacity
+// (measured at 128^3, rho 10: 48 cells 1.16 ms, 39 cells 1.29 ms, 32 cells
+// 1.49 ms per collision; a tile beyond the capacity takes a second group),
+// between MIN_TILE_CELLS and COLL_TCMAX
+int tile_cells_of(const rmp_batch* b, int override_cells, int64_t ncell, int64_t n)
 {
     int tc = override_cells > 0 ? override_cells : b->tun.collide_cells;
-    if (tc <= 0) tc = ncell >= ((int64_t)1 << 20) ? 64 : 32;
+    if (tc <= 0) {
+        const double rho = ncell > 0 ? (double)n / (double)ncell : 1.0;
+        const double cap = (double)(collide_nt(b) * collide_ppt(b));
+        tc = rho > 0.0 ? (int)(0.94 * cap / rho) : COLL_TCMAX;
+    }
     if (tc < MIN_TILE_CELLS) tc = MIN_TILE_CELLS;
     if (tc > COLL_TCMAX) tc = COLL_TCMAX;
-    int p2 = MIN_TILE_CELLS;
-    while (p2 * 2 <= tc) p2 *= 2;
-    return p2;
+    return tc;
 }
 
 void fill_desc(rmp_batch* b, Replica& r)
@@ -377,7 +388,7 @@ void fill_desc(rmp_batch* b, Replica& r)
     D.n_md = r.n_md;
     D.rule = p->rule;
     D.n_chunks = s.n_chunks;
-    D.tile_cells = tile_cells_of(b, r.tile_cells, s.ncell);
+    D.tile_cells = tile_cells_of(b, r.tile_cells, s.ncell, s.n);
     D.n_tiles = (int32_t)((s.ncell + D.tile_cells - 1) / D.tile_cells);
     D.n_scanblk = s.n_scanblk;
     D.cand_cap = s.cand_cap;
@@ -416,7 +427,7 @@ void fill_desc(rmp_batch* b, Replica& r)
         D.st[q] = (uint8_t*)(w + L.st[q]);
     }
     D.keyrank = (uint64_t*)(w + L.keyrank);
-    D.perm = (uint32_t*)(w + L.perm);
+    D.stage = (void*)(w + L.stage);
     D.cflag = (uint8_t*)(w + L.cflag);
     D.count = (uint32_t*)(w + L.count);
     D.start = (uint32_t*)(w + L.start);
@@ -427,8 +438,10 @@ void fill_desc(rmp_batch* b, Replica& r)
     D.rank_of = (const uint32_t*)(w + L.order);
     D.cell_of = (const uint32_t*)(w + L.order) + s.ncell;
     D.partials = (double*)(w + L.partials);
+    D.finals = (double*)(w + L.finals);
     D.epart = (double*)(w + L.epart);
     D.tpart = (double*)(w + L.tpart);
+    D.bigmask = (uint64_t*)(w + L.bigmask);
     D.ptable = (double*)(w + L.ptable);
     D.obs_part = (double*)(w + L.obs_part);
     D.cp = (ColloidParams*)(w + L.cp);
@@ -742,30 +755,66 @@ rmp_status launch_list(rmp_batch* b)
     return last_launch("list build");
 }
 
+template <class T, int RULE>
+void launch_collide_rule(rmp_batch* b, hipStream_t s)
+{
+    const dim3 g(b->totals[PF_TILE]);
+    const Work w = work(b, PF_TILE);
+    const int xcd = b->tun.collide_xcd;
+    const int nt = collide_nt(b), ppt = collide_ppt(b);
+    if (nt == 512 && ppt == 2) hipLaunchKernelGGL((k_collide<T, RULE, 512, 2>), g, dim3(512), 0, s, w, xcd);
+    else if (nt == 512) hipLaunchKernelGGL((k_collide<T, RULE, 512, 1>), g, dim3(512), 0, s, w, xcd);
+    else if (ppt == 2) hipLaunchKernelGGL((k_collide<T, RULE, 256, 2>), g, dim3(256), 0, s, w, xcd);
+    else hipLaunchKernelGGL((k_collide<T, RULE, 256, 1>), g, dim3(256), 0, s, w, xcd);
+}
+
+// every collision launch is followed by the pass over the cells beyond a
+// group's capacity (tiles without any such cell cost one mask load each)
+template <class T>
+void launch_collide(rmp_batch* b, hipStream_t s, int rule)
+{
+    const int items = b->totals[PF_TILE];
+    const dim3 gb((unsigned)((items + 63) / 64));
+    if (rule == 0) {
+        launch_collide_rule<T, 0>(b, s);
+        hipLaunchKernelGGL((k_collide_big<T, 0>), gb, dim3(256), 0, s, work(b, PF_TILE), items);
+    } else {
+        launch_collide_rule<T, 1>(b, s);
+        hipLaunchKernelGGL((k_collide_big<T, 1>), gb, dim3(256), 0, s, work(b, PF_TILE), items);
+    }
+}
+
 // one interval for every occupied replica
 template <class T>
 rmp_status launch_interval(rmp_batch* b, hipStream_t s)
 {
     const int nch = b->totals[PF_CHUNK];
     if (nch == 0) return RMP_OK;
-    // fork: the MD chain runs on the side stream next to the streaming kernel
-    HIPCHK(hipEventRecord(b->fork, s));
-    HIPCHK(hipStreamWaitEvent(b->side, b->fork, 0));
-    rmp_status st = launch_chain<T>(b, b->side);
+    // fork: the MD chain runs on the side stream next to the streaming
+    // kernel (chain_serial: before it, on the same stream)
+    const bool serial = b->tun.chain_serial != 0;
+    if (!serial) {
+        HIPCHK(hipEventRecord(b->fork, s));
+        HIPCHK(hipStreamWaitEvent(b->side, b->fork, 0));
+    }
+    rmp_status st = launch_chain<T>(b, serial ? s : b->side);
     if (st != RMP_OK) return st;
     {
         Timer tm(b, KN_STREAM, s);
+        // stream_block threads holding stream_ppt particles each (1, 2 or 4)
         int bs = b->tun.stream_block;
         if (bs != 64 && bs != 128 && bs != 256) bs = 256;
-        int ppt = b->tun.stream_ppt;
-        if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) ppt = 1;
-        int span = bs * ppt;
-        if (span > CHUNK) span = CHUNK;
-        const int wpc = CHUNK / span;
-        hipLaunchKernelGGL((k_stream_bin<T>), dim3(nch * wpc), dim3(bs), 0, s, work(b, PF_CHUNK), wpc);
+        const int ppt = b->tun.stream_ppt == 2 || b->tun.stream_ppt == 4 ? b->tun.stream_ppt : 1;
+        const int wpc = CHUNK / (bs * ppt);
+        const dim3 g(nch * wpc);
+        if (ppt == 4) hipLaunchKernelGGL((k_stream_bin<T, 4>), g, dim3(bs), 0, s, work(b, PF_CHUNK), wpc);
+        else if (ppt == 2) hipLaunchKernelGGL((k_stream_bin<T, 2>), g, dim3(bs), 0, s, work(b, PF_CHUNK), wpc);
+        else hipLaunchKernelGGL((k_stream_bin<T, 1>), g, dim3(bs), 0, s, work(b, PF_CHUNK), wpc);
     }
-    HIPCHK(hipEventRecord(b->join, b->side));
-    HIPCHK(hipStreamWaitEvent(s, b->join, 0));
+    if (!serial) {
+        HIPCHK(hipEventRecord(b->join, b->side));
+        HIPCHK(hipStreamWaitEvent(s, b->join, 0));
+    }
     // small grids: each scan block sums the counts before it itself
     const int direct = b->max_scanblk <= SCAN_DIRECT_BLOCKS ? 1 : 0;
     if (b->multi_scan && !direct) {
@@ -778,14 +827,12 @@ rmp_status launch_interval(rmp_batch* b, hipStream_t s)
     }
     {
         Timer tm(b, KN_SCATTER, s);
-        hipLaunchKernelGGL(k_scatter, dim3(nch), dim3(256), 0, s, work(b, PF_CHUNK));
+        hipLaunchKernelGGL((k_scatter<T>), dim3(nch), dim3(256), 0, s, work(b, PF_CHUNK));
     }
     {
         Timer tm(b, KN_COLLIDE, s);
-        if (b->have_rule[0])
-            hipLaunchKernelGGL((k_collide<T, 0>), dim3(b->totals[PF_TILE]), dim3(COLL_NT), 0, s, work(b, PF_TILE));
-        if (b->have_rule[1])
-            hipLaunchKernelGGL((k_collide<T, 1>), dim3(b->totals[PF_TILE]), dim3(COLL_NT), 0, s, work(b, PF_TILE));
+        for (int rule = 0; rule < 2; ++rule)
+            if (b->have_rule[rule]) launch_collide<T>(b, s, rule);
     }
     {
         Timer tm(b, KN_CHUNKSCAN, s);
@@ -1182,6 +1229,10 @@ rmp_status set_state_t(rmp_batch* b, int slot, const rmp_host_state* src)
     rs.md_step = src->md_step;
     rs.coll_step = src->coll_step;
     HIPCHK(hipMemcpy(R.ws + R.lay.rs, &rs, sizeof(rs), hipMemcpyHostToDevice));
+    // the MD chain's exchange words carry epochs derived from the step
+    // counters; a state that sets the counters back must not meet words left
+    // from the same epochs (epochs start at 1, so zero words never match)
+    HIPCHK(hipMemset(R.ws + R.lay.partials, 0, R.lay.epart - R.lay.partials));
     R.list_valid = false;
     return RMP_OK;
 }
@@ -1543,6 +1594,15 @@ rmp_status rmp_batch_set_tuning(rmp_batch* b, const rmp_tuning* t)
     if (t->chain_resident >= 0) n.chain_resident = t->chain_resident;
     if (t->chain_block >= 0) n.chain_block = t->chain_block;
     if (t->barrier_budget_us >= 0) n.barrier_budget_us = t->barrier_budget_us;
+    if (t->collide_block >= 0) n.collide_block = t->collide_block;
+    if (t->collide_ppt >= 0) n.collide_ppt = t->collide_ppt;
+    if (t->collide_xcd >= 0) n.collide_xcd = t->collide_xcd;
+    if (t->chain_serial >= 0) n.chain_serial = t->chain_serial;
+    if (n.chain_serial != 0 && n.chain_serial != 1) return RMP_EINVAL;
+    if (n.collide_block != 0 && n.collide_block != 256 && n.collide_block != 512) return RMP_EINVAL;
+    if (n.collide_ppt < 0 || n.collide_ppt > 2) return RMP_EINVAL;
+    if (n.collide_xcd != 0 && n.collide_xcd != 1) return RMP_EINVAL;
+    if (n.collide_cells > COLL_TCMAX) return RMP_EINVAL;
     if (n.chain_block != 0 && n.chain_block != 256 && n.chain_block != 512) return RMP_EINVAL;
     if (n.barrier_budget_us > BARRIER_BUDGET_MAX_US) return RMP_EINVAL;
     if (n.chain_k != 1 && n.chain_k != 2 && n.chain_k != 4) return RMP_EINVAL;

@@ -73,6 +73,24 @@ struct Analysis {
     double* msd;               // [nb][cap]
 };
 
+// A particle's record in the staging array that the scatter fills in cell
+// order for the collision: one aligned 64-byte record in FP64 (32 bytes in
+// FP32), so that the scatter writes and the collision reads whole sectors.
+// FP64: x[3], v[3], id, old index, state byte.  FP32: x[3], v[3], then id and
+// old index (both < 2^31) with the state's catalysis bit in bit 31 of the id
+// word and its species bit in bit 31 of the index word.
+template <class T> struct Rec;
+template <> struct alignas(64) Rec<double> {
+    double x[3], v[3];
+    uint32_t id, idx;
+    uint32_t st, pad;
+};
+template <> struct alignas(32) Rec<float> {
+    float x[3], v[3];
+    uint32_t id_f, idx_s;
+};
+static_assert(sizeof(Rec<double>) == 64 && sizeof(Rec<float>) == 32, "record sizes");
+
 // Per-replica descriptor, written by the host.
 struct RepDesc {
     int32_t L[3];              // cell grid (with walls L[2] is one layer more than the box)
@@ -97,7 +115,7 @@ struct RepDesc {
     uint32_t* id[2];
     uint8_t* st[2];
     uint64_t* keyrank;         // (key << 32) | rank
-    uint32_t* perm;
+    void* stage;               // [n] particle records in cell order (Rec<T>), written by the scatter
     uint32_t* count;           // [ncell]
     uint32_t* start;           // [ncell + 1]
     uint32_t* scanblk;         // [n_scanblk]
@@ -108,8 +126,10 @@ struct RepDesc {
     const uint32_t* rank_of;   // [ncell] sort rank of a cell (Hilbert order)
     const uint32_t* cell_of;   // [ncell] cell of a sort rank
     double* partials;          // [2][G][NVAL_MAX][2] 64-bit exchange words of the MD chain
+    double* finals;            // [2][NVAL_MAX][2] exchange totals of the MD chain (two-hop exchange)
     double* epart;             // [G][2] reaction energy / flips of the interval
-    double* tpart;             // [n_tiles][2]
+    double* tpart;             // [n_tiles][4] collision partials: temperature sum, cells, reaction energy, flips
+    uint64_t* bigmask;         // [n_tiles] cells of a tile beyond a collision group's capacity
     double* ptable;            // [RMP_PTABLE]
     double* obs_part;          // [n_chunks][8]
     ColloidParams* cp;

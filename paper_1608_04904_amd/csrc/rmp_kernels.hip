@@ -14,9 +14,11 @@
 //                  binary tree over list positions; inter-workgroup barrier
 //                  per step when the list spans several workgroups
 //   k_scan_*       exclusive scan of the cell counts -> cell_start
-//   k_scatter      perm[cell_start[key] + rank] = i
-//   k_collide      per LDS tile of cells: restore the stable (old-index)
-//                  order inside each cell, gather, FP64 centre-of-mass sums,
+//   k_scatter      each particle's record (x, v, id, old index, state) to
+//                  slot cell_start[key] + rank of the staging array
+//   k_collide      per tile of cells: read the tile's records (contiguous),
+//                  restore the stable (old-index) order inside each cell,
+//                  FP64 centre-of-mass sums,
 //                  rotation about a random axis (or Anderson thermostat),
 //                  bulk B->A reaction, Verlet-list flags for the next
 //                  interval, coalesced write of the cell-ordered arrays
@@ -83,6 +85,36 @@ __device__ __forceinline__ void wave_tree_sum_n(double (&v)[N])
                                           __builtin_amdgcn_readlane(__double2loint(v[i]), 63));
         v[i] = a + b;
     }
+}
+
+// minimum of lo and maximum of hi over the 64 lanes (DPP within rows of 16,
+// then the four rows' results read from lanes 15, 31, 47, 63); exact, in
+// every lane
+__device__ __forceinline__ void wave_min_max(double& lo, double& hi)
+{
+#define RMP_MM_STEP(CTRL)                                                       \
+    {                                                                           \
+        const double ol = dpp_d<CTRL, 0xF>(lo), oh = dpp_d<CTRL, 0xF>(hi);      \
+        lo = ol < lo ? ol : lo;                                                 \
+        hi = oh > hi ? oh : hi;                                                 \
+    }
+    RMP_MM_STEP(0xB1)       // quad_perm [1,0,3,2]
+    RMP_MM_STEP(0x4E)       // quad_perm [2,3,0,1]
+    RMP_MM_STEP(0x141)      // row_half_mirror
+    RMP_MM_STEP(0x140)      // row_mirror
+#undef RMP_MM_STEP
+    double l = lo, h = hi;
+#pragma unroll
+    for (int r = 15; r < 64; r += 16) {
+        const double rl = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(lo), r),
+                                           __builtin_amdgcn_readlane(__double2loint(lo), r));
+        const double rh = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(hi), r),
+                                           __builtin_amdgcn_readlane(__double2loint(hi), r));
+        l = rl < l ? rl : l;
+        h = rh > h ? rh : h;
+    }
+    lo = l;
+    hi = h;
 }
 
 // deterministic block sum: wave butterfly, then a pairwise tree over the
@@ -541,7 +573,12 @@ __global__ __launch_bounds__(256) void k_cand_write(Work w)
 // Rank of this lane's particle within its cell, with one atomic per run of
 // equal keys in consecutive lanes (particles arrive sorted by the previous
 // collision's cells, so runs are common).  All 64 lanes must call it.
-__device__ __forceinline__ uint32_t wave_rank(uint32_t* count, uint32_t key, bool valid)
+struct RankIssue {
+    uint32_t base;             // the run head's atomic result (head lanes only)
+    int h;                     // lane of this lane's run head
+};
+
+__device__ __forceinline__ RankIssue wave_rank_issue(uint32_t* count, uint32_t key, bool valid)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t k = valid ? key : 0xffffffffu;
@@ -552,10 +589,22 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t* count, uint32_t key, boo
     const int h = 63 - __clzll(H & upto);
     const uint64_t above = (h == 63) ? 0ull : (H & (~0ull << (h + 1)));
     const int nexth = above ? (__ffsll((long long)above) - 1) : 64;
-    uint32_t base = 0;
-    if (head && valid) base = atomicAdd(&count[key], (uint32_t)(nexth - h));
-    base = __shfl(base, h, 64);
-    return base + (uint32_t)(lane - h);
+    RankIssue r;
+    r.base = 0;
+    r.h = h;
+    if (head && valid) r.base = atomicAdd(&count[key], (uint32_t)(nexth - h));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t wave_rank_finish(const RankIssue& r)
+{
+    const int lane = threadIdx.x & 63;
+    return __shfl(r.base, r.h, 64) + (uint32_t)(lane - r.h);
+}
+
+__device__ __forceinline__ uint32_t wave_rank(uint32_t* count, uint32_t key, bool valid)
+{
+    return wave_rank_finish(wave_rank_issue(count, key, valid));
 }
 
 // One streaming step under the constant acceleration g, with the plates at
@@ -612,8 +661,11 @@ __device__ __forceinline__ void flow_step(T (&x)[3], T (&v)[3], const T (&g)[3],
 // wrap occurred and the per-step wrap can be skipped; otherwise the drifts
 // are replayed with the wrap.  Then the key of the shifted cell of the coming
 // collision and a rank within the cell.  Workgroup `sub` of a chunk covers
-// particles [sub*span, (sub+1)*span) of it, span = blockDim.x * ppt.
-template <class T>
+// particles [sub*span, (sub+1)*span) of it, span = blockDim.x * PPT; thread t
+// holds particles t, t + blockDim.x, ... of its span: every load is issued
+// before the drifts, every rank atomic before the first of them is waited
+// for.
+template <class T, int PPT>
 __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
 {
     const int item = blockIdx.x / wg_per_chunk;
@@ -635,42 +687,74 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
     const T Lt[3] = {(T)D.Ld[0], (T)D.Ld[1], (T)D.Ld[2]};
     T* xs[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
     T* vs[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
-    const bool flow = D.flow != 0;
-    const T g[3] = {(T)D.g[0], (T)D.g[1], (T)D.g[2]};
-    const T hdt = (T)(0.5 * D.dt);
     const int span = CHUNK / wg_per_chunk;
     const int64_t base = (int64_t)chunk * CHUNK + (int64_t)sub * span;
-    for (int j0 = 0; j0 < span; j0 += blockDim.x) {
-        const int64_t i = base + j0 + threadIdx.x;
-        bool valid = (j0 + (int)threadIdx.x < span) && (i < n);
-        if (valid) valid = D.cflag[i] == 0;
-        uint32_t key = 0;
-        if (valid) {
-            T x[3], v[3];
+    if (D.flow) {
+        const T g[3] = {(T)D.g[0], (T)D.g[1], (T)D.g[2]};
+        const T hdt = (T)(0.5 * D.dt);
+        for (int j0 = 0; j0 < span; j0 += blockDim.x) {
+            const int64_t i = base + j0 + threadIdx.x;
+            bool valid = (j0 + (int)threadIdx.x < span) && (i < n);
+            if (valid) valid = D.cflag[i] == 0;
+            uint32_t key = 0;
+            if (valid) {
+                T x[3], v[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) { x[d] = xs[d][i]; v[d] = vs[d][i]; }
-            if (flow) {
+                for (int d = 0; d < 3; ++d) { x[d] = xs[d][i]; v[d] = vs[d][i]; }
                 for (int k = 0; k < nmd; ++k) flow_step<T>(x, v, g, dt, hdt, Lt, D.walls != 0);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) { xs[d][i] = x[d]; vs[d][i] = v[d]; }
-            } else {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    T y = x[d];
-                    for (int k = 0; k < nmd; ++k) y = tfma(dt, v[d], y);
-                    const bool inside = (v[d] >= (T)0) ? (y < Lt[d]) : (y >= (T)0);
-                    if (!inside) {
-                        y = x[d];
-                        for (int k = 0; k < nmd; ++k) y = wrap_coord<T>(tfma(dt, v[d], y), Lt[d]);
-                    }
-                    x[d] = y;
-                    xs[d][i] = y;
-                }
+                key = cell_key(D, (double)x[0], (double)x[1], (double)x[2], s);
             }
-            key = cell_key(D, (double)x[0], (double)x[1], (double)x[2], s);
+            const uint32_t rank = wave_rank(D.count, key, valid);
+            if (valid) D.keyrank[i] = ((uint64_t)key << 32) | rank;
         }
-        const uint32_t rank = wave_rank(D.count, key, valid);
-        if (valid) D.keyrank[i] = ((uint64_t)key << 32) | rank;
+        return;
+    }
+    bool valid[PPT];
+    int64_t ii[PPT];
+    T x[PPT][3], v[PPT][3];
+    const int bs = (int)blockDim.x;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        ii[u] = base + u * bs + threadIdx.x;
+        valid[u] = (u * bs + (int)threadIdx.x < span) && (ii[u] < n);
+        if (valid[u]) valid[u] = D.cflag[ii[u]] == 0;
+    }
+#pragma unroll
+    for (int u = 0; u < PPT; ++u)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            x[u][d] = valid[u] ? xs[d][ii[u]] : (T)0;
+            v[u][d] = valid[u] ? vs[d][ii[u]] : (T)0;
+        }
+    uint32_t key[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            T y = x[u][d];
+            for (int k = 0; k < nmd; ++k) y = tfma(dt, v[u][d], y);
+            const bool inside = (v[u][d] >= (T)0) ? (y < Lt[d]) : (y >= (T)0);
+            if (!inside) {
+                y = x[u][d];
+                for (int k = 0; k < nmd; ++k) y = wrap_coord<T>(tfma(dt, v[u][d], y), Lt[d]);
+            }
+            x[u][d] = y;
+        }
+        key[u] = valid[u] ? cell_key(D, (double)x[u][0], (double)x[u][1], (double)x[u][2], s) : 0u;
+    }
+    RankIssue ri[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) ri[u] = wave_rank_issue(D.count, key[u], valid[u]);
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        const uint32_t rank = wave_rank_finish(ri[u]);
+        if (valid[u]) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) xs[d][ii[u]] = x[u][d];
+            D.keyrank[ii[u]] = ((uint64_t)key[u] << 32) | rank;
+        }
     }
 }
 
@@ -987,6 +1071,7 @@ __device__ __forceinline__ double uniform_d(double v)
 struct ChainConst {
     double Lv[3], hv[3];       // box lengths and half lengths
     uint64_t* partv;           // exchange words
+    uint64_t* finv;            // totals of the two-hop exchange [2][NVAL_MAX][2]
     int Gv;                    // workgroups of the replica's exchange buffers
     double catv;
     uint64_t seedv;
@@ -994,6 +1079,7 @@ struct ChainConst {
     __device__ double L(int d) const { return Lv[d]; }
     __device__ double h(int d) const { return hv[d]; }
     __device__ uint64_t* part() const { return partv; }
+    __device__ uint64_t* fin() const { return finv; }
     __device__ int G() const { return Gv; }
     __device__ double cat_prob() const { return catv; }
     __device__ uint64_t seed() const { return seedv; }
@@ -1008,6 +1094,7 @@ __device__ __forceinline__ ChainConst chain_const(const RepDesc& D, uint64_t bud
         c.hv[d] = uniform_d(D.halfL[d]);
     }
     c.partv = reinterpret_cast<uint64_t*>(uniform_u64((uint64_t)(uintptr_t)D.partials));
+    c.finv = reinterpret_cast<uint64_t*>(uniform_u64((uint64_t)(uintptr_t)D.finals));
     c.Gv = __builtin_amdgcn_readfirstlane(D.G);
     c.catv = uniform_d(D.cat_prob);
     c.seedv = uniform_u64(D.seed);
@@ -1025,6 +1112,11 @@ struct ChainCtx {
     int32_t cCat[MAXC], cType[MAXC];
     double sRed[NT / 64][NVAL_MAX];
     double sNode[NVAL_MAX];
+    // colloid-colloid pairs (a < b) of the current positions: force on the
+    // lower colloid and potential, and whether the pair interacts
+    static constexpr int NPAIR = NB > 1 ? MAXC * (MAXC - 1) / 2 : 1;
+    double sPairF[NPAIR][4];
+    uint8_t sPairOn[NPAIR];
     double sU;
     uint32_t sflags;
     // colloid state and bonds staged for the iterative RATTLE (bond networks)
@@ -1061,6 +1153,31 @@ __device__ __forceinline__ double species_dU_lds(const Ctx& S, const ChainConst&
     return du;
 }
 
+// WCA force of colloid b on colloid a (a < b, sigma_ab = sigma_a + sigma_b,
+// epsilon by the pair's types) and its potential, for the current colloid
+// images; `on` is 0 when the two are of one rigid body or beyond the cut-off
+// (then the values are not used)
+template <class Ctx>
+__device__ __forceinline__ void pair_force(const Ctx& S, const ChainConst& cc, const ColloidParams* cp, int a,
+                                           int b, double (&out)[4], uint8_t& on)
+{
+    on = 0;
+    out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; out[3] = 0.0;
+    if (cp->body[a] == cp->body[b]) return;
+    const double dx = min_image(S.sXw[a][0] - S.sXw[b][0], cc.L(0), cc.h(0));
+    const double dy = min_image(S.sXw[a][1] - S.sXw[b][1], cc.L(1), cc.h(1));
+    const double dz = min_image(S.sXw[a][2] - S.sXw[b][2], cc.L(2), cc.h(2));
+    const double r2 = dot3(dx, dy, dz, dx, dy, dz);
+    const double sab = S.cSigma[a] + S.cSigma[b];
+    const double rc = 0x1.1f59ac3c7d6c0p+0 * sab;
+    if (r2 < rc * rc) {
+        double coef, pot;
+        wca(r2, sab * sab, cp->eps_cc[S.cType[a]][S.cType[b]], coef, pot);
+        out[0] = coef * dx; out[1] = coef * dy; out[2] = coef * dz; out[3] = pot;
+        on = 1;
+    }
+}
+
 // First half of a force evaluation: forces on this workgroup's list
 // entries from all colloids, and the per-colloid force sums and the
 // potential reduced over this workgroup's list positions with the fixed
@@ -1081,6 +1198,51 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainCo
         u[j] = 0.0;
         inside[j] = false;
     }
+    // Colloids within reach of this wave: the bounding box of the wave's
+    // entries (minimum-image offsets from its first entry, which is valid
+    // whenever any is) against each colloid's cut-off sphere, one lane per
+    // colloid.  A colloid out of reach of the box contributes exactly zero to
+    // every entry of the wave, so its distances are not computed.  (Systems
+    // of one or two colloids test them all.)
+    uint32_t reach_mask = nc >= 32 ? 0xffffffffu : ((1u << nc) - 1u);
+    if (nc > 2) {
+        double ref[3], lo[3], hi[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ref[d] = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint((double)x[0][d])),
+                                      __builtin_amdgcn_readfirstlane(__double2loint((double)x[0][d])));
+            lo[d] = 1e300; hi[d] = -1e300;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (valid[j]) {
+                    const double o = min_image((double)x[j][d] - ref[d], cc.L(d), cc.h(d));
+                    lo[d] = o < lo[d] ? o : lo[d];
+                    hi[d] = o > hi[d] ? o : hi[d];
+                }
+            wave_min_max(lo[d], hi[d]);
+        }
+        bool near = true;
+        if (lane < nc) {
+            double r2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (!(hi[d] - lo[d] < cc.h(d))) continue;          // wide (or no entry): no bound
+                const double oc = min_image(S.sXw[lane][d] - ref[d], cc.L(d), cc.h(d));
+                double dd = 1e300;
+#pragma unroll
+                for (int img = -1; img <= 1; ++img) {
+                    const double ci = oc + (double)img * cc.L(d);
+                    double e = lo[d] - ci > ci - hi[d] ? lo[d] - ci : ci - hi[d];
+                    e = e > 0.0 ? e : 0.0;
+                    dd = e < dd ? e : dd;
+                }
+                r2 += dd * dd;
+            }
+            // margin far above the rounding of the entries' own r^2
+            near = r2 <= S.cRc2[lane] * (1.0 + 1e-9) + 1e-9;
+        }
+        reach_mask &= (uint32_t)__ballot(near);
+    }
     // colloids two at a time: forces and the reduction over the K entries
     // of each thread, then the wave trees of the six components (and, after
     // the last pair, of the potential) side by side
@@ -1093,7 +1255,7 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainCo
         for (int cb = 0; cb < CB; ++cb) {
             const int c = c0 + cb;
             tv[3 * cb + 0] = 0.0; tv[3 * cb + 1] = 0.0; tv[3 * cb + 2] = 0.0;
-            if (c >= nc) continue;
+            if (c >= nc || !((reach_mask >> c) & 1u)) continue;
             const double Xc0 = S.sXw[c][0], Xc1 = S.sXw[c][1], Xc2 = S.sXw[c][2];
             const double rc2 = S.cRc2[c], sig2 = S.cSig2[c];
             const double eA = S.cEpsA[c], eB = S.cEpsB[c];
@@ -1282,6 +1444,42 @@ __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0
     wave_tree_sum_n<VB>(out);
 }
 
+// Wait (bounded) for the totals of values [0, nv) of this barrier, published
+// by the workgroups that reduced them (two-hop exchange), into sNode.  One
+// wave; lane l holds values l and l + 64.
+template <class Ctx>
+__device__ __forceinline__ void poll_finals(Ctx& S, const uint64_t* fin, int nv, uint32_t epoch, uint64_t budget)
+{
+    const int lane = threadIdx.x & 63;
+    double val[2] = {0.0, 0.0};
+    const uint64_t t_start = wall_clock64();
+    int nap = 0;
+    while (true) {
+        bool ok = true;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int v = lane + 64 * r;
+            if (v < nv) {
+                const uint64_t wl = __hip_atomic_load(&fin[v * 2 + 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t wh = __hip_atomic_load(&fin[v * 2 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = ok && ((uint32_t)wl == epoch) && ((uint32_t)wh == epoch);
+                val[r] = __hiloint2double((int)(wh >> 32), (int)(wl >> 32));
+            }
+        }
+        if (__ballot(!ok) == 0) break;
+        if (__hip_atomic_load(&S.sflags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & RMP_FLAG_BARRIER)
+            break;
+        if (wall_clock64() - t_start > budget) {
+            if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
+            break;
+        }
+        if (++nap > 16) __builtin_amdgcn_s_sleep(2);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        if (lane + 64 * r < nv) S.sNode[lane + 64 * r] = val[r];
+}
+
 // Second half: wait for the other workgroups' node values of this
 // evaluation, finish the tree over workgroups, then the colloid forces
 // (solvent part, then colloid-colloid pairs in (a<b) order) into cF of
@@ -1299,7 +1497,7 @@ struct PairLane {
 
 template <class T, int K, int NT, int NB>
 __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const ChainConst& cc, const ColloidParams* cp,
-                              int nc, int Gact, int Gpad, uint32_t nbar, uint32_t epoch0,
+                              int nc, int g, int Gact, int Gpad, uint32_t nbar, uint32_t epoch0,
                               bool want_potential, double (&cF)[3], const PairLane& PL)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -1308,6 +1506,20 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const ChainCo
     const int Q = Gpad > 64 ? Gpad / 64 : 1;
     const bool solo = Q == 1 && nv <= 8;
     if (solo && wave != 0) return;
+    if constexpr (NB > 1) {
+        // colloid-colloid pair forces (a < b, enumerated row by row), one
+        // thread per pair: by the waves that have no exchange values to
+        // reduce while the totals arrive (wave 0 alone in the solo form)
+        const int np = nc * (nc - 1) / 2;
+        const int p0 = solo ? lane : t - 64, ps = solo ? 64 : NT - 64;
+        if (solo || wave >= 1)
+            for (int p = p0; p < np; p += ps) {
+                int a = 0, rem = p;
+                while (rem >= nc - 1 - a) { rem -= nc - 1 - a; ++a; }
+                const int b = a + 1 + rem;
+                pair_force(S, cc, cp, a, b, S.sPairF[p], S.sPairOn[p]);
+            }
+    }
     if (Gact > 1) {
         const uint32_t epoch = epoch0 + nbar;
         const uint64_t* part = cc.part() +
@@ -1320,20 +1532,64 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const ChainCo
                 for (int v = 0; v < 8; ++v)
                     if (v < nv) S.sNode[v] = out[v];
         } else {
+            // two hops: workgroup g completes the tree over workgroups of
+            // the values v = g + k Gact (its waves taking turns) and
+            // publishes each total, epoch-tagged like the node values; then
+            // wave 0 collects all totals.  Each workgroup reads Gact words
+            // per value it owns plus nv totals, instead of Gact words for
+            // every value.
             constexpr int VB = 4;
-            for (int v0 = wave; v0 < nv; v0 += NW * VB) {
+            uint64_t* fin = cc.fin() + (int64_t)(nbar & 1) * NVAL_MAX * 2;
+            // (with the pair forces on waves 1.., wave 0 reduces this
+            // workgroup's values alone)
+            constexpr int NWR = NB > 1 ? 1 : NW;
+            const int vs = NWR * Gact;
+            for (int v0 = g + wave * Gact; wave < NWR && v0 < nv; v0 += VB * vs) {
                 double out[VB];
-                poll_reduce<VB, 4>(S, part, v0, NW, nv, Gact, Q, epoch, cc.budget(), out);
+                poll_reduce<VB, 4>(S, part, v0, vs, nv, Gact, Q, epoch, cc.budget(), out);
                 if (lane == 0)
 #pragma unroll
-                    for (int vb = 0; vb < VB; ++vb)
-                        if (v0 + vb * NW < nv) S.sNode[v0 + vb * NW] = out[vb];
+                    for (int vb = 0; vb < VB; ++vb) {
+                        const int v = v0 + vb * vs;
+                        if (v < nv) {
+                            const uint64_t lo = ((uint64_t)(uint32_t)__double2loint(out[vb]) << 32) | epoch;
+                            const uint64_t hi = ((uint64_t)(uint32_t)__double2hiint(out[vb]) << 32) | epoch;
+                            __hip_atomic_store(&fin[v * 2 + 0], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(&fin[v * 2 + 1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
             }
+            if (wave == 0) poll_finals(S, fin, nv, epoch, cc.budget());
         }
     }
     if (solo) wave_sync();
     else __syncthreads();
     // colloid forces: solvent part, then colloid-colloid pairs in (a<b) order
+    if constexpr (NB > 1) {
+        // pairs from LDS (computed at the start of the evaluation): colloid c
+        // adds them in the order of the other colloid, + for the lower index
+        if (t < nc) {
+            const int c = t;
+            double F[3] = {-S.sNode[3 * c + 0], -S.sNode[3 * c + 1], -S.sNode[3 * c + 2]};
+            for (int a = 0; a < nc; ++a) {
+                if (a == c) continue;
+                const bool c_lo = c < a;
+                const int lo = c_lo ? c : a, hi = c_lo ? a : c;
+                const int p = lo * nc - (lo * (lo + 1)) / 2 + (hi - lo - 1);
+                if (!S.sPairOn[p]) continue;
+                for (int d = 0; d < 3; ++d) F[d] = c_lo ? F[d] + S.sPairF[p][d] : F[d] - S.sPairF[p][d];
+            }
+            for (int d = 0; d < 3; ++d) cF[d] = F[d];
+        }
+        if (t == 0 && want_potential) {
+            double ucc = 0.0;
+            const int np = nc * (nc - 1) / 2;
+            for (int p = 0; p < np; ++p)
+                if (S.sPairOn[p]) ucc = ucc + S.sPairF[p][3];
+            S.sU = S.sNode[3 * nc] + ucc;
+        }
+        return;
+    }
     if (t < nc) {
         const int c = t;
         double F[3] = {-S.sNode[3 * c + 0], -S.sNode[3 * c + 1], -S.sNode[3 * c + 2]};
@@ -1512,7 +1768,7 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
 
     // forces at the start of the interval
     chain_compute<T, K, NT>(S, cc, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
-    chain_collect<T, K, NT>(S, cc, cp, nc, Gact, Gpad, nbar, epoch0, false, cF, PL);
+    chain_collect<T, K, NT>(S, cc, cp, nc, g, Gact, Gpad, nbar, epoch0, false, cF, PL);
     // list entries: first half kick and drift of step 0
 #pragma unroll
     for (int j = 0; j < K; ++j)
@@ -1611,7 +1867,7 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
                 }
         }
         // the potential energy is an observable of the last force evaluation
-        chain_collect<T, K, NT>(S, cc, cp, nc, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF, PL);
+        chain_collect<T, K, NT>(S, cc, cp, nc, g, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF, PL);
         // colloids (wave 0, in registers): second half kick, RATTLE
         // velocity stage, Verlet-list soundness check (displacement within
         // the interval)
@@ -1800,6 +2056,63 @@ __global__ __launch_bounds__(1024) void k_scan_final(Work w, int direct)
     if (blk == D.n_scanblk - 1 && threadIdx.x == 0) D.start[D.ncell] = pre + total;
 }
 
+// Particle records of the staging array (Rec<T>): packed and unpacked with
+// the state byte split into the spare top bits of id and index in FP32.
+__device__ __forceinline__ void rec_put(Rec<double>* r, const double (&x)[3], const double (&v)[3],
+                                        uint32_t id, uint32_t idx, uint8_t st)
+{
+    Rec<double> q;
+    q.x[0] = x[0]; q.x[1] = x[1]; q.x[2] = x[2];
+    q.v[0] = v[0]; q.v[1] = v[1]; q.v[2] = v[2];
+    q.id = id; q.idx = idx; q.st = st; q.pad = 0u;
+    *r = q;
+}
+__device__ __forceinline__ void rec_put(Rec<float>* r, const float (&x)[3], const float (&v)[3],
+                                        uint32_t id, uint32_t idx, uint8_t st)
+{
+    Rec<float> q;
+    q.x[0] = x[0]; q.x[1] = x[1]; q.x[2] = x[2];
+    q.v[0] = v[0]; q.v[1] = v[1]; q.v[2] = v[2];
+    q.id_f = id | ((uint32_t)((st >> 1) & 1u) << 31);
+    q.idx_s = idx | ((uint32_t)(st & 1u) << 31);
+    *r = q;
+}
+__device__ __forceinline__ void rec_get(const Rec<double>* r, double (&x)[3], double (&v)[3],
+                                        uint32_t& id, uint32_t& idx, uint8_t& st)
+{
+    const Rec<double> q = *r;
+    x[0] = q.x[0]; x[1] = q.x[1]; x[2] = q.x[2];
+    v[0] = q.v[0]; v[1] = q.v[1]; v[2] = q.v[2];
+    id = q.id; idx = q.idx; st = (uint8_t)q.st;
+}
+__device__ __forceinline__ void rec_get(const Rec<float>* r, float (&x)[3], float (&v)[3],
+                                        uint32_t& id, uint32_t& idx, uint8_t& st)
+{
+    const Rec<float> q = *r;
+    x[0] = q.x[0]; x[1] = q.x[1]; x[2] = q.x[2];
+    v[0] = q.v[0]; v[1] = q.v[1]; v[2] = q.v[2];
+    id = q.id_f & 0x7fffffffu;
+    idx = q.idx_s & 0x7fffffffu;
+    st = (uint8_t)(((q.idx_s >> 31) & 1u) | (((q.id_f >> 31) & 1u) << 1));
+}
+
+// single fields of a record (the oversized-cell path reads them one by one)
+__device__ __forceinline__ uint32_t rec_idx(const Rec<double>* r) { return r->idx; }
+__device__ __forceinline__ uint32_t rec_idx(const Rec<float>* r) { return r->idx_s & 0x7fffffffu; }
+__device__ __forceinline__ uint8_t rec_st(const Rec<double>* r) { return (uint8_t)r->st; }
+__device__ __forceinline__ uint8_t rec_st(const Rec<float>* r)
+{
+    return (uint8_t)(((r->idx_s >> 31) & 1u) | (((r->id_f >> 31) & 1u) << 1));
+}
+__device__ __forceinline__ uint32_t rec_id(const Rec<double>* r) { return r->id; }
+__device__ __forceinline__ uint32_t rec_id(const Rec<float>* r) { return r->id_f & 0x7fffffffu; }
+template <class T>
+__device__ __forceinline__ double rec_v(const Rec<T>* r, int d) { return (double)r->v[d]; }
+
+// Counting-sort scatter: particle i (read in array order, coalesced) goes to
+// slot start[key] + rank of the staging array as one whole record, so the
+// collision reads each tile of cells as one contiguous run.
+template <class T>
 __global__ __launch_bounds__(256) void k_scatter(Work w)
 {
     const int item = blockIdx.x;
@@ -1807,49 +2120,288 @@ __global__ __launch_bounds__(256) void k_scatter(Work w)
     const int chunk = item - w.prefix[rep];
     const RepDesc& D = w.desc[rep];
     if (!D.active) return;
+    const int64_t n = D.n;
+    const int cur = (int)(D.rs->coll_step & 1);
+    const T* xs[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
+    const T* vs[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
+    const uint32_t* ids = D.id[cur];
+    const uint8_t* sts = D.st[cur];
+    Rec<T>* stage = reinterpret_cast<Rec<T>*>(D.stage);
     const int64_t base = (int64_t)chunk * CHUNK;
-    for (int j = threadIdx.x; j < CHUNK; j += 256) {
-        int64_t i = base + j;
-        if (i >= D.n) break;
-        uint64_t kr = D.keyrank[i];
-        uint32_t key = (uint32_t)(kr >> 32), rank = (uint32_t)kr;
-        D.perm[D.start[key] + rank] = (uint32_t)i;
+    // the chunk's four particles per thread: every load before the stores
+    constexpr int P = CHUNK / 256;
+    constexpr int RW = (int)(sizeof(Rec<T>) / 16);
+    int64_t ii[P];
+    uint32_t key[P], rank[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        ii[u] = base + u * 256 + threadIdx.x;
+        const uint64_t kr = ii[u] < n ? D.keyrank[ii[u]] : 0ull;
+        key[u] = (uint32_t)(kr >> 32);
+        rank[u] = (uint32_t)kr;
+    }
+    int64_t slot[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) slot[u] = ii[u] < n ? (int64_t)D.start[key[u]] + rank[u] : n;
+    T x[P][3], v[P][3];
+    uint32_t idv[P];
+    uint8_t stv[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        const int64_t i = ii[u] < n ? ii[u] : 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) { x[u][d] = xs[d][i]; v[u][d] = vs[d][i]; }
+        idv[u] = ids[i];
+        stv[u] = sts[i];
+    }
+    // each record through LDS, then written by RW consecutive lanes (one
+    // 16-byte word each), so a record leaves as one contiguous request
+    __shared__ Rec<T> s_out[256];
+    __shared__ int64_t s_slot[256];
+    const uint4* s_out4 = reinterpret_cast<const uint4*>(s_out);
+    uint4* stage4 = reinterpret_cast<uint4*>(stage);
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        if (u) __syncthreads();
+        rec_put(&s_out[threadIdx.x], x[u], v[u], idv[u], (uint32_t)ii[u], stv[u]);
+        s_slot[threadIdx.x] = (ii[u] < n && slot[u] < n) ? slot[u] : -1;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const int k4 = q * 256 + (int)threadIdx.x;
+            const int r = k4 / RW, part = k4 - r * RW;
+            const int64_t sl = s_slot[r];
+            if (sl >= 0) stage4[sl * RW + part] = s_out4[k4];
+        }
     }
 }
 
 // ------------------------------------------------------------- collision
 
-// Add this lane's Verlet-list flag to the count of its chunk.  The active
-// lanes of the wave hold consecutive slots o, so they span at most two
-// chunks: one atomic per chunk and wave instead of one per flagged slot.
-__device__ __forceinline__ void count_flag(uint32_t* chunk_cnt, int64_t o, bool f)
+// Add the Verlet-list flags of the wave's particles to their chunks' counts.
+// The particles of one collision group occupy slots [q0, q0 + ns) with
+// ns <= CHUNK, so they span the chunks c_lo = q0 / CHUNK and c_lo + 1 at
+// most: one atomic per chunk and wave.  All 64 lanes must call it.
+__device__ __forceinline__ void count_flag(uint32_t* chunk_cnt, int64_t o, bool f, int64_t c_lo)
 {
     const int64_t ch = o / CHUNK;
-    const int64_t c_lo = (int64_t)__builtin_amdgcn_readfirstlane((int)ch);
     const uint32_t n_lo = (uint32_t)__popcll(__ballot(f && ch == c_lo));
     const uint32_t n_hi = (uint32_t)__popcll(__ballot(f && ch != c_lo));
-    const uint64_t act = __ballot(true);
-    const int leader = __ffsll((long long)act) - 1;
-    if ((int)(threadIdx.x & 63) == leader) {
+    if ((threadIdx.x & 63) == 0) {
         if (n_lo) atomicAdd(&chunk_cnt[c_lo], n_lo);
         if (n_hi) atomicAdd(&chunk_cnt[c_lo + 1], n_hi);
     }
 }
 
-constexpr int COLL_NT = 256;
-// Particles per LDS group: 512 keeps the LDS of a collision workgroup near
-// 22 KB, so five workgroups share a compute unit (register-limited); 1024
-// held it to four (LDS-limited), 3 % slower at 128^3.
-constexpr int COLL_CAP = 512;
+// Verlet-list membership (as is_candidate) tested only against the colloids
+// of `mask`: the others were found out of reach of every particle of the
+// tile, so they cannot change the outcome.
+__device__ __forceinline__ bool is_candidate_masked(const RepDesc& D, const ColloidParams* cp, uint32_t mask,
+                                                    const double (*Xw)[3], uint8_t st,
+                                                    double x0, double x1, double x2,
+                                                    double v0, double v1, double v2)
+{
+    if (D.flow) return false;
+    if (st & 2) return true;
+    if (mask == 0) return false;
+    const double vv = dot3(v0, v1, v2, v0, v1, v2);
+    const double reach = sqrt(vv) * D.tau;
+    for (uint32_t m = mask; m; m &= m - 1) {
+        const int c = __ffs(m) - 1;
+        double dx = min_image(x0 - Xw[c][0], D.Ld[0], D.halfL[0]);
+        double dy = min_image(x1 - Xw[c][1], D.Ld[1], D.halfL[1]);
+        double dz = min_image(x2 - Xw[c][2], D.Ld[2], D.halfL[2]);
+        double r2 = dot3(dx, dy, dz, dx, dy, dz);
+        double tt = cp->reachR[c] + reach;
+        if (r2 < tt * tt) return true;
+    }
+    return false;
+}
+
 constexpr int COLL_TCMAX = 64;       // cells per tile at most
 
-// MPCD collision on one tile of cells of the shifted grid.  Cells of the
-// tile are processed in groups whose particles fit in LDS; a cell larger
-// than the group capacity is handled by a serial fallback.
-template <class T, int RULE>
-__global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
+// wave-wide max of a non-negative double (its bit pattern orders like the
+// value), folded into an LDS word by one atomic per wave
+__device__ __forceinline__ void wave_max_to(uint64_t* dst, double v)
 {
-    const int item = blockIdx.x;
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = __shfl_xor(b, m, 64);
+        b = o > b ? o : b;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)dst, (unsigned long long)b);
+}
+
+__device__ __forceinline__ void wave_min_to(uint64_t* dst, double v)
+{
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = __shfl_xor(b, m, 64);
+        b = o < b ? o : b;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMin((unsigned long long*)dst, (unsigned long long)b);
+}
+
+// One cell of the tile holding more particles than a collision group (rare:
+// hundreds of particles in one cell).  Its records are contiguous in the
+// staging array; the stable order is found by counting ranks of the old
+// indices into scratch (the key/rank array is dead after the scatter), then
+// the per-cell quantities by one thread in that order, then every particle.
+template <class T, int RULE, int NT>
+__device__ void collide_big_cell(const RepDesc& D, const ColloidParams* cp, int nc, const double (*s_Xw)[3],
+                                 int64_t coll, int64_t cell, uint32_t q0, int nn,
+                                 double* s_u, double* s_n, int32_t* s_flip,
+                                 double& t_sum, double& t_cells, double& du_sum, double& n_flip)
+{
+    RepState* rs = D.rs;
+    const int t = threadIdx.x;
+    const int64_t n = D.n;
+    const int cur = (int)(coll & 1), nxt = cur ^ 1;
+    T* xn[3] = {comp<T>(D.x[nxt], n, 0), comp<T>(D.x[nxt], n, 1), comp<T>(D.x[nxt], n, 2)};
+    T* vn[3] = {comp<T>(D.v[nxt], n, 0), comp<T>(D.v[nxt], n, 1), comp<T>(D.v[nxt], n, 2)};
+    uint32_t* idn = D.id[nxt];
+    uint8_t* stn = D.st[nxt];
+    const Rec<T>* rec = reinterpret_cast<const Rec<T>*>(D.stage) + q0;
+    const double ca = D.ca, sa = D.sa, oma = 1.0 - D.ca;
+    uint32_t* srt = reinterpret_cast<uint32_t*>(D.keyrank) + q0;   // stable rank -> record
+    for (int j = t; j < nn; j += NT) {
+        const uint32_t pj = rec_idx(&rec[j]);
+        int r = 0;
+        for (int q = 0; q < nn; ++q) r += rec_idx(&rec[q]) < pj ? 1 : 0;
+        srt[r] = (uint32_t)j;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double S0 = 0.0, S1 = 0.0, S2 = 0.0;
+        for (int k = 0; k < nn; ++k) {
+            const Rec<T>* q = &rec[srt[k] < (uint32_t)nn ? srt[k] : 0u];
+            S0 = S0 + rec_v(q, 0);
+            S1 = S1 + rec_v(q, 1);
+            S2 = S2 + rec_v(q, 2);
+        }
+        const double u0 = S0 / (double)nn, u1 = S1 / (double)nn, u2 = S2 / (double)nn;
+        double tsum = 0.0, G0 = 0.0, G1 = 0.0, G2 = 0.0;
+        int nB = 0;
+        for (int k = 0; k < nn; ++k) {
+            const Rec<T>* q = &rec[srt[k] < (uint32_t)nn ? srt[k] : 0u];
+            double w0 = rec_v(q, 0) - u0, w1 = rec_v(q, 1) - u1, w2 = rec_v(q, 2) - u2;
+            tsum = tsum + dot3(w0, w1, w2, w0, w1, w2);
+            nB += rec_st(q) & 1;
+            if constexpr (RULE == 1) {
+                uint64_t wv[4]; double z[3];
+                philox((uint64_t)coll, rec_id(q), 0, D.seed, TAG_THERMO, wv);
+                normals3(wv, z);
+                G0 = G0 + (D.vscale * z[0]);
+                G1 = G1 + (D.vscale * z[1]);
+                G2 = G2 + (D.vscale * z[2]);
+            }
+        }
+        t_sum += (D.mass * tsum) / (double)(nn - 1);
+        t_cells += 1.0;
+        if (!(isfinite(u0) && isfinite(u1) && isfinite(u2))) atomicOr(&rs->flags, RMP_FLAG_NONFINITE);
+        s_u[0] = u0; s_u[1] = u1; s_u[2] = u2;
+        if constexpr (RULE == 1) {
+            s_n[0] = G0 / (double)nn; s_n[1] = G1 / (double)nn; s_n[2] = G2 / (double)nn;
+        }
+        int flipk = -1;
+        if (D.bulk_on && nB > 0) {
+            uint64_t wv[4];
+            philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
+            double P = D.ptable[nB < RMP_PTABLE ? nB : RMP_PTABLE - 1];
+            if (u01(wv[0]) < P) {
+                int jb = (int)(u01(wv[1]) * (double)nB);
+                if (jb >= nB) jb = nB - 1;
+                for (int k = 0; k < nn; ++k)
+                    if (rec_st(&rec[srt[k] < (uint32_t)nn ? srt[k] : 0u]) & 1) {
+                        if (jb == 0) { flipk = k; break; }
+                        jb--;
+                    }
+            }
+        }
+        *s_flip = flipk;
+    }
+    __syncthreads();
+    const double u0 = s_u[0], u1 = s_u[1], u2 = s_u[2];
+    const int flipk = *s_flip;
+    for (int k0 = 0; k0 < nn; k0 += NT) {
+        const int k = k0 + t;
+        bool cnd = false;
+        const int64_t o = (int64_t)q0 + k;
+        if (k < nn) {
+            T xt[3], vq[3]; uint32_t idq, pq; uint8_t s;
+            rec_get(&rec[srt[k] < (uint32_t)nn ? srt[k] : 0u], xt, vq, idq, pq, s);
+            const double vv0 = (double)vq[0], vv1 = (double)vq[1], vv2 = (double)vq[2];
+            double v3[3];
+            if constexpr (RULE == 0) {
+                const double nax[3] = {s_n[0], s_n[1], s_n[2]};
+                double rw[3];
+                rotate(nax, ca, sa, oma, vv0 - u0, vv1 - u1, vv2 - u2, rw);
+                v3[0] = u0 + rw[0]; v3[1] = u1 + rw[1]; v3[2] = u2 + rw[2];
+            } else {
+                uint64_t wv[4]; double z[3];
+                philox((uint64_t)coll, idq, 0, D.seed, TAG_THERMO, wv);
+                normals3(wv, z);
+                v3[0] = u0 + ((D.vscale * z[0]) - s_n[0]);
+                v3[1] = u1 + ((D.vscale * z[1]) - s_n[1]);
+                v3[2] = u2 + ((D.vscale * z[2]) - s_n[2]);
+            }
+            if (k == flipk) {
+                du_sum += species_dU(D, cp, nc, s_Xw, (double)xt[0], (double)xt[1], (double)xt[2], 1, 0);
+                n_flip += 1.0;
+                s = 0;
+            }
+            const T vt[3] = {(T)v3[0], (T)v3[1], (T)v3[2]};
+            for (int d = 0; d < 3; ++d) { xn[d][o] = xt[d]; vn[d][o] = vt[d]; }
+            idn[o] = idq;
+            stn[o] = s;
+            cnd = is_candidate(D, cp, nc, s_Xw, s, (double)xt[0], (double)xt[1], (double)xt[2],
+                               (double)vt[0], (double)vt[1], (double)vt[2]);
+            D.cflag[o] = cnd ? 1 : 0;
+        }
+        // the wave's slots lie in [q0 + k0, q0 + k0 + NT): at most two chunks
+        count_flag(D.chunk_cnt, o, cnd, ((int64_t)q0 + k0) / CHUNK);
+    }
+    __syncthreads();
+}
+
+// MPCD collision on one tile of cells of the shifted grid (sort ranks
+// [c0, c0 + TC)).  The scatter has put the tile's particles in the
+// contiguous slots [start[c0], start[c0 + TC)) of the staging array, cell
+// by cell (in scatter order within a cell).  The tile's cells are taken in
+// groups whose particles fit the workgroup (NT threads holding PPT particles
+// each); usually the whole tile is one group.  Per group:
+//   B  each thread reads whole records of the group's slots (coalesced) and
+//      finds each slot's cell by binary search over the cell starts;
+//   C  it ranks its particle by old index among its cell's records (the
+//      stable order), writes position and id to the output slot of that
+//      rank, velocity and species to LDS at that slot for the per-cell sums;
+//   D  one thread per cell: sequential FP64 sums in the stable order,
+//      centre-of-mass velocity, temperature term, bulk reaction decision;
+//      one lane per colloid: is the colloid within reach of any particle of
+//      the tile (bounding box of the tile's particles, largest speed)?
+//   E  each thread rotates its particles about their cell's axis, applies
+//      the reaction, and writes velocity, species and Verlet-list flag.
+// The random axes and bulk-reaction uniforms of all cells of the tile are
+// drawn at tile start (they depend on nothing loaded), next to the loads.
+// The register file is held to 96 VGPRs with one particle per thread (five
+// waves per SIMD) and to 128 with two (four waves); a few bytes of values
+// spill in FP64.
+template <class T, int RULE, int NT, int PPT>
+__global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xcd_map)
+{
+    constexpr int CAP = NT * PPT;
+    static_assert(CAP <= CHUNK, "a collision group spans at most two chunks");
+    static_assert(NT >= 256, "the tile-start draws use the last two waves");
+    int item = blockIdx.x;
+    if (xcd_map && (gridDim.x & 7) == 0) {
+        // workgroups are dealt to the eight XCDs in turn: give each XCD a
+        // contiguous range of tiles so that neighbouring tiles, which gather
+        // from the same source lines, share an L2
+        const int per = (int)(gridDim.x >> 3);
+        item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    }
     const int rep = find_rep(w.prefix, w.nrep, item);
     const int tile = item - w.prefix[rep];
     const RepDesc& D = w.desc[rep];
@@ -1858,246 +2410,234 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
     const ColloidParams* cp = D.cp;
     const int nc = cp->nc;
     const int t = threadIdx.x;
+    const int lane = t & 63;
 
     __shared__ uint32_t s_start[COLL_TCMAX + 1];
-    __shared__ uint32_t s_perm[COLL_CAP], s_src[COLL_CAP];
-    __shared__ double s_v[3][COLL_CAP];
-    __shared__ double s_g[3][RULE ? COLL_CAP : 1];
-    __shared__ uint8_t s_st[COLL_CAP];
-    __shared__ uint8_t s_cell[COLL_CAP];
+    __shared__ uint32_t s_perm[CAP];
+    __shared__ T s_v[3][CAP];
+    __shared__ double s_g[3][RULE ? CAP : 1];
+    __shared__ uint8_t s_st[CAP];
     __shared__ double s_u[COLL_TCMAX][3], s_n[COLL_TCMAX][3];
-    __shared__ int32_t s_flip[COLL_TCMAX], s_nn[COLL_TCMAX];
+    __shared__ double s_b[COLL_TCMAX][2];       // bulk-reaction uniforms
+    __shared__ double s_z[COLL_TCMAX][3];       // virtual-momentum normal of a plate-layer cell
+    __shared__ int32_t s_flip[COLL_TCMAX];
     __shared__ uint8_t s_go[COLL_TCMAX];
     __shared__ double s_Xw[MAXC][3];
-    __shared__ int32_t s_group[2];
-    __shared__ double sred[COLL_NT / 64 + 1];
+    __shared__ uint64_t s_box[7];      // min, max of the offsets from s_ref (+ L, so positive);
+                                       // max |v|^2 (bit patterns order like the values)
+    __shared__ double s_ref[3];        // a particle of the tile: reference point of the box
+    __shared__ int32_t s_ref_set;
+    __shared__ uint32_t s_cmask;
+    __shared__ double sred[(NT / 64 + 1) * 4];
 
     const int64_t coll = rs->coll_step;
-    const int cur = (int)(coll & 1), nxt = cur ^ 1;
+    const int nxt = (int)(coll & 1) ^ 1;
     const int64_t n = D.n;
     const int TC = D.tile_cells;
     const int64_t c0 = (int64_t)tile * TC;
     const int64_t c1 = (c0 + TC < D.ncell) ? c0 + TC : D.ncell;
     const int ncl = (int)(c1 - c0);
-    for (int k = t; k <= ncl; k += COLL_NT) {
+    // the colloid cull needs a bound on the speed after the collision:
+    // the rotation gives one (below), the thermostat's fresh draws do not
+    const bool cull = RULE == 0 && nc > 0 && !D.flow;
+
+    // ---- A: cell starts (and the counters zeroed for the next binning);
+    //         per-cell random draws; colloid images
+    for (int k = t; k <= ncl; k += NT) {
         s_start[k] = D.start[c0 + k];
-        // the cell counters are read by the scans; zero them for the next
-        // interval's binning (every cell lies in exactly one tile)
         if (k < ncl) D.count[c0 + k] = 0;
     }
-    if (t < nc)
-        for (int d = 0; d < 3; ++d) s_Xw[t][d] = colloid_image(rs->X[t][d], D.Ld[d]);
+    if (t >= NT - 128 && t < NT - 64) {
+        if constexpr (RULE == 0) {
+            for (int lc = t - (NT - 128); lc < ncl; lc += 64) {
+                const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : D.cell_of[c0 + lc];
+                double nax[3];
+                marsaglia_axis(D.seed, (uint64_t)coll, (uint64_t)cell, nax);
+                s_n[lc][0] = nax[0]; s_n[lc][1] = nax[1]; s_n[lc][2] = nax[2];
+            }
+        }
+    } else if (t >= NT - 64) {
+        if (D.bulk_on)
+            for (int lc = t - (NT - 64); lc < ncl; lc += 64) {
+                const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : D.cell_of[c0 + lc];
+                uint64_t wv[4];
+                philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
+                s_b[lc][0] = u01(wv[0]);
+                s_b[lc][1] = u01(wv[1]);
+            }
+    } else if (t >= 64 && t < 128) {
+        if (D.walls) {
+            // plates (flows have no colloids): the virtual-momentum normal of
+            // every cell of the first and last layer, used if the cell turns
+            // out to be cut and under-filled
+            for (int lc = t - 64; lc < ncl; lc += 64) {
+                const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : D.cell_of[c0 + lc];
+                const int64_t cz = cell / ((int64_t)D.L[0] * D.L[1]);
+                if (cz == 0 || cz == D.L[2] - 1) {
+                    uint64_t wv[4]; double z[3];
+                    philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_VIRT, wv);
+                    normals3(wv, z);
+                    s_z[lc][0] = z[0]; s_z[lc][1] = z[1]; s_z[lc][2] = z[2];
+                }
+            }
+        } else if (t < 64 + nc) {
+            for (int d = 0; d < 3; ++d) s_Xw[t - 64][d] = colloid_image(rs->X[t - 64][d], D.Ld[d]);
+        }
+    }
+    if (t < 3) { s_box[t] = ~0ull; s_box[3 + t] = 0ull; }
+    if (t == 3) { s_box[6] = 0ull; s_cmask = 0u; s_ref_set = 0; }
     __syncthreads();
 
-    const T* xo[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
-    const T* vo[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
+    const Rec<T>* stage = reinterpret_cast<const Rec<T>*>(D.stage);
     T* xn[3] = {comp<T>(D.x[nxt], n, 0), comp<T>(D.x[nxt], n, 1), comp<T>(D.x[nxt], n, 2)};
     T* vn[3] = {comp<T>(D.v[nxt], n, 0), comp<T>(D.v[nxt], n, 1), comp<T>(D.v[nxt], n, 2)};
-    const uint32_t* ido = D.id[cur];
-    const uint8_t* sto = D.st[cur];
     uint32_t* idn = D.id[nxt];
     uint8_t* stn = D.st[nxt];
     const double ca = D.ca, sa = D.sa, oma = 1.0 - D.ca;
 
     double t_sum = 0.0, t_cells = 0.0, du_sum = 0.0, n_flip = 0.0;
+    uint64_t big = 0;          // tile-local cells left to k_collide_big (uniform)
     int ga = 0;
     while (ga < ncl) {
-        if (t == 0) {
-            int gb = ga + 1;
-            while (gb < ncl && s_start[gb + 1] - s_start[ga] <= (uint32_t)COLL_CAP) gb++;
-            s_group[0] = gb;
+        int gb;
+        if (s_start[ncl] - s_start[ga] <= (uint32_t)CAP) {
+            gb = ncl;
+        } else {
+            // the longest run of cells from ga whose particles fit (at least one cell)
+            const int k = ga + 1 + t;
+            const bool ok = k <= ncl && s_start[k] - s_start[ga] <= (uint32_t)CAP;
+            const int cnt = __syncthreads_count(ok);
+            gb = ga + (cnt > 0 ? cnt : 1);
         }
-        __syncthreads();
-        const int gb = s_group[0];
         const uint32_t q0 = s_start[ga], q1 = s_start[gb];
         const int ns = (int)(q1 - q0);
-        if (ns > COLL_CAP) {
-            // One cell larger than an LDS group (the group is this cell
-            // alone).  Stable order by counting ranks into scratch: the
-            // key/rank array is dead after the scatter and is reused here.
-            const int64_t cell = D.hbits == KEY_ROW ? c0 + ga : D.cell_of[c0 + ga];   // tiles run over sort ranks
-            const int nn = ns;
-            uint32_t* srt = reinterpret_cast<uint32_t*>(D.keyrank);
-            for (int j = t; j < nn; j += COLL_NT) {
-                const uint32_t p = D.perm[q0 + j];
-                int r = 0;
-                for (int q = 0; q < nn; ++q) r += D.perm[q0 + q] < p ? 1 : 0;
-                srt[q0 + r] = p < (uint32_t)n ? p : 0u;
-            }
-            __syncthreads();
-            // ordered per-cell quantities by one thread (FP64, stable order)
-            if (t == 0) {
-                double S0 = 0.0, S1 = 0.0, S2 = 0.0;
-                for (int k = 0; k < nn; ++k) {
-                    const uint32_t p = srt[q0 + k] < (uint32_t)n ? srt[q0 + k] : 0u;
-                    S0 = S0 + (double)vo[0][p];
-                    S1 = S1 + (double)vo[1][p];
-                    S2 = S2 + (double)vo[2][p];
-                }
-                const double u0 = S0 / (double)nn, u1 = S1 / (double)nn, u2 = S2 / (double)nn;
-                double tsum = 0.0, G0 = 0.0, G1 = 0.0, G2 = 0.0;
-                int nB = 0;
-                for (int k = 0; k < nn; ++k) {
-                    const uint32_t p = srt[q0 + k] < (uint32_t)n ? srt[q0 + k] : 0u;
-                    double w0 = (double)vo[0][p] - u0, w1 = (double)vo[1][p] - u1,
-                           w2 = (double)vo[2][p] - u2;
-                    tsum = tsum + dot3(w0, w1, w2, w0, w1, w2);
-                    nB += sto[p] & 1;
-                    if constexpr (RULE == 1) {
-                        uint64_t wv[4]; double z[3];
-                        philox((uint64_t)coll, ido[p], 0, D.seed, TAG_THERMO, wv);
-                        normals3(wv, z);
-                        G0 = G0 + (D.vscale * z[0]);
-                        G1 = G1 + (D.vscale * z[1]);
-                        G2 = G2 + (D.vscale * z[2]);
-                    }
-                }
-                t_sum += (D.mass * tsum) / (double)(nn - 1);
-                t_cells += 1.0;
-                if (!(isfinite(u0) && isfinite(u1) && isfinite(u2))) atomicOr(&rs->flags, RMP_FLAG_NONFINITE);
-                s_u[0][0] = u0; s_u[0][1] = u1; s_u[0][2] = u2;
-                if constexpr (RULE == 0) {
-                    double nax[3];
-                    marsaglia_axis(D.seed, (uint64_t)coll, (uint64_t)cell, nax);
-                    s_n[0][0] = nax[0]; s_n[0][1] = nax[1]; s_n[0][2] = nax[2];
-                } else {
-                    s_n[0][0] = G0 / (double)nn; s_n[0][1] = G1 / (double)nn; s_n[0][2] = G2 / (double)nn;
-                }
-                int flipk = -1;
-                if (D.bulk_on && nB > 0) {
-                    uint64_t wv[4];
-                    philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
-                    double P = D.ptable[nB < RMP_PTABLE ? nB : RMP_PTABLE - 1];
-                    if (u01(wv[0]) < P) {
-                        int jb = (int)(u01(wv[1]) * (double)nB);
-                        if (jb >= nB) jb = nB - 1;
-                        for (int k = 0; k < nn; ++k)
-                            if (sto[srt[q0 + k] < (uint32_t)n ? srt[q0 + k] : 0u] & 1) {
-                                if (jb == 0) { flipk = k; break; }
-                                jb--;
-                            }
-                    }
-                }
-                s_flip[0] = flipk;
-            }
-            __syncthreads();
-            const double u0 = s_u[0][0], u1 = s_u[0][1], u2 = s_u[0][2];
-            for (int k = t; k < nn; k += COLL_NT) {
-                const uint32_t p = srt[q0 + k] < (uint32_t)n ? srt[q0 + k] : 0u;
-                const double vv0 = (double)vo[0][p], vv1 = (double)vo[1][p], vv2 = (double)vo[2][p];
-                double v3[3];
-                if constexpr (RULE == 0) {
-                    const double nax[3] = {s_n[0][0], s_n[0][1], s_n[0][2]};
-                    double rw[3];
-                    rotate(nax, ca, sa, oma, vv0 - u0, vv1 - u1, vv2 - u2, rw);
-                    v3[0] = u0 + rw[0]; v3[1] = u1 + rw[1]; v3[2] = u2 + rw[2];
-                } else {
-                    uint64_t wv[4]; double z[3];
-                    philox((uint64_t)coll, ido[p], 0, D.seed, TAG_THERMO, wv);
-                    normals3(wv, z);
-                    v3[0] = u0 + ((D.vscale * z[0]) - s_n[0][0]);
-                    v3[1] = u1 + ((D.vscale * z[1]) - s_n[0][1]);
-                    v3[2] = u2 + ((D.vscale * z[2]) - s_n[0][2]);
-                }
-                uint8_t s = sto[p];
-                const T xt[3] = {xo[0][p], xo[1][p], xo[2][p]};
-                if (k == s_flip[0]) {
-                    du_sum += species_dU(D, cp, nc, s_Xw, (double)xt[0], (double)xt[1], (double)xt[2], 1, 0);
-                    n_flip += 1.0;
-                    s = 0;
-                }
-                const int64_t o = (int64_t)q0 + k;
-                const T vt[3] = {(T)v3[0], (T)v3[1], (T)v3[2]};
-                for (int d = 0; d < 3; ++d) { xn[d][o] = xt[d]; vn[d][o] = vt[d]; }
-                idn[o] = ido[p];
-                stn[o] = s;
-                bool cnd = is_candidate(D, cp, nc, s_Xw, s, (double)xt[0], (double)xt[1], (double)xt[2],
-                                        (double)vt[0], (double)vt[1], (double)vt[2]);
-                D.cflag[o] = cnd ? 1 : 0;
-                count_flag(D.chunk_cnt, o, cnd);
-            }
-            __syncthreads();
+        if (ns > CAP) {
+            // one cell beyond a group's capacity: left to k_collide_big
+            big |= 1ull << ga;
             ga = gb;
             continue;
         }
-        // 1. permutation entries and local cell of each slot
-        for (int j = t; j < ns; j += COLL_NT) {
-            s_perm[j] = D.perm[q0 + j];
-            const uint32_t q = q0 + j;
-            int lo = ga, hi = gb - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (s_start[mid] <= q) lo = mid; else hi = mid - 1;
-            }
-            s_cell[j] = (uint8_t)(lo - ga);
-        }
-        __syncthreads();
-        // 2. stable order inside each cell: rank by old index
-        for (int j = t; j < ns; j += COLL_NT) {
-            const int cl = ga + s_cell[j];
-            const int cb = (int)(s_start[cl] - q0), ce = (int)(s_start[cl + 1] - q0);
-            const uint32_t p = s_perm[j];
-            int r = 0;
-            for (int q = cb; q < ce; ++q) r += s_perm[q] < p ? 1 : 0;
-            s_src[cb + r] = p;
-        }
-        __syncthreads();
-        // 3. gather velocities and species in the stable order
-        for (int j = t; j < ns; j += COLL_NT) {
-            uint32_t p = s_src[j];
-            if (p >= (uint32_t)n) { p = 0; s_src[j] = 0; }   // memory safety only
-            s_v[0][j] = (double)vo[0][p];
-            s_v[1][j] = (double)vo[1][p];
-            s_v[2][j] = (double)vo[2][p];
-            s_st[j] = sto[p];
-            if constexpr (RULE == 1) {
-                uint64_t wv[4]; double z[3];
-                philox((uint64_t)coll, ido[p], 0, D.seed, TAG_THERMO, wv);
-                normals3(wv, z);
-                s_g[0][j] = D.vscale * z[0];
-                s_g[1][j] = D.vscale * z[1];
-                s_g[2][j] = D.vscale * z[2];
+        // ---- B: records of the group's slots, cell of each slot
+        T xr[PPT][3], vq[PPT][3];
+        uint32_t idq[PPT], pj[PPT];
+        uint8_t sr[PPT];
+        int lcj[PPT];
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int j = t + u * NT;
+            lcj[u] = ga;
+            pj[u] = 0u;
+            sr[u] = 0;
+            if (j < ns) {
+                rec_get(&stage[q0 + j], xr[u], vq[u], idq[u], pj[u], sr[u]);
+                s_perm[j] = pj[u];
+                if (j == 0 && !s_ref_set) {     // the first group of the tile fixes it
+                    for (int d = 0; d < 3; ++d) s_ref[d] = (double)xr[u][d];
+                    s_ref_set = 1;
+                }
+                const uint32_t q = q0 + (uint32_t)j;
+                int lo = ga, hi = gb - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_start[mid] <= q) lo = mid; else hi = mid - 1;
+                }
+                lcj[u] = lo;
             }
         }
         __syncthreads();
-        // 4. per cell: centre-of-mass velocity (sequential FP64 sum in the
-        //    stable order), temperature term, axis, bulk reaction
-        for (int lc = t; lc < gb - ga; lc += COLL_NT) {
-            const int cl = ga + lc;
-            const int64_t cell = D.hbits == KEY_ROW ? c0 + cl : D.cell_of[c0 + cl];   // cell of this sort rank
+        // ---- C: stable rank; position and id written at the rank's slot
+        int slot[PPT];
+        double gmin[3] = {1e300, 1e300, 1e300}, gmax[3] = {0.0, 0.0, 0.0}, gv2 = 0.0;
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int j = t + u * NT;
+            slot[u] = -1;
+            if (j < ns) {
+                const int cb = (int)(s_start[lcj[u]] - q0), ce = (int)(s_start[lcj[u] + 1] - q0);
+                const uint32_t p = pj[u];
+                int r = 0;
+                for (int q = cb; q < ce; ++q) r += s_perm[q] < p ? 1 : 0;
+                const int sl = cb + r;
+                slot[u] = sl;
+                const int64_t o = (int64_t)q0 + sl;
+                const T (&xr_)[3] = xr[u];
+                const T (&vq_)[3] = vq[u];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) { xn[d][o] = xr_[d]; s_v[d][sl] = vq_[d]; }
+                idn[o] = idq[u];
+                s_st[sl] = sr[u];
+                if constexpr (RULE == 1) {
+                    uint64_t wv[4]; double z[3];
+                    philox((uint64_t)coll, idq[u], 0, D.seed, TAG_THERMO, wv);
+                    normals3(wv, z);
+                    s_g[0][sl] = D.vscale * z[0];
+                    s_g[1][sl] = D.vscale * z[1];
+                    s_g[2][sl] = D.vscale * z[2];
+                }
+                if (cull) {
+                    // the bounding box of the tile's particles (minimum-image
+                    // offsets from a particle of the tile, shifted by L to be
+                    // positive) and their largest speed vmax, for the colloid
+                    // cull: after the rotation a speed is at most
+                    // |u| + |v - u| <= 3 vmax
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double xd = min_image((double)xr_[d] - s_ref[d], D.Ld[d], D.halfL[d]) + D.Ld[d];
+                        gmin[d] = xd < gmin[d] ? xd : gmin[d];
+                        gmax[d] = xd > gmax[d] ? xd : gmax[d];
+                    }
+                    const double vv = dot3((double)vq_[0], (double)vq_[1], (double)vq_[2],
+                                           (double)vq_[0], (double)vq_[1], (double)vq_[2]);
+                    gv2 = vv > gv2 ? vv : gv2;
+                    if (!(vv <= 1e300)) gv2 = 1e300;          // inf or NaN: no cull
+                }
+            }
+        }
+        if (cull) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                wave_min_to(&s_box[d], gmin[d]);
+                wave_max_to(&s_box[3 + d], gmax[d]);
+            }
+            wave_max_to(&s_box[6], gv2);
+        }
+        __syncthreads();
+        // ---- D: per cell (one thread each); colloid cull (second wave)
+        for (int cl = ga + t; cl < gb; cl += NT) {
+            const int64_t cell = D.hbits == KEY_ROW ? c0 + cl : D.cell_of[c0 + cl];
             const int cb = (int)(s_start[cl] - q0), ce = (int)(s_start[cl + 1] - q0);
             const int nn = ce - cb;
-            s_nn[lc] = nn;
-            s_flip[lc] = -1;
+            s_flip[cl] = -1;
             // Lamura et al. (2001): a cell of the first or last layer (cut by
             // a plate) with fewer than n0 particles holds n0 - n virtual ones
             // at rest on average; only their summed momentum enters, a normal
             // vector of variance (n0 - n) kT / m per component
             const int64_t cz = cell / ((int64_t)D.L[0] * D.L[1]);
             const bool virt = D.walls && (cz == 0 || cz == D.L[2] - 1) && nn >= 1 && nn < D.wall_n0;
-            s_go[lc] = (nn >= 2 || virt) ? 1 : 0;
-            if (nn >= 2 || virt) {
+            const bool go = nn >= 2 || virt;
+            s_go[cl] = go ? 1 : 0;
+            int nB = 0;
+            if (go) {
                 double S0 = 0.0, S1 = 0.0, S2 = 0.0;
                 for (int q = cb; q < ce; ++q) {
-                    S0 = S0 + s_v[0][q];
-                    S1 = S1 + s_v[1][q];
-                    S2 = S2 + s_v[2][q];
+                    S0 = S0 + (double)s_v[0][q];
+                    S1 = S1 + (double)s_v[1][q];
+                    S2 = S2 + (double)s_v[2][q];
+                    nB += s_st[q] & 1;
                 }
                 double u0, u1, u2;
                 if (virt) {
-                    uint64_t wv[4]; double z[3];
-                    philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_VIRT, wv);
-                    normals3(wv, z);
                     const double sd = sqrt((double)(D.wall_n0 - nn)) * D.vscale;
                     const double n0 = (double)D.wall_n0;
-                    u0 = (S0 + (sd * z[0])) / n0;
-                    u1 = (S1 + (sd * z[1])) / n0;
-                    u2 = (S2 + (sd * z[2])) / n0;
+                    u0 = (S0 + (sd * s_z[cl][0])) / n0;
+                    u1 = (S1 + (sd * s_z[cl][1])) / n0;
+                    u2 = (S2 + (sd * s_z[cl][2])) / n0;
                 } else {
                     u0 = S0 / (double)nn; u1 = S1 / (double)nn; u2 = S2 / (double)nn;
                     double tsum = 0.0;
                     for (int q = cb; q < ce; ++q) {
-                        double w0 = s_v[0][q] - u0, w1 = s_v[1][q] - u1, w2 = s_v[2][q] - u2;
+                        const double w0 = (double)s_v[0][q] - u0, w1 = (double)s_v[1][q] - u1,
+                                     w2 = (double)s_v[2][q] - u2;
                         tsum = tsum + dot3(w0, w1, w2, w0, w1, w2);
                     }
                     t_sum += (D.mass * tsum) / (double)(nn - 1);
@@ -2106,88 +2646,191 @@ __global__ __launch_bounds__(COLL_NT) void k_collide(Work w)
                 // a non-finite centre-of-mass velocity would spread through
                 // its cell: latched for the caller
                 if (!(isfinite(u0) && isfinite(u1) && isfinite(u2))) atomicOr(&rs->flags, RMP_FLAG_NONFINITE);
-                s_u[lc][0] = u0; s_u[lc][1] = u1; s_u[lc][2] = u2;
-                if constexpr (RULE == 0) {
-                    double nax[3];
-                    marsaglia_axis(D.seed, (uint64_t)coll, (uint64_t)cell, nax);
-                    s_n[lc][0] = nax[0]; s_n[lc][1] = nax[1]; s_n[lc][2] = nax[2];
-                } else {
+                s_u[cl][0] = u0; s_u[cl][1] = u1; s_u[cl][2] = u2;
+                if constexpr (RULE == 1) {
                     double G0 = 0.0, G1 = 0.0, G2 = 0.0;
                     for (int q = cb; q < ce; ++q) {
                         G0 = G0 + s_g[0][q];
                         G1 = G1 + s_g[1][q];
                         G2 = G2 + s_g[2][q];
                     }
-                    s_n[lc][0] = G0 / (double)nn; s_n[lc][1] = G1 / (double)nn; s_n[lc][2] = G2 / (double)nn;
+                    s_n[cl][0] = G0 / (double)nn; s_n[cl][1] = G1 / (double)nn; s_n[cl][2] = G2 / (double)nn;
+                }
+            } else if (nn == 1) {
+                nB = s_st[cb] & 1;
+            }
+            if (D.bulk_on && nB > 0) {
+                const double P = D.ptable[nB < RMP_PTABLE ? nB : RMP_PTABLE - 1];
+                if (s_b[cl][0] < P) {
+                    int jb = (int)(s_b[cl][1] * (double)nB);
+                    if (jb >= nB) jb = nB - 1;
+                    for (int q = cb; q < ce; ++q)
+                        if (s_st[q] & 1) {
+                            if (jb == 0) { s_flip[cl] = q; break; }
+                            jb--;
+                        }
                 }
             }
-            if (D.bulk_on && nn > 0) {
-                int nB = 0;
-                for (int q = cb; q < ce; ++q) nB += s_st[q] & 1;
-                if (nB > 0) {
-                    uint64_t wv[4];
-                    philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
-                    double P = D.ptable[nB < RMP_PTABLE ? nB : RMP_PTABLE - 1];
-                    if (u01(wv[0]) < P) {
-                        int jb = (int)(u01(wv[1]) * (double)nB);
-                        if (jb >= nB) jb = nB - 1;
-                        for (int q = cb; q < ce; ++q)
-                            if (s_st[q] & 1) {
-                                if (jb == 0) { s_flip[lc] = q; break; }
-                                jb--;
-                            }
+        }
+        if (cull && t >= 64 && t < 128) {
+            // colloid c can reach a particle of the tile only if its reach
+            // sphere, widened by the largest speed times tau, meets the
+            // particles' bounding box (minimum image per axis, margin far
+            // above rounding)
+            bool near = false;
+            const int c = t - 64;
+            if (c < nc) {
+                const double vmax2 = __longlong_as_double((long long)s_box[6]);
+                const double reach = ((3.0 * sqrt(vmax2)) * D.tau + cp->reachR[c]) * (1.0 + 1e-6) + 1e-6;
+                double r2 = 0.0;
+                bool wide = !(reach < 1e200);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    // box [lo, hi] of offsets from s_ref; the colloid's offset
+                    // and its periodic images: the nearest one counts
+                    const double lo = __longlong_as_double((long long)s_box[d]) - D.Ld[d];
+                    const double hi = __longlong_as_double((long long)s_box[3 + d]) - D.Ld[d];
+                    if (!(hi - lo < 0.5 * D.Ld[d])) { wide = true; continue; }
+                    const double oc = min_image(s_Xw[c][d] - s_ref[d], D.Ld[d], D.halfL[d]);
+                    double dd = 1e300;
+#pragma unroll
+                    for (int img = -1; img <= 1; ++img) {
+                        const double ci = oc + (double)img * D.Ld[d];
+                        double e = lo - ci > ci - hi ? lo - ci : ci - hi;
+                        e = e > 0.0 ? e : 0.0;
+                        dd = e < dd ? e : dd;
+                    }
+                    r2 += dd * dd;
+                }
+                near = wide || r2 < reach * reach;
+            }
+            const uint64_t m = __ballot(near);
+            if (lane == 0) s_cmask = (uint32_t)m;
+        }
+        __syncthreads();
+        // ---- E: rotate (or thermostat), react, write, Verlet-list flag
+        // without the cull every colloid is tested
+        const uint32_t cmask = cull ? s_cmask : (nc >= 32 ? 0xffffffffu : ((1u << nc) - 1u));
+        const int64_t c_lo = (int64_t)q0 / CHUNK;
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            bool cnd = false;
+            int64_t o = (int64_t)q0;
+            if (slot[u] >= 0) {
+                const int cl = lcj[u];
+                double v3[3] = {(double)s_v[0][slot[u]], (double)s_v[1][slot[u]], (double)s_v[2][slot[u]]};
+                if (s_go[cl]) {
+                    const double u0 = s_u[cl][0], u1 = s_u[cl][1], u2 = s_u[cl][2];
+                    if constexpr (RULE == 0) {
+                        const double nax[3] = {s_n[cl][0], s_n[cl][1], s_n[cl][2]};
+                        double rw[3];
+                        rotate(nax, ca, sa, oma, v3[0] - u0, v3[1] - u1, v3[2] - u2, rw);
+                        v3[0] = u0 + rw[0]; v3[1] = u1 + rw[1]; v3[2] = u2 + rw[2];
+                    } else {
+                        v3[0] = u0 + (s_g[0][slot[u]] - s_n[cl][0]);
+                        v3[1] = u1 + (s_g[1][slot[u]] - s_n[cl][1]);
+                        v3[2] = u2 + (s_g[2][slot[u]] - s_n[cl][2]);
                     }
                 }
-            }
-        }
-        __syncthreads();
-        // 5. rotate, react, flag for the next Verlet list, write in cell order
-        for (int j = t; j < ns; j += COLL_NT) {
-            const int lc = s_cell[j];
-            const uint32_t p = s_src[j];
-            double v3[3] = {s_v[0][j], s_v[1][j], s_v[2][j]};
-            if (s_go[lc]) {
-                const double u0 = s_u[lc][0], u1 = s_u[lc][1], u2 = s_u[lc][2];
-                if constexpr (RULE == 0) {
-                    const double nax[3] = {s_n[lc][0], s_n[lc][1], s_n[lc][2]};
-                    double rw[3];
-                    rotate(nax, ca, sa, oma, v3[0] - u0, v3[1] - u1, v3[2] - u2, rw);
-                    v3[0] = u0 + rw[0]; v3[1] = u1 + rw[1]; v3[2] = u2 + rw[2];
-                } else {
-                    v3[0] = u0 + (s_g[0][j] - s_n[lc][0]);
-                    v3[1] = u1 + (s_g[1][j] - s_n[lc][1]);
-                    v3[2] = u2 + (s_g[2][j] - s_n[lc][2]);
+                uint8_t s = sr[u];
+                o = (int64_t)q0 + slot[u];
+                const bool flip = s_flip[cl] == slot[u];
+                // the position (written to the output slot in C by this
+                // thread) is read back only for a flip or a colloid within
+                // reach of the tile
+                T xo3[3] = {(T)0, (T)0, (T)0};
+                if (flip || cmask != 0u)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) xo3[d] = xn[d][o];
+                if (flip) {
+                    du_sum += species_dU(D, cp, nc, s_Xw, (double)xo3[0], (double)xo3[1], (double)xo3[2], 1, 0);
+                    n_flip += 1.0;
+                    s = 0;
                 }
+                const T vt[3] = {(T)v3[0], (T)v3[1], (T)v3[2]};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vn[d][o] = vt[d];
+                stn[o] = s;
+                cnd = is_candidate_masked(D, cp, cmask, s_Xw, s, (double)xo3[0], (double)xo3[1],
+                                          (double)xo3[2], (double)vt[0], (double)vt[1], (double)vt[2]);
+                D.cflag[o] = cnd ? 1 : 0;
             }
-            uint8_t s = s_st[j];
-            const T xt[3] = {xo[0][p], xo[1][p], xo[2][p]};
-            if (s_flip[lc] == j) {
-                du_sum += species_dU(D, cp, nc, s_Xw, (double)xt[0], (double)xt[1], (double)xt[2], 1, 0);
-                n_flip += 1.0;
-                s = 0;
-            }
-            const int64_t o = (int64_t)q0 + j;
-            const T vt[3] = {(T)v3[0], (T)v3[1], (T)v3[2]};
-            for (int d = 0; d < 3; ++d) { xn[d][o] = xt[d]; vn[d][o] = vt[d]; }
-            idn[o] = ido[p];
-            stn[o] = s;
-            bool cnd = is_candidate(D, cp, nc, s_Xw, s, (double)xt[0], (double)xt[1], (double)xt[2],
-                                    (double)vt[0], (double)vt[1], (double)vt[2]);
-            D.cflag[o] = cnd ? 1 : 0;
-            count_flag(D.chunk_cnt, o, cnd);
+            count_flag(D.chunk_cnt, o, cnd, c_lo);
         }
-        __syncthreads();
         ga = gb;
+        if (ga < ncl) __syncthreads();   // the next group reuses the LDS
     }
-    t_sum = block_sum<COLL_NT>(t_sum, sred);
-    t_cells = block_sum<COLL_NT>(t_cells, sred);
-    du_sum = block_sum<COLL_NT>(du_sum, sred);
-    n_flip = block_sum<COLL_NT>(n_flip, sred);
+    double red[4] = {t_sum, t_cells, du_sum, n_flip};
+    block_sum_n<NT, 4>(red, sred);
     if (t == 0) {
-        D.tpart[(int64_t)tile * 4 + 0] = t_sum;
-        D.tpart[(int64_t)tile * 4 + 1] = t_cells;
-        D.tpart[(int64_t)tile * 4 + 2] = du_sum;
-        D.tpart[(int64_t)tile * 4 + 3] = n_flip;
+        D.tpart[(int64_t)tile * 4 + 0] = red[0];
+        D.tpart[(int64_t)tile * 4 + 1] = red[1];
+        D.tpart[(int64_t)tile * 4 + 2] = red[2];
+        D.tpart[(int64_t)tile * 4 + 3] = red[3];
+        D.bigmask[tile] = big;
+    }
+}
+
+// The cells that k_collide found beyond a group's capacity (a bit per
+// tile-local cell in bigmask[tile]).  Workgroup w looks at tiles
+// [64 w, 64 w + 64) of the launch and collides each such cell with all its
+// threads (collide_big_cell); the cell's temperature, reaction energy and
+// flips are added to its tile's partials after those of the tile's other
+// cells, cell by cell, so the sums stay deterministic.
+template <class T, int RULE>
+__global__ __launch_bounds__(256) void k_collide_big(Work w, int n_items)
+{
+    constexpr int NT = 256;
+    const int t = threadIdx.x;
+    __shared__ uint64_t s_mask[64];
+    __shared__ double s_u[3], s_n[3];
+    __shared__ int32_t s_flip;
+    __shared__ double s_Xw[MAXC][3];
+    __shared__ double sred[(NT / 64 + 1) * 4];
+    const int item0 = blockIdx.x * 64;
+    bool any = false;
+    if (t < 64) {
+        const int item = item0 + t;
+        uint64_t m = 0;
+        if (item < n_items) {
+            const int rep = find_rep(w.prefix, w.nrep, item);
+            const RepDesc& D = w.desc[rep];
+            if (D.active && D.rule == RULE) m = D.bigmask[item - w.prefix[rep]];
+        }
+        s_mask[t] = m;
+        any = m != 0;
+    }
+    if (__syncthreads_or(any) == 0) return;
+    for (int q = 0; q < 64; ++q) {
+        const uint64_t mask = s_mask[q];
+        if (mask == 0) continue;
+        const int item = item0 + q;
+        const int rep = find_rep(w.prefix, w.nrep, item);
+        const int tile = item - w.prefix[rep];
+        const RepDesc& D = w.desc[rep];
+        RepState* rs = D.rs;
+        const ColloidParams* cp = D.cp;
+        const int nc = cp->nc;
+        const int64_t coll = rs->coll_step;
+        if (t < nc)
+            for (int d = 0; d < 3; ++d) s_Xw[t][d] = colloid_image(rs->X[t][d], D.Ld[d]);
+        const int64_t c0 = (int64_t)tile * D.tile_cells;
+        double t_sum = 0.0, t_cells = 0.0, du_sum = 0.0, n_flip = 0.0;
+        for (uint64_t m = mask; m; m &= m - 1) {
+            const int ga = __ffsll((long long)m) - 1;
+            const int64_t cell = D.hbits == KEY_ROW ? c0 + ga : D.cell_of[c0 + ga];
+            const uint32_t q0 = D.start[c0 + ga];
+            const int nn = (int)(D.start[c0 + ga + 1] - q0);
+            if (RULE == 0 && t == 0) marsaglia_axis(D.seed, (uint64_t)coll, (uint64_t)cell, s_n);
+            __syncthreads();
+            collide_big_cell<T, RULE, NT>(D, cp, nc, s_Xw, coll, cell, q0, nn, s_u, s_n, &s_flip,
+                                          t_sum, t_cells, du_sum, n_flip);
+        }
+        double red[4] = {t_sum, t_cells, du_sum, n_flip};
+        block_sum_n<NT, 4>(red, sred);
+        if (t == 0)
+            for (int j = 0; j < 4; ++j) D.tpart[(int64_t)tile * 4 + j] = D.tpart[(int64_t)tile * 4 + j] + red[j];
+        __syncthreads();
     }
 }
 
@@ -2409,14 +3052,25 @@ __global__ __launch_bounds__(256) void k_msd(Analysis* A, int32_t max_lag)
     template __global__ void k_init<T>(const RepDesc*);                          \
     template __global__ void k_init_sub<T>(const RepDesc*, const double*);       \
     template __global__ void k_list<T>(Work);                                    \
-    template __global__ void k_stream_bin<T>(Work, int);                         \
+    template __global__ void k_stream_bin<T, 1>(Work, int);                      \
+    template __global__ void k_stream_bin<T, 2>(Work, int);                      \
+    template __global__ void k_stream_bin<T, 4>(Work, int);                      \
+    template __global__ void k_scatter<T>(Work);                                 \
     RMP_CHAIN_INST(T, 1, 256)                                                    \
     RMP_CHAIN_INST(T, 2, 256)                                                    \
     RMP_CHAIN_INST(T, 4, 256)                                                    \
     RMP_CHAIN_INST(T, 1, 512)                                                    \
     RMP_CHAIN_INST(T, 2, 512)                                                    \
-    template __global__ void k_collide<T, 0>(Work);                              \
-    template __global__ void k_collide<T, 1>(Work);                              \
+    template __global__ void k_collide_big<T, 0>(Work, int);                     \
+    template __global__ void k_collide_big<T, 1>(Work, int);                     \
+    template __global__ void k_collide<T, 0, 256, 2>(Work, int);                 \
+    template __global__ void k_collide<T, 1, 256, 2>(Work, int);                 \
+    template __global__ void k_collide<T, 0, 512, 2>(Work, int);                 \
+    template __global__ void k_collide<T, 1, 512, 2>(Work, int);                 \
+    template __global__ void k_collide<T, 0, 256, 1>(Work, int);                 \
+    template __global__ void k_collide<T, 1, 256, 1>(Work, int);                 \
+    template __global__ void k_collide<T, 0, 512, 1>(Work, int);                 \
+    template __global__ void k_collide<T, 1, 512, 1>(Work, int);                 \
     template __global__ void k_observe<T>(Work);                              \
     template __global__ void k_analysis<T>(Work);
 
