@@ -3,8 +3,8 @@
 For a box class (box edge, density, colloid count, precision, n_md) it times
 a few intervals of a seeded system for each point of a small grid of launch
 parameters -- Verlet-list entries per thread of the MD chain (which sets the
-number of chain workgroups), cells per collision tile, threads per
-streaming workgroup -- and caches the fastest in a JSON file keyed by the box
+number of chain workgroups), cells per collision tile, particles per
+streaming thread -- and caches the fastest in a JSON file keyed by the box
 class.  Tuning never changes results: every launch shape evaluates the same
 operations (the FP64 parity tests run several shapes against the oracle).
 """
@@ -15,8 +15,9 @@ import json
 import os
 import time
 
-GRID = dict(chain_k=(1, 2, 4), collide_cells=(16, 32, 64), stream_block=(128, 256))
-DEFAULT = dict(chain_k=1, collide_cells=0, stream_block=256, stream_ppt=1)   # collide_cells 0: by box size
+# collide_cells 0: sized from the density (the library's default)
+GRID = dict(chain_k=(1, 2), collide_cells=(0, 32, 40), stream_ppt=(1, 2))
+DEFAULT = dict(chain_k=1, collide_cells=0, stream_block=256, stream_ppt=2)
 
 
 def default_cache_path() -> str:
