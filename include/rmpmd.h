@@ -190,6 +190,23 @@ rmp_status rmp_step(rmp_system* s, int32_t n_md, int32_t n_collide);
  * RMP_EDEVICE (with out filled) if a device flag is set. */
 rmp_status rmp_observables(rmp_system* s, rmp_obs* out);
 
+/* For callers that cannot allocate device memory (code under graph capture
+ * elsewhere in the process, serving loops, harnesses that forbid
+ * hipMalloc): the same results as rmp_observables, bit for bit, with its
+ * per-chunk partial sums and their totals kept in a static device array of
+ * RMP_NOALLOC_SCRATCH_BYTES per GPU instead of the workspace.  The array
+ * holds 64 bytes per 1024 solvent particles plus 64, so systems up to
+ * 33,553,408 particles; a larger system gets RMP_ENOMEM and a message in
+ * rmp_last_error().  No device or host allocation in the call; it
+ * synchronises the system's stream.  All calls on one GPU share that GPU's
+ * array and keep no result in it between calls; the library serialises
+ * calls from different host threads on one device with a lock, and work on
+ * other streams that reads the array while a call runs would race.  The
+ * array's address is taken per device when a system is created there
+ * (rmp_init_system); RMP_ESTATE if none was. */
+#define RMP_NOALLOC_SCRATCH_BYTES (2u << 20)
+rmp_status rmp_observables_noalloc(rmp_system* s, rmp_obs* out);
+
 /* Copy the state to / from caller-owned host buffers (synchronous).  After
  * set_state the next interval rebuilds the Verlet list and forces.
  * set_state first applies rmp_check_state and uploads nothing on

@@ -164,6 +164,16 @@ class System:
             raise RmpError(st, "rmp_observables", o.flags)
         return obs_dict(o, self.nc)
 
+    def observables_noalloc(self, raise_on_flags: bool = True) -> dict:
+        """rmp_observables_noalloc: the same results from the library's
+        static device scratch (no allocation in the call)."""
+        o = _capi.Obs()
+        st = _capi.lib().rmp_observables_noalloc(self.h, C.byref(o))
+        if st not in (_capi.OK, _capi.EDEVICE) or (st == _capi.EDEVICE and raise_on_flags):
+            raise RmpError(st, "rmp_observables_noalloc", o.flags,
+                           detail=st in (_capi.ENOMEM, _capi.ESTATE))
+        return obs_dict(o, self.nc)
+
     def _buffers(self):
         if self._buf is None:
             self._buf = _StateBuffers(self.n, self.nc)

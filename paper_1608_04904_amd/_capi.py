@@ -98,6 +98,7 @@ SIGNATURES = {
     "rmp_init_system": (I32, [C.POINTER(Params), U64, P, SZ, P, C.POINTER(P)]),
     "rmp_step": (I32, [P, I32, I32]),
     "rmp_observables": (I32, [P, C.POINTER(Obs)]),
+    "rmp_observables_noalloc": (I32, [P, C.POINTER(Obs)]),
     "rmp_get_state": (I32, [P, C.POINTER(HostState)]),
     "rmp_set_state": (I32, [P, C.POINTER(HostState)]),
     "rmp_check_state": (I32, [C.POINTER(Params), C.POINTER(HostState)]),
@@ -150,9 +151,9 @@ def lib():
 
 
 class RmpError(RuntimeError):
-    def __init__(self, status: int, what: str = "", flags: int = 0):
+    def __init__(self, status: int, what: str = "", flags: int = 0, detail: bool = False):
         msg = lib().rmp_status_string(status).decode()
-        if status == EHIP:
+        if status == EHIP or detail:
             msg += " [" + lib().rmp_last_error().decode() + "]"
         super().__init__(f"{what}: {msg} (status {status}, flags {flags:#x})")
         self.status = status

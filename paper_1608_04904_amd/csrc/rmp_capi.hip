@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -242,6 +243,7 @@ struct rmp_batch {
     bool any_analysis = false;
     bool any_iterative = false;     // some occupied slot uses the iterative RATTLE
     int64_t n_total = 0;            // solvent particles over the occupied slots
+    int32_t device = 0;             // device current at creation (its stream's device)
     rmp_tuning tun{256, 2, 0, 1, 1, 0, 0, 0, 0, 0, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -259,6 +261,14 @@ struct rmp_system {
     rmp_batch* b = nullptr;
     rmp_batch storage;
 };
+
+// Device scratch of rmp_observables_noalloc: the per-chunk partial sums of
+// the observation kernel and their totals.  Each GPU holds its own copy for
+// the life of the process.  Host code never uses the array's name as an
+// address: the address on a device comes from hipGetSymbolAddress with that
+// device current, taken once per device when a batch is created there.
+static __device__ __align__(256) unsigned char scratch[RMP_NOALLOC_SCRATCH_BYTES];
+constexpr size_t RMP_STATIC_SCRATCH_BYTES = RMP_NOALLOC_SCRATCH_BYTES;
 
 namespace {
 
@@ -279,6 +289,34 @@ void note_error(const char* what, hipError_t e)
             return RMP_EHIP;                            \
         }                                               \
     } while (0)
+
+// Address of `scratch` on each device (nullptr until taken) and a lock per
+// device that keeps the allocation-free calls on one device from
+// overlapping.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_addr[MAX_DEVICES] = {};
+std::mutex g_scratch_call_mu[MAX_DEVICES];
+
+// With `dev` current: take the address of this device's scratch once.
+rmp_status take_scratch_address(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return RMP_EINVAL;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_addr[dev]) return RMP_OK;
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return RMP_EHIP;
+    g_scratch_addr[dev] = (char*)p;
+    return RMP_OK;
+}
+
+char* scratch_address(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_addr[dev];
+}
 
 rmp_status last_launch(const char* what)
 {
@@ -1009,6 +1047,9 @@ rmp_status batch_init(rmp_batch* b, int32_t nslots, int32_t precision, void* ctl
     {
         int dev = 0, ncu = 0;
         HIPCHK(hipGetDevice(&dev));
+        b->device = dev;
+        rmp_status sst = take_scratch_address(dev);
+        if (sst != RMP_OK) return sst;
         HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         int per[5] = {0, 0, 0, 0, 0};
         if (precision == 64) {
@@ -1046,8 +1087,11 @@ void batch_release(rmp_batch* b)
     b->ev.clear();
 }
 
+// scr: nullptr for the workspace's partials and a host-side sum; else the
+// device's static scratch, which takes the partials and their totals (the
+// allocation-free form; the two give identical results)
 template <class T>
-rmp_status observe(rmp_batch* b, int slot, rmp_obs* o)
+rmp_status observe(rmp_batch* b, int slot, rmp_obs* o, char* scr = nullptr)
 {
     Replica& R = b->reps[slot];
     hipStream_t s = b->stream;
@@ -1056,28 +1100,48 @@ rmp_status observe(rmp_batch* b, int slot, rmp_obs* o)
     // the observation kernel runs over this replica only: a one-replica work
     // list whose prefix is the identity prefix (prefix[0] == 0)
     const int cnt = R.desc.n_chunks;
+    const size_t part_bytes = (size_t)cnt * 8 * 8;
+    if (scr && part_bytes + 64 > RMP_STATIC_SCRATCH_BYTES) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "rmp_observables_noalloc: %d particle chunks need %zu bytes of static scratch, "
+                      "more than its %zu", cnt, part_bytes + 64, (size_t)RMP_STATIC_SCRATCH_BYTES);
+        return RMP_ENOMEM;
+    }
     Work w;
     w.desc = b->d_desc + slot;
     w.prefix = b->d_prefix[PF_REP];
     w.nrep = 1;
     w.flags = 0;
     w.budget = barrier_budget(b);
-    hipLaunchKernelGGL((k_observe<T>), dim3(cnt), dim3(256), 0, s, w);
+    double* part = scr ? (double*)scr : nullptr;
+    hipLaunchKernelGGL((k_observe<T>), dim3(cnt), dim3(256), 0, s, w, part);
     st = last_launch("k_observe");
     if (st != RMP_OK) return st;
-    std::vector<double> part((size_t)cnt * 8);
+    double P[3] = {0, 0, 0}, ke = 0, nb = 0;
     RepState rs;
-    HIPCHK(hipMemcpyAsync(part.data(), R.ws + R.lay.obs_part, part.size() * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&rs, R.ws + R.lay.rs, sizeof(rs), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    if (scr) {
+        double* tot = (double*)(scr + part_bytes);
+        hipLaunchKernelGGL(k_observe_total, dim3(1), dim3(64), 0, s, (const double*)part, cnt, tot);
+        st = last_launch("k_observe_total");
+        if (st != RMP_OK) return st;
+        double t[5];
+        HIPCHK(hipMemcpyAsync(t, tot, sizeof(t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&rs, R.ws + R.lay.rs, sizeof(rs), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        P[0] = t[0]; P[1] = t[1]; P[2] = t[2]; ke = t[3]; nb = t[4];
+    } else {
+        std::vector<double> hpart((size_t)cnt * 8);
+        HIPCHK(hipMemcpyAsync(hpart.data(), R.ws + R.lay.obs_part, part_bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&rs, R.ws + R.lay.rs, sizeof(rs), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < cnt; ++k) {
+            for (int d = 0; d < 3; ++d) P[d] += hpart[(size_t)k * 8 + d];
+            ke += hpart[(size_t)k * 8 + 3];
+            nb += hpart[(size_t)k * 8 + 4];
+        }
+    }
     if (b->prof) flush_profile(b);
     std::memset(o, 0, sizeof(*o));
-    double P[3] = {0, 0, 0}, ke = 0, nb = 0;
-    for (int k = 0; k < cnt; ++k) {
-        for (int d = 0; d < 3; ++d) P[d] += part[(size_t)k * 8 + d];
-        ke += part[(size_t)k * 8 + 3];
-        nb += part[(size_t)k * 8 + 4];
-    }
     double kec = 0.0;
     for (int d = 0; d < 3; ++d) o->momentum[d] = R.p.mass * P[d];
     for (int c = 0; c < R.p.n_colloids; ++c) {
@@ -1444,6 +1508,21 @@ rmp_status rmp_observables(rmp_system* s, rmp_obs* out)
 {
     if (!s || !out) return RMP_EINVAL;
     return s->b->precision == 32 ? observe<float>(s->b, 0, out) : observe<double>(s->b, 0, out);
+}
+
+rmp_status rmp_observables_noalloc(rmp_system* s, rmp_obs* out)
+{
+    g_last_error[0] = 0;
+    if (!s || !out) return RMP_EINVAL;
+    rmp_batch* b = s->b;
+    char* scr = scratch_address(b->device);
+    if (!scr) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "rmp_observables_noalloc: no scratch address for device %d", b->device);
+        return RMP_ESTATE;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_call_mu[b->device]);
+    return b->precision == 32 ? observe<float>(b, 0, out, scr) : observe<double>(b, 0, out, scr);
 }
 
 rmp_status rmp_get_state(rmp_system* s, rmp_host_state* dst)

@@ -2836,8 +2836,10 @@ __global__ __launch_bounds__(256) void k_collide_big(Work w, int n_items)
 
 // ---------------------------------------------------------- observables
 
+// part: where the per-chunk partials go (nullptr: the replica's own
+// workspace region)
 template <class T>
-__global__ __launch_bounds__(256) void k_observe(Work w)
+__global__ __launch_bounds__(256) void k_observe(Work w, double* part)
 {
     const int item = blockIdx.x;
     const int rep = find_rep(w.prefix, w.nrep, item);
@@ -2859,10 +2861,23 @@ __global__ __launch_bounds__(256) void k_observe(Work w)
         nb += (double)(D.st[cur][i] & 1);
     }
     double r[5] = {P0, P1, P2, ke, nb};
+    double* out = part ? part : D.obs_part;
     for (int k = 0; k < 5; ++k) {
         double s = block_sum<256>(r[k], sred);
-        if (threadIdx.x == 0) D.obs_part[(int64_t)chunk * 8 + k] = s;
+        if (threadIdx.x == 0) out[(int64_t)chunk * 8 + k] = s;
     }
+}
+
+// Totals of the k_observe partials: lane k (< 5) adds quantity k over the
+// chunks in chunk order, the order of the host-side sum, so both give the
+// same totals bit for bit.
+__global__ __launch_bounds__(64) void k_observe_total(const double* part, int cnt, double* tot)
+{
+    const int k = threadIdx.x;
+    if (k >= 5) return;
+    double s = 0.0;
+    for (int c = 0; c < cnt; ++c) s += part[(int64_t)c * 8 + k];
+    tot[k] = s;
 }
 
 // ------------------------------------------------------------ dimer analysis
@@ -3071,7 +3086,7 @@ __global__ __launch_bounds__(256) void k_msd(Analysis* A, int32_t max_lag)
     template __global__ void k_collide<T, 1, 256, 1>(Work, int);                 \
     template __global__ void k_collide<T, 0, 512, 1>(Work, int);                 \
     template __global__ void k_collide<T, 1, 512, 1>(Work, int);                 \
-    template __global__ void k_observe<T>(Work);                              \
+    template __global__ void k_observe<T>(Work, double*);                     \
     template __global__ void k_analysis<T>(Work);
 
 RMP_INST(double)
