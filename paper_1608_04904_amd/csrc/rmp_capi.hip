@@ -35,7 +35,7 @@ struct Sizes {
 };
 
 constexpr int MIN_TILE_CELLS = 8;
-constexpr int MAX_G = 256;
+constexpr int MAX_G = MAX_CHAIN_G;
 constexpr int K_MAX = 4;
 
 int64_t auto_capacity(const rmp_params* p)
@@ -148,7 +148,7 @@ Sizes sizes_of(const rmp_params* p)
 // offsets of every array inside a replica workspace
 struct Layout {
     size_t cp, rs, x[2], v[2], id[2], st[2], keyrank, stage, cflag, count, start, scanblk,
-        chunk_cnt, chunk_off, cand_idx, order, partials, finals, epart, tpart, bigmask, ptable, obs_part, mean, total;
+        chunk_cnt, chunk_off, cand_idx, order, partials, epart, tpart, bigmask, ptable, obs_part, mean, total;
 };
 
 Layout layout_of(const rmp_params* p)
@@ -176,8 +176,7 @@ Layout layout_of(const rmp_params* p)
     L.chunk_off = take(4 * (size_t)s.n_chunks);
     L.cand_idx = take(4 * (size_t)s.cand_cap);
     L.order = take(2 * 4 * (size_t)s.ncell);
-    L.partials = take(2 * (size_t)s.G * NVAL_MAX * 2 * 8);
-    L.finals = take(2 * (size_t)NVAL_MAX * 2 * 8);
+    L.partials = take(2 * ((size_t)s.G * ROWW + BCW) * 8);
     L.epart = take((size_t)s.G * 2 * 8);
     L.tpart = take((size_t)s.n_tiles_max * 4 * 8);
     L.bigmask = take((size_t)s.n_tiles_max * 8);
@@ -456,6 +455,12 @@ void fill_desc(rmp_batch* b, Replica& r)
     D.sa = std::sin(p->alpha);
     D.cat_prob = p->cat_prob;
     D.skin_half2 = (0.5 * p->skin) * (0.5 * p->skin);
+    // the chain's per-interval colloid cull holds while list entries move less
+    // than cull_me from their interval-start positions (five thermal speeds
+    // over tau, plus room for the colloid forces); past it a wave tests every
+    // colloid, so the margin sets speed only, never results
+    D.cull_me = 5.0 * std::sqrt(p->kT / p->mass) * (r.n_md * p->dt) + 0.5;
+    D.cull_margin = D.cull_me + 0.5 * p->skin;
     D.bulk_on = p->bulk_rate > 0.0 ? 1 : 0;
     D.seed = r.seed;
     for (int q = 0; q < 2; ++q) {
@@ -476,7 +481,6 @@ void fill_desc(rmp_batch* b, Replica& r)
     D.rank_of = (const uint32_t*)(w + L.order);
     D.cell_of = (const uint32_t*)(w + L.order) + s.ncell;
     D.partials = (double*)(w + L.partials);
-    D.finals = (double*)(w + L.finals);
     D.epart = (double*)(w + L.epart);
     D.tpart = (double*)(w + L.tpart);
     D.bigmask = (uint64_t*)(w + L.bigmask);

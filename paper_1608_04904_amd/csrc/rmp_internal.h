@@ -14,6 +14,10 @@ constexpr int SCAN_BLK = 4096;       // cells per block of the multi-block cell 
 constexpr int SCAN_DIRECT_BLOCKS = 8; // up to this many blocks, no separate block-sum pass
 constexpr int CHAIN_BLOCK = 256;     // threads per Verlet-list workgroup
 constexpr int NVAL_MAX = 3 * MAXC + 1;  // reduced values per MD step: F per colloid + U
+constexpr int MAX_CHAIN_G = 256;      // MD-chain workgroups per system at most
+constexpr int ROWW = 2 * NVAL_MAX + 2;    // MD-chain exchange: words per workgroup
+constexpr int BCW = 6 * MAXC + 2;         // MD-chain broadcast of the colloid positions: words
+constexpr int XTAB_V = 49, XTAB_R = 128;   // MD-chain master: values and rows per table chunk
 constexpr uint64_t BARRIER_BUDGET_TICKS = 25000000;  // 0.25 s of the 100 MHz wall clock (default)
 constexpr int32_t BARRIER_BUDGET_MAX_US = 10000000;  // largest budget a caller may set (10 s)
 constexpr int32_t KEY_TABLE = -1;                    // cell sort rank from rank_of[]
@@ -103,6 +107,7 @@ struct RepDesc {
     int32_t hbits;             // cell sort rank: >= 0 Hilbert index with hbits bits, KEY_TABLE, KEY_ROW
     double Ld[3], halfL[3];
     double dt, h, tau, vscale, mass, ca, sa, cat_prob, skin_half2;
+    double cull_me, cull_margin; // MD chain cull: entry displacement allowed per interval; + skin/2
     int32_t bulk_on, pad1;
     int32_t flow;              // constant acceleration and/or walls: every particle streams
     int32_t walls;             // plates at z = 0 and z = Ld[2]
@@ -125,8 +130,7 @@ struct RepDesc {
     uint32_t* cand_idx;        // [cand_cap]
     const uint32_t* rank_of;   // [ncell] sort rank of a cell (Hilbert order)
     const uint32_t* cell_of;   // [ncell] cell of a sort rank
-    double* partials;          // [2][G][NVAL_MAX][2] 64-bit exchange words of the MD chain
-    double* finals;            // [2][NVAL_MAX][2] exchange totals of the MD chain (two-hop exchange)
+    double* partials;          // [2][G * ROWW + BCW] 64-bit exchange words of the MD chain
     double* epart;             // [G][2] reaction energy / flips of the interval
     double* tpart;             // [n_tiles][4] collision partials: temperature sum, cells, reaction energy, flips
     uint64_t* bigmask;         // [n_tiles] cells of a tile beyond a collision group's capacity

@@ -517,7 +517,7 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(Work w, int after_collision
         // counters may have moved backwards: clear the exchange words so no
         // stale epoch can match
         uint64_t* part = reinterpret_cast<uint64_t*>(D.partials);
-        for (int64_t k = t; k < (int64_t)2 * D.G * NVAL_MAX * 2; k += 1024) part[k] = 0ull;
+        for (int64_t k = t; k < 2 * ((int64_t)D.G * ROWW + BCW); k += 1024) part[k] = 0ull;
     }
     if (t == 0) {
         rs->n_cand = total;
@@ -1070,8 +1070,8 @@ __device__ __forceinline__ double uniform_d(double v)
 // the exchange.
 struct ChainConst {
     double Lv[3], hv[3];       // box lengths and half lengths
-    uint64_t* partv;           // exchange words
-    uint64_t* finv;            // totals of the two-hop exchange [2][NVAL_MAX][2]
+    uint64_t* partv;           // exchange buffers, two of stridev words
+    int64_t stridev;           // G * ROWW + BCW
     int Gv;                    // workgroups of the replica's exchange buffers
     double catv;
     uint64_t seedv;
@@ -1079,8 +1079,8 @@ struct ChainConst {
     __device__ double L(int d) const { return Lv[d]; }
     __device__ double h(int d) const { return hv[d]; }
     __device__ uint64_t* part() const { return partv; }
-    __device__ uint64_t* fin() const { return finv; }
     __device__ int G() const { return Gv; }
+    __device__ int64_t stride() const { return stridev; }
     __device__ double cat_prob() const { return catv; }
     __device__ uint64_t seed() const { return seedv; }
     __device__ uint64_t budget() const { return budgetv; }
@@ -1094,8 +1094,8 @@ __device__ __forceinline__ ChainConst chain_const(const RepDesc& D, uint64_t bud
         c.hv[d] = uniform_d(D.halfL[d]);
     }
     c.partv = reinterpret_cast<uint64_t*>(uniform_u64((uint64_t)(uintptr_t)D.partials));
-    c.finv = reinterpret_cast<uint64_t*>(uniform_u64((uint64_t)(uintptr_t)D.finals));
     c.Gv = __builtin_amdgcn_readfirstlane(D.G);
+    c.stridev = (int64_t)c.Gv * ROWW + BCW;
     c.catv = uniform_d(D.cat_prob);
     c.seedv = uniform_u64(D.seed);
     c.budgetv = uniform_u64(budget);
@@ -1109,9 +1109,20 @@ struct ChainCtx {
     double sXw[MAXC][3];       // periodic images of the colloid positions
     // colloid constants read in every MD step, staged once per interval
     double cRc2[MAXC], cSig2[MAXC], cEpsA[MAXC], cEpsB[MAXC], cSigma[MAXC];
-    int32_t cCat[MAXC], cType[MAXC];
+    double cCull2[MAXC];       // (cut-off + reach margin)^2 of the interval's cull
+    int32_t cCat[MAXC], cType[MAXC], cBody[MAXC];
+    double cEcc[2][2];
     double sRed[NT / 64][NVAL_MAX];
     double sNode[NVAL_MAX];
+    uint32_t sWhit[NT / 64];   // colloids that some entry of the wave is within cut-off of
+    // master of the multi-workgroup exchange: the colloids each row listed
+    // at the last look, the rows' first slots, and a chunk of the values by
+    // value and row
+    uint32_t sE[MAX_CHAIN_G];
+    uint32_t sOff[XTAB_R + 1];
+    double sTab[XTAB_V][XTAB_R];
+    uint32_t sPairMask[MAXC];  // colloid c: bit a set when the pair (c, a) interacts
+    uint32_t sFull;            // a colloid left its interval-start reach margin: no cull
     // colloid-colloid pairs (a < b) of the current positions: force on the
     // lower colloid and potential, and whether the pair interacts
     static constexpr int NPAIR = NB > 1 ? MAXC * (MAXC - 1) / 2 : 1;
@@ -1163,7 +1174,7 @@ __device__ __forceinline__ void pair_force(const Ctx& S, const ChainConst& cc, c
 {
     on = 0;
     out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; out[3] = 0.0;
-    if (cp->body[a] == cp->body[b]) return;
+    if (S.cBody[a] == S.cBody[b]) return;
     const double dx = min_image(S.sXw[a][0] - S.sXw[b][0], cc.L(0), cc.h(0));
     const double dy = min_image(S.sXw[a][1] - S.sXw[b][1], cc.L(1), cc.h(1));
     const double dz = min_image(S.sXw[a][2] - S.sXw[b][2], cc.L(2), cc.h(2));
@@ -1172,7 +1183,7 @@ __device__ __forceinline__ void pair_force(const Ctx& S, const ChainConst& cc, c
     const double rc = 0x1.1f59ac3c7d6c0p+0 * sab;
     if (r2 < rc * rc) {
         double coef, pot;
-        wca(r2, sab * sab, cp->eps_cc[S.cType[a]][S.cType[b]], coef, pot);
+        wca(r2, sab * sab, S.cEcc[S.cType[a]][S.cType[b]], coef, pot);
         out[0] = coef * dx; out[1] = coef * dy; out[2] = coef * dz; out[3] = pot;
         on = 1;
     }
@@ -1186,9 +1197,9 @@ __device__ __forceinline__ void pair_force(const Ctx& S, const ChainConst& cc, c
 // the others (chain_collect completes the tree over workgroups).
 template <class T, int K, int NT, int NB>
 __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainConst& cc, const ColloidParams* cp,
-                              int nc, const bool* valid, const T (*x)[3], const uint8_t* st,
-                              double (*f)[3], bool* inside, int g, int Gact,
-                              uint32_t& nbar, uint32_t epoch0)
+                              int nc, const bool* valid, const T (*x)[3], const T (*x0)[3], const uint8_t* st,
+                              double (*f)[3], bool* inside, int g, int Gact, bool solo,
+                              uint32_t& wmask, double me2, uint32_t& nbar, uint32_t epoch0)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double u[K];
@@ -1198,51 +1209,28 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainCo
         u[j] = 0.0;
         inside[j] = false;
     }
-    // Colloids within reach of this wave: the bounding box of the wave's
-    // entries (minimum-image offsets from its first entry, which is valid
-    // whenever any is) against each colloid's cut-off sphere, one lane per
-    // colloid.  A colloid out of reach of the box contributes exactly zero to
-    // every entry of the wave, so its distances are not computed.  (Systems
-    // of one or two colloids test them all.)
-    uint32_t reach_mask = nc >= 32 ? 0xffffffffu : ((1u << nc) - 1u);
-    if (nc > 2) {
-        double ref[3], lo[3], hi[3];
+    // Colloids within reach of this wave: wmask, set at the start of the
+    // interval from the box of the wave's entries (reach_box).  It holds
+    // while every entry stays within the margin me of its position at the
+    // start and every colloid within half the skin of its own; once either
+    // fails the wave tests every colloid for the rest of the interval.  A
+    // colloid out of reach contributes exactly zero to every entry of the
+    // wave, so its distances are not computed.
+    const uint32_t all_mask = nc >= 32 ? 0xffffffffu : ((1u << nc) - 1u);
+    if (wmask != all_mask) {
+        bool moved = false;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            ref[d] = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint((double)x[0][d])),
-                                      __builtin_amdgcn_readfirstlane(__double2loint((double)x[0][d])));
-            lo[d] = 1e300; hi[d] = -1e300;
-#pragma unroll
-            for (int j = 0; j < K; ++j)
-                if (valid[j]) {
-                    const double o = min_image((double)x[j][d] - ref[d], cc.L(d), cc.h(d));
-                    lo[d] = o < lo[d] ? o : lo[d];
-                    hi[d] = o > hi[d] ? o : hi[d];
-                }
-            wave_min_max(lo[d], hi[d]);
-        }
-        bool near = true;
-        if (lane < nc) {
-            double r2 = 0.0;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                if (!(hi[d] - lo[d] < cc.h(d))) continue;          // wide (or no entry): no bound
-                const double oc = min_image(S.sXw[lane][d] - ref[d], cc.L(d), cc.h(d));
-                double dd = 1e300;
-#pragma unroll
-                for (int img = -1; img <= 1; ++img) {
-                    const double ci = oc + (double)img * cc.L(d);
-                    double e = lo[d] - ci > ci - hi[d] ? lo[d] - ci : ci - hi[d];
-                    e = e > 0.0 ? e : 0.0;
-                    dd = e < dd ? e : dd;
-                }
-                r2 += dd * dd;
+        for (int j = 0; j < K; ++j)
+            if (valid[j]) {
+                const double dx = min_image((double)x[j][0] - (double)x0[j][0], cc.L(0), cc.h(0));
+                const double dy = min_image((double)x[j][1] - (double)x0[j][1], cc.L(1), cc.h(1));
+                const double dz = min_image((double)x[j][2] - (double)x0[j][2], cc.L(2), cc.h(2));
+                moved = moved || !(dot3(dx, dy, dz, dx, dy, dz) < me2);
             }
-            // margin far above the rounding of the entries' own r^2
-            near = r2 <= S.cRc2[lane] * (1.0 + 1e-9) + 1e-9;
-        }
-        reach_mask &= (uint32_t)__ballot(near);
+        if (__ballot(moved) != 0 || S.sFull != 0) wmask = all_mask;
     }
+    const uint32_t reach_mask = wmask;
+    uint32_t whit = 0;           // colloids some entry of the wave is within cut-off of
     // colloids two at a time: forces and the reduction over the K entries
     // of each thread, then the wave trees of the six components (and, after
     // the last pair, of the potential) side by side
@@ -1280,6 +1268,7 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainCo
             }
             if (__ballot(any) != 0) {
                 hit_chunk = true;
+                whit |= 1u << c;
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     double coef, pot;
@@ -1339,6 +1328,7 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainCo
         // no colloid: the potential of the list is zero (tree of zeros)
         if (lane == 0) S.sRed[wave][0] = 0.0;
     }
+    if (lane == 0) S.sWhit[wave] = whit;
     __syncthreads();
     const int nv = 3 * nc + 1;
     constexpr int NW = NT / 64;
@@ -1353,24 +1343,322 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainCo
         S.sNode[t] = a[0];
     }
     if (Gact > 1) {
-        // Exchange of the workgroup nodes: value v of workgroup g is
-        // published as two 64-bit words (low and high half of the double,
-        // each with the barrier's epoch in its low 32 bits).  A reader
-        // accepts a word only when its epoch matches, so no separate flag,
-        // fence or counter is needed.  Epochs are unique per barrier of the
-        // replica; the two buffers alternate between barriers.
+        // Publish this workgroup's node values, each double as two 64-bit
+        // words (low and high half, each with the barrier's epoch in its low
+        // 32 bits), so that a reader accepts a word only when its epoch
+        // matches and needs no separate flag or fence.  Epochs are unique per
+        // barrier of the replica; the two buffers alternate between barriers.
+        // Solo form: value v in planes 2v and 2v + 1, column g (every value).
+        // Otherwise the packed row g of the master exchange (exchange_master).
         nbar++;
         const uint32_t epoch = epoch0 + nbar;
-        uint64_t* part = cc.part() +
-                         (int64_t)(nbar & 1) * cc.G() * NVAL_MAX * 2;
+        const int64_t Gs = cc.G();
+        uint64_t* P = cc.part() + (int64_t)(nbar & 1) * cc.stride();
+        uint32_t m = 0;
+        if (t < nv || t == 0)
+#pragma unroll
+            for (int w2 = 0; w2 < NW; ++w2) m |= S.sWhit[w2];
         if (t < nv) {
             const double val = S.sNode[t];
             const uint64_t lo = ((uint64_t)(uint32_t)__double2loint(val) << 32) | epoch;
             const uint64_t hi = ((uint64_t)(uint32_t)__double2hiint(val) << 32) | epoch;
-            __hip_atomic_store(&part[((int64_t)g * NVAL_MAX + t) * 2 + 0], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&part[((int64_t)g * NVAL_MAX + t) * 2 + 1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t o = -1;
+            if (solo) {
+                o = (int64_t)(2 * t) * Gs + g;          // planes 2t, 2t + 1 (all values)
+            } else if (t == 3 * nc) {
+                o = (int64_t)g * ROWW + 2;               // potential: slot 1
+            } else if ((m >> (t / 3)) & 1u) {
+                const int c = t / 3;
+                o = (int64_t)g * ROWW + 2 * (2 + 3 * __popc(m & ((1u << c) - 1u)) + (t - 3 * c));
+            }
+            if (o >= 0) {
+                __hip_atomic_store(&P[o], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&P[solo ? o + Gs : o + 1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (t == 0 && !solo)
+            __hip_atomic_store(&P[(int64_t)g * ROWW], ((uint64_t)m << 32) | epoch, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Colloids within reach of this wave for an interval: the bounding box of
+// the wave's entries at its start (minimum-image offsets from its first
+// entry, which is valid whenever any is) against each colloid's sphere of
+// the cut-off plus the reach margin (me plus half the skin, cCull2), one lane
+// per colloid.  Systems of one or two colloids test them all.
+template <class T, int K, int NT, int NB>
+__device__ __forceinline__ uint32_t reach_box(const ChainCtx<NT, NB>& S, const ChainConst& cc, int nc,
+                                              const bool* valid, const T (*x)[3])
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t mask = nc >= 32 ? 0xffffffffu : ((1u << nc) - 1u);
+    if (nc <= 2) return mask;
+    double ref[3], lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ref[d] = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint((double)x[0][d])),
+                                  __builtin_amdgcn_readfirstlane(__double2loint((double)x[0][d])));
+        lo[d] = 1e300; hi[d] = -1e300;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (valid[j]) {
+                const double o = min_image((double)x[j][d] - ref[d], cc.L(d), cc.h(d));
+                lo[d] = o < lo[d] ? o : lo[d];
+                hi[d] = o > hi[d] ? o : hi[d];
+            }
+        wave_min_max(lo[d], hi[d]);
+    }
+    bool near = true;
+    if (lane < nc) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (!(hi[d] - lo[d] < cc.h(d))) continue;          // wide (or no entry): no bound
+            const double oc = min_image(S.sXw[lane][d] - ref[d], cc.L(d), cc.h(d));
+            double dd = 1e300;
+#pragma unroll
+            for (int img = -1; img <= 1; ++img) {
+                const double ci = oc + (double)img * cc.L(d);
+                double e = lo[d] - ci > ci - hi[d] ? lo[d] - ci : ci - hi[d];
+                e = e > 0.0 ? e : 0.0;
+                dd = e < dd ? e : dd;
+            }
+            r2 += dd * dd;
+        }
+        // margin far above the rounding of the entries' own r^2
+        near = r2 <= S.cCull2[lane] * (1.0 + 1e-9) + 1e-9;
+    }
+    return mask & (uint32_t)__ballot(near);
+}
+
+// Exchange through a master workgroup (workgroup 0), used when the solo
+// form does not apply.  Every workgroup publishes a packed row: the header
+// (the mask of the colloids some entry of the workgroup was within cut-off
+// of, and the barrier's epoch), the potential, then the three components
+// of each listed colloid in ascending order, each double as two 64-bit
+// words tagged with the epoch.  The node value of an unlisted colloid is
+// exactly +0.0 (a tree of zeros), so it is not sent.  The master reads the
+// rows in slots of two words (slot 0 the header, 1 the potential, 2 + 3j + d
+// component d of the j-th listed colloid), expecting the colloids each row
+// listed at the last look (sE); a round is repeated until every header is
+// current and lists what was expected and every slot read is current.  The
+// values are then spread into a table by value and row, and each value is
+// summed over the rows with the wave tree of each group of 64 rows, the
+// groups pairwise (the same tree as over all rows at once).  The master
+// alone then updates the colloids and broadcasts their positions
+// (broadcast_images / await_images).
+constexpr int XSLOTS = 4;      // slots per thread and batch of the master's reads
+
+__device__ __forceinline__ int nth_bit(uint32_t m, int j)
+{
+    for (int i = 0; i < j; ++i) m &= m - 1u;
+    return __ffs(m) - 1;
+}
+
+template <int NT, int NB>
+__device__ __forceinline__ void exchange_master(ChainCtx<NT, NB>& S, const ChainConst& cc, int nc, int Gact,
+                                                uint32_t nbar, uint32_t epoch0)
+{
+    constexpr int NW = NT / 64;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t epoch = epoch0 + nbar;
+    const uint64_t* P = cc.part() + (int64_t)(nbar & 1) * cc.stride();
+    const int nv = 3 * nc + 1;
+    const uint64_t t_start = wall_clock64();
+    // passes over chunks of XTAB_V values and of XTAB_R rows of the table
+    for (int v0 = 0; v0 < nv; v0 += XTAB_V)
+        for (int r0 = 0; r0 < Gact; r0 += XTAB_R) {
+            const int nr = Gact - r0 < XTAB_R ? Gact - r0 : XTAB_R;
+            int nap = 0;
+            while (true) {
+                __asm__ __volatile__("" ::: "memory");
+                // slot offsets of the rows (2 + 3 m slots each), one lane per
+                // row, the exclusive scan over the rows in order
+                if (wave == 0) {
+                    constexpr int RPL = (XTAB_R + 63) / 64;     // rows per lane
+                    uint32_t cnt[RPL], sum = 0;
+#pragma unroll
+                    for (int q = 0; q < RPL; ++q) {
+                        const int r = lane * RPL + q;
+                        cnt[q] = r < nr ? 2u + 3u * (uint32_t)__popc(S.sE[r0 + r]) : 0u;
+                        sum += cnt[q];
+                    }
+                    uint32_t inc = sum;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const uint32_t y = __shfl_up(inc, o, 64);
+                        if (lane >= o) inc += y;
+                    }
+                    uint32_t off = inc - sum;
+#pragma unroll
+                    for (int q = 0; q < RPL; ++q) {
+                        const int r = lane * RPL + q;
+                        if (r < nr) S.sOff[r] = off;
+                        off += cnt[q];
+                    }
+                    if (lane == 63) S.sOff[nr] = inc;
+                }
+                // the table of this chunk starts at +0.0 (unlisted values)
+                for (int k = t; k < XTAB_V * XTAB_R; k += NT) (&S.sTab[0][0])[k] = 0.0;
+                __syncthreads();
+                const int T = (int)S.sOff[nr];
+                int ok = 1;
+                for (int base = 0; base < T; base += XSLOTS * NT) {
+                    uint64_t hw[XSLOTS], wl[XSLOTS], wh[XSLOTS];
+                    int rr[XSLOTS], ss[XSLOTS];
+#pragma unroll
+                    for (int k = 0; k < XSLOTS; ++k) {
+                        const int i = base + t + k * NT;
+                        rr[k] = -1;
+                        ss[k] = 0;
+                        hw[k] = wl[k] = wh[k] = 0ull;
+                        if (i < T) {
+                            // the row holding slot i: the last r with sOff[r] <= i
+                            int lo = 0, hi = nr - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if ((int)S.sOff[mid] <= i) lo = mid;
+                                else hi = mid - 1;
+                            }
+                            rr[k] = lo;
+                            ss[k] = i - (int)S.sOff[lo];
+                            const uint64_t* row = P + (int64_t)(r0 + lo) * ROWW;
+                            hw[k] = __hip_atomic_load(&row[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            if (ss[k] > 0) {
+                                wl[k] = __hip_atomic_load(&row[2 * ss[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                wh[k] = __hip_atomic_load(&row[2 * ss[k] + 1], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < XSLOTS; ++k) {
+                        if (rr[k] < 0) continue;
+                        const int r = rr[k], s = ss[k];
+                        const bool cur = (uint32_t)hw[k] == epoch;
+                        const uint32_t m = (uint32_t)(hw[k] >> 32);
+                        const uint32_t e = S.sE[r0 + r];
+                        ok &= (cur && m == e) ? 1 : 0;
+                        if (s > 0) {
+                            ok &= ((uint32_t)wl[k] == epoch && (uint32_t)wh[k] == epoch) ? 1 : 0;
+                            // value index of the slot
+                            int v = 3 * nc;
+                            if (s >= 2) {
+                                const int j = (s - 2) / 3, d = (s - 2) - 3 * j;
+                                v = 3 * nth_bit(e, j) + d;
+                            }
+                            if (v >= v0 && v < v0 + XTAB_V)
+                                S.sTab[v - v0][r] = __hiloint2double((int)(wh[k] >> 32), (int)(wl[k] >> 32));
+                        } else if (cur && m != e) {
+                            S.sE[r0 + r] = m;      // look for the listed colloids next round
+                        }
+                    }
+                }
+                if (__syncthreads_and(ok)) break;
+                // the time budget, decided for the workgroup by thread 0; once
+                // given up (RMP_FLAG_BARRIER) later barriers do not wait
+                if (t == 0 && !(S.sflags & RMP_FLAG_BARRIER) && wall_clock64() - t_start > cc.budget())
+                    atomicOr(&S.sflags, RMP_FLAG_BARRIER);
+                __syncthreads();
+                if (S.sflags & RMP_FLAG_BARRIER) break;
+                if (++nap > 16) __builtin_amdgcn_s_sleep(2);
+            }
+            // trees: wave w takes the values v0 + w, v0 + w + NW, ...; lane l
+            // rows l and l + 64 of the chunk
+            for (int vb = wave; vb < XTAB_V && v0 + vb < nv; vb += 4 * NW) {
+                double a[4][2];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int vv = vb + i * NW;
+                    const bool use = vv < XTAB_V && v0 + vv < nv;
+                    a[i][0] = use ? S.sTab[use ? vv : 0][lane] : 0.0;
+                    a[i][1] = use ? S.sTab[use ? vv : 0][lane + 64] : 0.0;
+                }
+                wave_tree_sum_n<8>(reinterpret_cast<double(&)[8]>(a));
+                if (lane == 0)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int vv = vb + i * NW;
+                        if (vv < XTAB_V && v0 + vv < nv) {
+                            const double tot = a[i][0] + a[i][1];
+                            S.sNode[v0 + vv] = r0 == 0 ? tot : S.sNode[v0 + vv] + tot;
+                        }
+                    }
+            }
+            // the next chunk rewrites the table only after every wave has read it
+            __syncthreads();
+        }
+}
+
+// Master: the colloid positions of the coming MD step (their images, as in
+// sXw) for the other workgroups, each double as two words tagged with the
+// barrier's epoch, then the flag word (sFull << 32 | epoch).  Wave 0.
+template <int NT, int NB>
+__device__ __forceinline__ void broadcast_images(ChainCtx<NT, NB>& S, const ChainConst& cc, int nc, uint32_t nbar,
+                                                 uint32_t epoch0)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t epoch = epoch0 + nbar;
+    uint64_t* B = cc.part() + (int64_t)(nbar & 1) * cc.stride() + cc.G() * (int64_t)ROWW;
+    for (int k = lane; k < 3 * nc; k += 64) {
+        const double val = S.sXw[k / 3][k % 3];
+        const uint64_t lo = ((uint64_t)(uint32_t)__double2loint(val) << 32) | epoch;
+        const uint64_t hi = ((uint64_t)(uint32_t)__double2hiint(val) << 32) | epoch;
+        __hip_atomic_store(&B[2 * k], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&B[2 * k + 1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0)
+        __hip_atomic_store(&B[6 * nc], ((uint64_t)S.sFull << 32) | epoch, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Other workgroups: wait (bounded) for the master's positions of the coming
+// MD step into sXw and sFull.  Wave 0: lane 0 polls the flag word, then the
+// wave reads the positions (read again if a word is not yet current).
+template <int NT, int NB>
+__device__ __forceinline__ void await_images(ChainCtx<NT, NB>& S, const ChainConst& cc, int nc, uint32_t nbar,
+                                             uint32_t epoch0)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t epoch = epoch0 + nbar;
+    const uint64_t* B = cc.part() + (int64_t)(nbar & 1) * cc.stride() + cc.G() * (int64_t)ROWW;
+    const uint64_t t_start = wall_clock64();
+    int nap = 0;
+    uint64_t fw = 0;
+    bool gave_up = (__hip_atomic_load(&S.sflags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) &
+                    RMP_FLAG_BARRIER) != 0;
+    while (!gave_up) {
+        __asm__ __volatile__("" ::: "memory");
+        uint64_t f = 0;
+        if (lane == 0) f = __hip_atomic_load(&B[6 * nc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        fw = __shfl(f, 0, 64);
+        if ((uint32_t)fw == epoch) break;
+        if (wall_clock64() - t_start > cc.budget()) {
+            if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
+            gave_up = true;
+            break;
+        }
+        if (++nap > 16) __builtin_amdgcn_s_sleep(2);
+    }
+    while (!gave_up) {
+        // every round loads anew (no load of the words may be carried over
+        // from an earlier round)
+        __asm__ __volatile__("" ::: "memory");
+        bool good = true;
+        for (int k = lane; k < 3 * nc; k += 64) {
+            const uint64_t lo = __hip_atomic_load(&B[2 * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t hi = __hip_atomic_load(&B[2 * k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            good = good && (uint32_t)lo == epoch && (uint32_t)hi == epoch;
+            S.sXw[k / 3][k % 3] = __hiloint2double((int)(hi >> 32), (int)(lo >> 32));
+        }
+        if (__ballot(!good) == 0) break;
+        if (wall_clock64() - t_start > cc.budget()) {
+            if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
+            break;
         }
     }
+    if (lane == 0 && (fw >> 32) != 0) S.sFull = 1u;
 }
 
 // Wait (bounded) for the exchange words of values v = v0 + vb*vs (vb < VB,
@@ -1381,8 +1669,8 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainCo
 // that exist are loaded (wave-uniform guards): a co-resident workgroup that
 // is still computing must not be starved by polling traffic.
 template <int VB, int QM, class Ctx>
-__device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0, int vs, int nv, int Gact,
-                                            int Q, uint32_t epoch, uint64_t budget, double (&out)[VB])
+__device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int64_t Gs, int v0, int vs, int nv,
+                                            int Gact, int Q, uint32_t epoch, uint64_t budget, double (&out)[VB])
 {
     const int lane = threadIdx.x & 63;
     double b4[VB][QM];
@@ -1392,6 +1680,8 @@ __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0
     const uint64_t t_start = wall_clock64();
     int nap = 0;
     while (true) {
+        // every round loads anew
+        __asm__ __volatile__("" ::: "memory");
         uint64_t wl[VB][QM], wh[VB][QM];
 #pragma unroll
         for (int vb = 0; vb < VB; ++vb) {
@@ -1400,10 +1690,10 @@ __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0
             for (int q = 0; q < QM; ++q) {
                 const int gg = lane * Q + q;
                 const int gc = gg < Gact ? gg : 0;
-                const int64_t o = ((int64_t)gc * NVAL_MAX + v) * 2;
+                const int64_t o = (int64_t)(2 * v) * Gs + gc;
                 if (v < nv && q < Q) {
                     wl[vb][q] = __hip_atomic_load(&part[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    wh[vb][q] = __hip_atomic_load(&part[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    wh[vb][q] = __hip_atomic_load(&part[o + Gs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else {
                     wl[vb][q] = 0;
                     wh[vb][q] = 0;
@@ -1444,49 +1734,14 @@ __device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int v0
     wave_tree_sum_n<VB>(out);
 }
 
-// Wait (bounded) for the totals of values [0, nv) of this barrier, published
-// by the workgroups that reduced them (two-hop exchange), into sNode.  One
-// wave; lane l holds values l and l + 64.
-template <class Ctx>
-__device__ __forceinline__ void poll_finals(Ctx& S, const uint64_t* fin, int nv, uint32_t epoch, uint64_t budget)
-{
-    const int lane = threadIdx.x & 63;
-    double val[2] = {0.0, 0.0};
-    const uint64_t t_start = wall_clock64();
-    int nap = 0;
-    while (true) {
-        bool ok = true;
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int v = lane + 64 * r;
-            if (v < nv) {
-                const uint64_t wl = __hip_atomic_load(&fin[v * 2 + 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t wh = __hip_atomic_load(&fin[v * 2 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = ok && ((uint32_t)wl == epoch) && ((uint32_t)wh == epoch);
-                val[r] = __hiloint2double((int)(wh >> 32), (int)(wl >> 32));
-            }
-        }
-        if (__ballot(!ok) == 0) break;
-        if (__hip_atomic_load(&S.sflags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & RMP_FLAG_BARRIER)
-            break;
-        if (wall_clock64() - t_start > budget) {
-            if (lane == 0) atomicOr(&S.sflags, RMP_FLAG_BARRIER);
-            break;
-        }
-        if (++nap > 16) __builtin_amdgcn_s_sleep(2);
-    }
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-        if (lane + 64 * r < nv) S.sNode[lane + 64 * r] = val[r];
-}
-
 // Second half: wait for the other workgroups' node values of this
 // evaluation, finish the tree over workgroups, then the colloid forces
 // (solvent part, then colloid-colloid pairs in (a<b) order) into cF of
 // thread c (c < nc) and, when requested, the potential into sU.  With at
 // most 8 values and 64 workgroups (one workgroup per lane) wave 0 does all
-// of it alone, and the other waves go straight on; otherwise every wave
-// collects a share of the values and the workgroup meets at a barrier.
+// of it alone (the solo form: it reads every value of every row) and the
+// other waves go straight on; otherwise the whole workgroup takes part in
+// the sparse exchange.
 // Constants of the colloid of lane c (c < nc) used by the pair forces,
 // loaded once per interval
 struct PairLane {
@@ -1502,81 +1757,56 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const ChainCo
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nv = 3 * nc + 1;
-    constexpr int NW = NT / 64;
     const int Q = Gpad > 64 ? Gpad / 64 : 1;
     const bool solo = Q == 1 && nv <= 8;
     if (solo && wave != 0) return;
     if constexpr (NB > 1) {
         // colloid-colloid pair forces (a < b, enumerated row by row), one
-        // thread per pair: by the waves that have no exchange values to
-        // reduce while the totals arrive (wave 0 alone in the solo form)
+        // thread per pair, and the mask of the interacting pairs of each
+        // colloid (cleared with the colloid position update)
         const int np = nc * (nc - 1) / 2;
-        const int p0 = solo ? lane : t - 64, ps = solo ? 64 : NT - 64;
-        if (solo || wave >= 1)
-            for (int p = p0; p < np; p += ps) {
-                int a = 0, rem = p;
-                while (rem >= nc - 1 - a) { rem -= nc - 1 - a; ++a; }
-                const int b = a + 1 + rem;
-                pair_force(S, cc, cp, a, b, S.sPairF[p], S.sPairOn[p]);
+        const int ps = solo ? 64 : NT;
+        for (int p = t; p < np; p += ps) {
+            int a = 0, rem = p;
+            while (rem >= nc - 1 - a) { rem -= nc - 1 - a; ++a; }
+            const int b = a + 1 + rem;
+            pair_force(S, cc, cp, a, b, S.sPairF[p], S.sPairOn[p]);
+            if (S.sPairOn[p]) {
+                atomicOr(&S.sPairMask[a], 1u << b);
+                atomicOr(&S.sPairMask[b], 1u << a);
             }
+        }
     }
     if (Gact > 1) {
-        const uint32_t epoch = epoch0 + nbar;
-        const uint64_t* part = cc.part() +
-                               (int64_t)(nbar & 1) * cc.G() * NVAL_MAX * 2;
         if (solo) {
+            const uint32_t epoch = epoch0 + nbar;
+            const uint64_t* part = cc.part() + (int64_t)(nbar & 1) * cc.stride();
             double out[8];
-            poll_reduce<8, 1>(S, part, 0, 1, nv, Gact, 1, epoch, cc.budget(), out);
+            poll_reduce<8, 1>(S, part, cc.G(), 0, 1, nv, Gact, 1, epoch, cc.budget(), out);
             if (lane == 0)
 #pragma unroll
                 for (int v = 0; v < 8; ++v)
                     if (v < nv) S.sNode[v] = out[v];
         } else {
-            // two hops: workgroup g completes the tree over workgroups of
-            // the values v = g + k Gact (its waves taking turns) and
-            // publishes each total, epoch-tagged like the node values; then
-            // wave 0 collects all totals.  Each workgroup reads Gact words
-            // per value it owns plus nv totals, instead of Gact words for
-            // every value.
-            constexpr int VB = 4;
-            uint64_t* fin = cc.fin() + (int64_t)(nbar & 1) * NVAL_MAX * 2;
-            // (with the pair forces on waves 1.., wave 0 reduces this
-            // workgroup's values alone)
-            constexpr int NWR = NB > 1 ? 1 : NW;
-            const int vs = NWR * Gact;
-            for (int v0 = g + wave * Gact; wave < NWR && v0 < nv; v0 += VB * vs) {
-                double out[VB];
-                poll_reduce<VB, 4>(S, part, v0, vs, nv, Gact, Q, epoch, cc.budget(), out);
-                if (lane == 0)
-#pragma unroll
-                    for (int vb = 0; vb < VB; ++vb) {
-                        const int v = v0 + vb * vs;
-                        if (v < nv) {
-                            const uint64_t lo = ((uint64_t)(uint32_t)__double2loint(out[vb]) << 32) | epoch;
-                            const uint64_t hi = ((uint64_t)(uint32_t)__double2hiint(out[vb]) << 32) | epoch;
-                            __hip_atomic_store(&fin[v * 2 + 0], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            __hip_atomic_store(&fin[v * 2 + 1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                    }
-            }
-            if (wave == 0) poll_finals(S, fin, nv, epoch, cc.budget());
+            exchange_master(S, cc, nc, Gact, nbar, epoch0);
         }
     }
     if (solo) wave_sync();
     else __syncthreads();
     // colloid forces: solvent part, then colloid-colloid pairs in (a<b) order
     if constexpr (NB > 1) {
-        // pairs from LDS (computed at the start of the evaluation): colloid c
-        // adds them in the order of the other colloid, + for the lower index
+        // pairs from LDS: colloid c adds those that interact in the order of
+        // the other colloid, + for the lower index
         if (t < nc) {
             const int c = t;
             double F[3] = {-S.sNode[3 * c + 0], -S.sNode[3 * c + 1], -S.sNode[3 * c + 2]};
-            for (int a = 0; a < nc; ++a) {
-                if (a == c) continue;
+            uint32_t m = S.sPairMask[c];
+            while (m) {
+                const int a = __ffs(m) - 1;
+                m &= m - 1u;
                 const bool c_lo = c < a;
                 const int lo = c_lo ? c : a, hi = c_lo ? a : c;
                 const int p = lo * nc - (lo * (lo + 1)) / 2 + (hi - lo - 1);
-                if (!S.sPairOn[p]) continue;
                 for (int d = 0; d < 3; ++d) F[d] = c_lo ? F[d] + S.sPairF[p][d] : F[d] - S.sPairF[p][d];
             }
             for (int d = 0; d < 3; ++d) cF[d] = F[d];
@@ -1675,7 +1905,13 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
 
     __shared__ ChainCtx<NT, NC == 0 ? RMP_MAX_BONDS : 1> S;
     const int t = threadIdx.x;
-    if (t == 0) S.sflags = 0;
+    if (t == 0) {
+        S.sflags = 0;
+        S.sFull = 0;
+    }
+    if (t < MAXC) S.sPairMask[t] = 0u;
+    for (int r = t; r < MAX_CHAIN_G; r += NT) S.sE[r] = 0u;
+    if (t < 4) S.cEcc[t >> 1][t & 1] = cp->eps_cc[t >> 1][t & 1];
     // colloid c lives in registers of thread c (c < nc, wave 0): position,
     // velocity, force, position at the start of the interval
     double cX[3] = {0.0, 0.0, 0.0}, cV[3] = {0.0, 0.0, 0.0}, cF[3] = {0.0, 0.0, 0.0};
@@ -1700,12 +1936,17 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
             S.sXw[t][d] = colloid_image(cX[d], cc.L(d));
         }
         S.cRc2[t] = cp->rc2[t];
+        {
+            const double rr = sqrt(cp->rc2[t]) + D.cull_margin;
+            S.cCull2[t] = rr * rr;
+        }
         S.cSig2[t] = cp->sig2[t];
         S.cEpsA[t] = cp->epsA[t];
         S.cEpsB[t] = cp->epsB[t];
         S.cSigma[t] = cp->sigma[t];
         S.cCat[t] = cp->catalytic[t];
         S.cType[t] = cp->ctype[t];
+        S.cBody[t] = cp->body[t];
     }
     if (iter) {
         // bonds of the iterative RATTLE in LDS for the interval
@@ -1739,7 +1980,7 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
 
     bool valid[K];
     int64_t idx[K];
-    T x[K][3], v[K][3];
+    T x[K][3], v[K][3], x0[K][3];
     double f[K][3];
     uint8_t st[K];
     uint32_t pid[K];
@@ -1755,8 +1996,20 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
         }
         st[j] = valid[j] ? stb[idx[j]] : 0;
         pid[j] = valid[j] ? idb[idx[j]] : 0;
+        for (int d = 0; d < 3; ++d) x0[j][d] = x[j][d];
     }
     __syncthreads();
+    // this wave's colloids within reach for the interval
+    uint32_t wmask = reach_box<T, K>(S, cc, nc, valid, x);
+    const double me2 = D.cull_me * D.cull_me;
+    // Roles: with one workgroup, or in the solo form, every workgroup
+    // completes the exchange and updates the colloids itself; otherwise
+    // workgroup 0 (the master) does, and the others take the colloid
+    // positions of each MD step from its broadcast.
+    const int Qx = Gpad > 64 ? Gpad / 64 : 1;
+    const bool solo = Qx == 1 && 3 * nc + 1 <= 8;
+    const bool worker = Gact > 1 && !solo && g != 0;
+    const bool updates = !worker;
     uint32_t nbar = 0;
     // barrier epochs: unique per barrier of the replica between list
     // rebuilds (md_step + coll_step grows by n_md + 1 per interval)
@@ -1767,8 +2020,8 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
     const bool colloid_wave = t < 64;
 
     // forces at the start of the interval
-    chain_compute<T, K, NT>(S, cc, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
-    chain_collect<T, K, NT>(S, cc, cp, nc, g, Gact, Gpad, nbar, epoch0, false, cF, PL);
+    chain_compute<T, K, NT>(S, cc, cp, nc, valid, x, x0, st, f, inside, g, Gact, solo, wmask, me2, nbar, epoch0);
+    if (updates) chain_collect<T, K, NT>(S, cc, cp, nc, g, Gact, Gpad, nbar, epoch0, false, cF, PL);
     // list entries: first half kick and drift of step 0
 #pragma unroll
     for (int j = 0; j < K; ++j)
@@ -1783,7 +2036,9 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
         const int64_t md = md0 + step;
         // colloids (wave 0, in registers): half kick, drift, RATTLE
         // position stage, periodic images for the force evaluation
-        if (colloid_wave) {
+        if (worker) {
+            if (colloid_wave) await_images(S, cc, nc, nbar, epoch0);
+        } else if (colloid_wave) {
             double cXo[3];
             if (t < nc) {
                 for (int d = 0; d < 3; ++d) {
@@ -1819,11 +2074,22 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
                 rattle_pos_lane(BL, dt, cX, cV, cXo, lflags);
             }
             if (lflags) atomicOr(&S.sflags, lflags);
-            if (t < nc)
+            if (t < nc) {
                 for (int d = 0; d < 3; ++d) S.sXw[t][d] = colloid_image(cX[d], cc.L(d));
+                // a colloid beyond half the skin from its interval-start
+                // position voids the reach masks of the interval
+                const double dx = cX[0] - cX0[0], dy = cX[1] - cX0[1], dz = cX[2] - cX0[2];
+                if (dot3(dx, dy, dz, dx, dy, dz) >= D.skin_half2) S.sFull = 1u;
+                S.sPairMask[t] = 0u;
+            }
+            if (Gact > 1 && !solo) {
+                wave_sync();
+                broadcast_images(S, cc, nc, nbar, epoch0);
+            }
         }
         __syncthreads();
-        chain_compute<T, K, NT>(S, cc, cp, nc, valid, x, st, f, inside, g, Gact, nbar, epoch0);
+        chain_compute<T, K, NT>(S, cc, cp, nc, valid, x, x0, st, f, inside, g, Gact, solo, wmask, me2, nbar,
+                                epoch0);
         // while the other workgroups' sums arrive: the list entries' second
         // half kick, catalysis, and (except after the last step) the next
         // step's first half kick and drift -- each entry's own arithmetic,
@@ -1867,11 +2133,12 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
                 }
         }
         // the potential energy is an observable of the last force evaluation
-        chain_collect<T, K, NT>(S, cc, cp, nc, g, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF, PL);
+        if (updates)
+            chain_collect<T, K, NT>(S, cc, cp, nc, g, Gact, Gpad, nbar, epoch0, step == nmd - 1, cF, PL);
         // colloids (wave 0, in registers): second half kick, RATTLE
         // velocity stage, Verlet-list soundness check (displacement within
         // the interval)
-        if (colloid_wave) {
+        if (updates && colloid_wave) {
             if (t < nc)
                 for (int d = 0; d < 3; ++d) cV[d] = fma(chc, cF[d], cV[d]);
             if (iter) {

@@ -149,19 +149,22 @@ def test_autotune_caches_best_per_box_class(tmp_path):
 
     def fake_timer(params, cfg, seed, intervals):
         calls.append(cfg)
-        return 1.0 + cfg["chain_k"] + (cfg["collide_cells"] == 32) * -0.5 + (cfg["stream_block"] == 128) * 0.1
+        return 1.0 + cfg["chain_k"] + (cfg["collide_cells"] == 32) * -0.5 + (cfg["stream_ppt"] == 1) * 0.1
 
     best = autotune.tune(p, cache_path=cache, timer=fake_timer)
-    assert best == dict(chain_k=1, collide_cells=32, stream_block=256)
-    assert len(calls) == 3 * 3 * 2
+    assert best == dict(chain_k=1, collide_cells=32, stream_ppt=2)
+    npts = 1
+    for v in autotune.GRID.values():
+        npts *= len(v)
+    assert len(calls) == npts
     again = autotune.tune(p, cache_path=cache, timer=fake_timer)
-    assert again == best and len(calls) == 18            # cached
+    assert again == best and len(calls) == npts            # cached
     assert autotune.lookup(p, cache_path=cache) == best
     q = W.dimer_system(L=20, rho=5, n_md=10, seed=1)
     assert autotune.box_class(q) != autotune.box_class(p)
     assert autotune.lookup(q, cache_path=cache) == autotune.DEFAULT
     data = json.load(open(cache))
-    assert autotune.box_class(p) in data and len(data[autotune.box_class(p)]["points"]) == 18
+    assert autotune.box_class(p) in data and len(data[autotune.box_class(p)]["points"]) == npts
 
 
 def test_barrier_timeout_restarts_the_job_once():
