@@ -2852,6 +2852,7 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
                         const double xd = min_image((double)xr_[d] - s_ref[d], D.Ld[d], D.halfL[d]) + D.Ld[d];
                         gmin[d] = xd < gmin[d] ? xd : gmin[d];
                         gmax[d] = xd > gmax[d] ? xd : gmax[d];
+                        if (!(xd <= 1e300)) { gmin[d] = 0.0; gmax[d] = 1e300; }   // non-finite: no bound
                     }
                     const double vv = dot3((double)vq_[0], (double)vq_[1], (double)vq_[2],
                                            (double)vq_[0], (double)vq_[1], (double)vq_[2]);
@@ -2861,12 +2862,20 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
             }
         }
         if (cull) {
+            // wave minima and maxima by DPP (exact), then one LDS atomic per
+            // wave and value (positive doubles order like their bit patterns)
+            double vlo = gv2;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                wave_min_to(&s_box[d], gmin[d]);
-                wave_max_to(&s_box[3 + d], gmax[d]);
+            for (int d = 0; d < 3; ++d) wave_min_max(gmin[d], gmax[d]);
+            wave_min_max(vlo, gv2);
+            if (lane == 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    atomicMin((unsigned long long*)&s_box[d], (unsigned long long)__double_as_longlong(gmin[d]));
+                    atomicMax((unsigned long long*)&s_box[3 + d], (unsigned long long)__double_as_longlong(gmax[d]));
+                }
+                atomicMax((unsigned long long*)&s_box[6], (unsigned long long)__double_as_longlong(gv2));
             }
-            wave_max_to(&s_box[6], gv2);
         }
         __syncthreads();
         // ---- D: per cell (one thread each); colloid cull (second wave)
