@@ -117,6 +117,56 @@ __device__ __forceinline__ void wave_min_max(double& lo, double& hi)
     hi = h;
 }
 
+// minimum of lo and maximum of hi over the 64 lanes, for integers (same
+// pattern as wave_min_max)
+__device__ __forceinline__ void wave_min_max_i(int& lo, int& hi)
+{
+#define RMP_MMI_STEP(CTRL)                                                      \
+    {                                                                           \
+        const int ol = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);  \
+        const int oh = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);  \
+        lo = ol < lo ? ol : lo;                                                 \
+        hi = oh > hi ? oh : hi;                                                 \
+    }
+    RMP_MMI_STEP(0xB1)
+    RMP_MMI_STEP(0x4E)
+    RMP_MMI_STEP(0x141)
+    RMP_MMI_STEP(0x140)
+#undef RMP_MMI_STEP
+    int l = lo, h = hi;
+#pragma unroll
+    for (int r = 15; r < 64; r += 16) {
+        const int rl = __builtin_amdgcn_readlane(lo, r), rh = __builtin_amdgcn_readlane(hi, r);
+        l = rl < l ? rl : l;
+        h = rh > h ? rh : h;
+    }
+    lo = l;
+    hi = h;
+}
+
+// maximum of v over the 64 lanes (exact), in every lane
+__device__ __forceinline__ double wave_max_d(double v)
+{
+#define RMP_MX_STEP(CTRL)                                                       \
+    {                                                                           \
+        const double o = dpp_d<CTRL, 0xF>(v);                                   \
+        v = o > v ? o : v;                                                      \
+    }
+    RMP_MX_STEP(0xB1)
+    RMP_MX_STEP(0x4E)
+    RMP_MX_STEP(0x141)
+    RMP_MX_STEP(0x140)
+#undef RMP_MX_STEP
+    double m = v;
+#pragma unroll
+    for (int r = 15; r < 64; r += 16) {
+        const double o = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), r),
+                                          __builtin_amdgcn_readlane(__double2loint(v), r));
+        m = o > m ? o : m;
+    }
+    return m;
+}
+
 // deterministic block sum: wave butterfly, then a pairwise tree over the
 // wave sums (xor butterfly over the first NT/64 lanes of wave 0)
 template <int NT>
@@ -2487,30 +2537,6 @@ __device__ __forceinline__ bool is_candidate_masked(const RepDesc& D, const Coll
 
 constexpr int COLL_TCMAX = 64;       // cells per tile at most
 
-// wave-wide max of a non-negative double (its bit pattern orders like the
-// value), folded into an LDS word by one atomic per wave
-__device__ __forceinline__ void wave_max_to(uint64_t* dst, double v)
-{
-    uint64_t b = (uint64_t)__double_as_longlong(v);
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t o = __shfl_xor(b, m, 64);
-        b = o > b ? o : b;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)dst, (unsigned long long)b);
-}
-
-__device__ __forceinline__ void wave_min_to(uint64_t* dst, double v)
-{
-    uint64_t b = (uint64_t)__double_as_longlong(v);
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t o = __shfl_xor(b, m, 64);
-        b = o < b ? o : b;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMin((unsigned long long*)dst, (unsigned long long)b);
-}
-
 // One cell of the tile holding more particles than a collision group (rare:
 // hundreds of particles in one cell).  Its records are contiguous in the
 // staging array; the stable order is found by counting ranks of the old
@@ -2640,25 +2666,28 @@ __device__ void collide_big_cell(const RepDesc& D, const ColloidParams* cp, int 
 // groups whose particles fit the workgroup (NT threads holding PPT particles
 // each); usually the whole tile is one group.  Per group:
 //   B  each thread reads whole records of the group's slots (coalesced) and
-//      finds each slot's cell by binary search over the cell starts;
+//      looks up each slot's cell (a slot-to-cell map of the tile built at
+//      tile start; binary search over the cell starts past its end);
 //   C  it ranks its particle by old index among its cell's records (the
 //      stable order), writes position and id to the output slot of that
 //      rank, velocity and species to LDS at that slot for the per-cell sums;
 //   D  one thread per cell: sequential FP64 sums in the stable order,
 //      centre-of-mass velocity, temperature term, bulk reaction decision;
 //      one lane per colloid: is the colloid within reach of any particle of
-//      the tile (bounding box of the tile's particles, largest speed)?
+//      the tile (the box of the tile's cells, the particles' largest speed)?
 //   E  each thread rotates its particles about their cell's axis, applies
 //      the reaction, and writes velocity, species and Verlet-list flag.
-// The random axes and bulk-reaction uniforms of all cells of the tile are
-// drawn at tile start (they depend on nothing loaded), next to the loads.
-// The register file is held to 96 VGPRs with one particle per thread (five
-// waves per SIMD) and to 128 with two (four waves); a few bytes of values
-// spill in FP64.
+// The random axes and bulk-reaction uniforms of all cells of the tile, the
+// slot-to-cell map and the tile's box are made at tile start (they depend on
+// nothing loaded), next to the loads.
+// The register file is held to 96 VGPRs (five waves per SIMD) with one
+// particle per thread, or two in FP32, and to 128 (four waves) with two in
+// FP64; a few bytes of values spill.
 template <class T, int RULE, int NT, int PPT>
-__global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xcd_map)
+__global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_collide(Work w, int xcd_map)
 {
     constexpr int CAP = NT * PPT;
+    constexpr int FILLCAP = 2 * CAP;    // leading slots of the tile with their cell in s_cellof
     static_assert(CAP <= CHUNK, "a collision group spans at most two chunks");
     static_assert(NT >= 256, "the tile-start draws use the last two waves");
     int item = blockIdx.x;
@@ -2680,6 +2709,7 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
     const int lane = t & 63;
 
     __shared__ uint32_t s_start[COLL_TCMAX + 1];
+    __shared__ uint8_t s_cellof[FILLCAP];
     __shared__ uint32_t s_perm[CAP];
     __shared__ T s_v[3][CAP];
     __shared__ double s_g[3][RULE ? CAP : 1];
@@ -2690,10 +2720,9 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
     __shared__ int32_t s_flip[COLL_TCMAX];
     __shared__ uint8_t s_go[COLL_TCMAX];
     __shared__ double s_Xw[MAXC][3];
-    __shared__ uint64_t s_box[7];      // min, max of the offsets from s_ref (+ L, so positive);
-                                       // max |v|^2 (bit patterns order like the values)
-    __shared__ double s_ref[3];        // a particle of the tile: reference point of the box
-    __shared__ int32_t s_ref_set;
+    __shared__ double s_box[6];        // the tile's box: lower, upper offsets from s_ref
+    __shared__ double s_ref[3];        // lower corner of the tile's first cell (unshifted)
+    __shared__ uint64_t s_vmax2;       // max |v|^2 (bit patterns order like the values)
     __shared__ uint32_t s_cmask;
     __shared__ double sred[(NT / 64 + 1) * 4];
 
@@ -2751,8 +2780,51 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
             for (int d = 0; d < 3; ++d) s_Xw[t - 64][d] = colloid_image(rs->X[t - 64][d], D.Ld[d]);
         }
     }
-    if (t < 3) { s_box[t] = ~0ull; s_box[3 + t] = 0ull; }
-    if (t == 3) { s_box[6] = 0ull; s_cmask = 0u; s_ref_set = 0; }
+    if (cull && t < 64) {
+        // the tile's box for the colloid cull, from its cells: a cell
+        // (c0, c1, c2) of the grid shifted by s in [0, 1)^3 holds the points
+        // with c + s <= x < c + 1 + s, inside [c, c + 2) whatever the shift;
+        // cell offsets from the first cell by minimum image, so a tile
+        // across the periodic boundary stays compact
+        const uint32_t L0 = (uint32_t)D.L[0], L1 = (uint32_t)D.L[1];
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        int ref[3];
+        {
+            const uint32_t lin = (uint32_t)(D.hbits == KEY_ROW ? c0 : D.cell_of[c0]);
+            ref[0] = (int)(lin % L0);
+            ref[1] = (int)((lin / L0) % L1);
+            ref[2] = (int)(lin / (L0 * L1));
+        }
+        if (lane < ncl) {
+            const uint32_t lin = (uint32_t)(D.hbits == KEY_ROW ? c0 + lane : D.cell_of[c0 + lane]);
+            const int cc[3] = {(int)(lin % L0), (int)((lin / L0) % L1), (int)(lin / (L0 * L1))};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                int o = cc[d] - ref[d];
+                if (2 * o >= D.L[d]) o -= D.L[d];
+                else if (2 * o < -D.L[d]) o += D.L[d];
+                lo[d] = hi[d] = o;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) wave_min_max_i(lo[d], hi[d]);
+        if (lane == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                s_ref[d] = (double)ref[d];
+                s_box[d] = (double)lo[d];
+                s_box[3 + d] = (double)hi[d] + 2.0;
+            }
+        }
+    }
+    if (t < 64 && lane < ncl) {
+        // tile-local cell of each of the tile's first FILLCAP slots (the
+        // cells' slot ranges are contiguous and in order)
+        const uint32_t base = D.start[c0], a = D.start[c0 + lane], b = D.start[c0 + lane + 1];
+        const uint32_t e = b - base < (uint32_t)FILLCAP ? b - base : (uint32_t)FILLCAP;
+        for (uint32_t r = a - base; r < e; ++r) s_cellof[r] = (uint8_t)lane;
+    }
+    if (t == 64) { s_vmax2 = 0ull; s_cmask = 0u; }
     __syncthreads();
 
     const Rec<T>* stage = reinterpret_cast<const Rec<T>*>(D.stage);
@@ -2798,23 +2870,23 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
             if (j < ns) {
                 rec_get(&stage[q0 + j], xr[u], vq[u], idq[u], pj[u], sr[u]);
                 s_perm[j] = pj[u];
-                if (j == 0 && !s_ref_set) {     // the first group of the tile fixes it
-                    for (int d = 0; d < 3; ++d) s_ref[d] = (double)xr[u][d];
-                    s_ref_set = 1;
-                }
                 const uint32_t q = q0 + (uint32_t)j;
-                int lo = ga, hi = gb - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_start[mid] <= q) lo = mid; else hi = mid - 1;
+                if (q - s_start[0] < (uint32_t)FILLCAP) {
+                    lcj[u] = s_cellof[q - s_start[0]];
+                } else {
+                    int lo = ga, hi = gb - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_start[mid] <= q) lo = mid; else hi = mid - 1;
+                    }
+                    lcj[u] = lo;
                 }
-                lcj[u] = lo;
             }
         }
         __syncthreads();
         // ---- C: stable rank; position and id written at the rank's slot
         int slot[PPT];
-        double gmin[3] = {1e300, 1e300, 1e300}, gmax[3] = {0.0, 0.0, 0.0}, gv2 = 0.0;
+        double gv2 = 0.0;
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
             const int j = t + u * NT;
@@ -2822,8 +2894,11 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
             if (j < ns) {
                 const int cb = (int)(s_start[lcj[u]] - q0), ce = (int)(s_start[lcj[u] + 1] - q0);
                 const uint32_t p = pj[u];
-                int r = 0;
-                for (int q = cb; q < ce; ++q) r += s_perm[q] < p ? 1 : 0;
+                int r = 0, q = cb;
+                for (; q + 4 <= ce; q += 4)
+                    r += (s_perm[q] < p ? 1 : 0) + (s_perm[q + 1] < p ? 1 : 0) + (s_perm[q + 2] < p ? 1 : 0) +
+                         (s_perm[q + 3] < p ? 1 : 0);
+                for (; q < ce; ++q) r += s_perm[q] < p ? 1 : 0;
                 const int sl = cb + r;
                 slot[u] = sl;
                 const int64_t o = (int64_t)q0 + sl;
@@ -2842,18 +2917,9 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
                     s_g[2][sl] = D.vscale * z[2];
                 }
                 if (cull) {
-                    // the bounding box of the tile's particles (minimum-image
-                    // offsets from a particle of the tile, shifted by L to be
-                    // positive) and their largest speed vmax, for the colloid
-                    // cull: after the rotation a speed is at most
+                    // the largest speed vmax of the tile's particles, for the
+                    // colloid cull: after the rotation a speed is at most
                     // |u| + |v - u| <= 3 vmax
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const double xd = min_image((double)xr_[d] - s_ref[d], D.Ld[d], D.halfL[d]) + D.Ld[d];
-                        gmin[d] = xd < gmin[d] ? xd : gmin[d];
-                        gmax[d] = xd > gmax[d] ? xd : gmax[d];
-                        if (!(xd <= 1e300)) { gmin[d] = 0.0; gmax[d] = 1e300; }   // non-finite: no bound
-                    }
                     const double vv = dot3((double)vq_[0], (double)vq_[1], (double)vq_[2],
                                            (double)vq_[0], (double)vq_[1], (double)vq_[2]);
                     gv2 = vv > gv2 ? vv : gv2;
@@ -2862,25 +2928,14 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
             }
         }
         if (cull) {
-            // wave minima and maxima by DPP (exact), then one LDS atomic per
-            // wave and value (positive doubles order like their bit patterns)
-            double vlo = gv2;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) wave_min_max(gmin[d], gmax[d]);
-            wave_min_max(vlo, gv2);
-            if (lane == 0) {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    atomicMin((unsigned long long*)&s_box[d], (unsigned long long)__double_as_longlong(gmin[d]));
-                    atomicMax((unsigned long long*)&s_box[3 + d], (unsigned long long)__double_as_longlong(gmax[d]));
-                }
-                atomicMax((unsigned long long*)&s_box[6], (unsigned long long)__double_as_longlong(gv2));
-            }
+            // wave maximum by DPP (exact), then one LDS atomic per wave
+            // (non-negative doubles order like their bit patterns)
+            gv2 = wave_max_d(gv2);
+            if (lane == 0) atomicMax((unsigned long long*)&s_vmax2, (unsigned long long)__double_as_longlong(gv2));
         }
         __syncthreads();
         // ---- D: per cell (one thread each); colloid cull (second wave)
         for (int cl = ga + t; cl < gb; cl += NT) {
-            const int64_t cell = D.hbits == KEY_ROW ? c0 + cl : D.cell_of[c0 + cl];
             const int cb = (int)(s_start[cl] - q0), ce = (int)(s_start[cl + 1] - q0);
             const int nn = ce - cb;
             s_flip[cl] = -1;
@@ -2888,8 +2943,12 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
             // a plate) with fewer than n0 particles holds n0 - n virtual ones
             // at rest on average; only their summed momentum enters, a normal
             // vector of variance (n0 - n) kT / m per component
-            const int64_t cz = cell / ((int64_t)D.L[0] * D.L[1]);
-            const bool virt = D.walls && (cz == 0 || cz == D.L[2] - 1) && nn >= 1 && nn < D.wall_n0;
+            bool virt = false;
+            if (D.walls && nn >= 1 && nn < D.wall_n0) {
+                const int64_t cell = D.hbits == KEY_ROW ? c0 + cl : D.cell_of[c0 + cl];
+                const int64_t cz = cell / ((int64_t)D.L[0] * D.L[1]);
+                virt = cz == 0 || cz == D.L[2] - 1;
+            }
             const bool go = nn >= 2 || virt;
             s_go[cl] = go ? 1 : 0;
             int nB = 0;
@@ -2951,12 +3010,11 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
         if (cull && t >= 64 && t < 128) {
             // colloid c can reach a particle of the tile only if its reach
             // sphere, widened by the largest speed times tau, meets the
-            // particles' bounding box (minimum image per axis, margin far
-            // above rounding)
+            // tile's box (minimum image per axis, margin far above rounding)
             bool near = false;
             const int c = t - 64;
             if (c < nc) {
-                const double vmax2 = __longlong_as_double((long long)s_box[6]);
+                const double vmax2 = __longlong_as_double((long long)s_vmax2);
                 const double reach = ((3.0 * sqrt(vmax2)) * D.tau + cp->reachR[c]) * (1.0 + 1e-6) + 1e-6;
                 double r2 = 0.0;
                 bool wide = !(reach < 1e200);
@@ -2964,8 +3022,7 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
                 for (int d = 0; d < 3; ++d) {
                     // box [lo, hi] of offsets from s_ref; the colloid's offset
                     // and its periodic images: the nearest one counts
-                    const double lo = __longlong_as_double((long long)s_box[d]) - D.Ld[d];
-                    const double hi = __longlong_as_double((long long)s_box[3 + d]) - D.Ld[d];
+                    const double lo = s_box[d], hi = s_box[3 + d];
                     if (!(hi - lo < 0.5 * D.Ld[d])) { wide = true; continue; }
                     const double oc = min_image(s_Xw[c][d] - s_ref[d], D.Ld[d], D.halfL[d]);
                     double dd = 1e300;
@@ -3036,14 +3093,34 @@ __global__ __launch_bounds__(NT, PPT == 1 ? 5 : 4) void k_collide(Work w, int xc
         ga = gb;
         if (ga < ncl) __syncthreads();   // the next group reuses the LDS
     }
-    double red[4] = {t_sum, t_cells, du_sum, n_flip};
-    block_sum_n<NT, 4>(red, sred);
-    if (t == 0) {
-        D.tpart[(int64_t)tile * 4 + 0] = red[0];
-        D.tpart[(int64_t)tile * 4 + 1] = red[1];
-        D.tpart[(int64_t)tile * 4 + 2] = red[2];
-        D.tpart[(int64_t)tile * 4 + 3] = red[3];
-        D.bigmask[tile] = big;
+    // the tile's sums: the wave trees, then the waves in order (as
+    // block_sum_n).  The temperature terms live in wave 0 alone (one thread
+    // per cell, at most 64 cells) and the reaction terms only where a flip
+    // happened; a wave holding only +0.0 has the tree +0.0, which is not
+    // formed (no sum here is ever -0.0)
+    {
+        constexpr int NW = NT / 64;
+        const int wave = t >> 6;
+        double red[4] = {0.0, 0.0, 0.0, 0.0};
+        if (wave == 0) {
+            red[0] = wave_tree_sum(t_sum);
+            red[1] = wave_tree_sum(t_cells);
+        }
+        if (__ballot(n_flip != 0.0) != 0) {
+            red[2] = wave_tree_sum(du_sum);
+            red[3] = wave_tree_sum(n_flip);
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sred[wave * 4 + q] = red[q];
+        __syncthreads();
+        if (t < 4) {
+            double a = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) a = a + sred[w * 4 + t];
+            D.tpart[(int64_t)tile * 4 + t] = a;
+        }
+        if (t == 0) D.bigmask[tile] = big;
     }
 }
 
