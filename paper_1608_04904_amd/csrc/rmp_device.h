@@ -7,6 +7,26 @@
 
 namespace rmp {
 
+// A pointer typed as pointing into global memory.  Pointers read from a
+// descriptor are generic, and a generic access compiles to a flat
+// instruction, which also counts against the LDS counter: every later LDS
+// wait, and every workgroup barrier, would then wait for the memory access
+// to complete.  Accesses through a gptr compile to global instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> G(T* p)
+{
+    return (gptr<T>)p;
+}
+
+// relaxed device-scope add on global memory (the result unused: no return)
+__device__ __forceinline__ void g_add(gptr<uint32_t> p, uint32_t v)
+{
+    (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Philox4x64-10 (Salmon et al., SC'11): counter (a, b, c, 0), key (seed, tag).
 __device__ __forceinline__ void philox(uint64_t a, uint64_t b, uint64_t c,
                                        uint64_t seed, uint64_t tag, uint64_t w[4])

@@ -628,7 +628,7 @@ struct RankIssue {
     int h;                     // lane of this lane's run head
 };
 
-__device__ __forceinline__ RankIssue wave_rank_issue(uint32_t* count, uint32_t key, bool valid)
+__device__ __forceinline__ RankIssue wave_rank_issue(gptr<uint32_t> count, uint32_t key, bool valid)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t k = valid ? key : 0xffffffffu;
@@ -642,7 +642,8 @@ __device__ __forceinline__ RankIssue wave_rank_issue(uint32_t* count, uint32_t k
     RankIssue r;
     r.base = 0;
     r.h = h;
-    if (head && valid) r.base = atomicAdd(&count[key], (uint32_t)(nexth - h));
+    if (head && valid)
+        r.base = __hip_atomic_fetch_add(count + key, (uint32_t)(nexth - h), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return r;
 }
 
@@ -652,7 +653,7 @@ __device__ __forceinline__ uint32_t wave_rank_finish(const RankIssue& r)
     return __shfl(r.base, r.h, 64) + (uint32_t)(lane - r.h);
 }
 
-__device__ __forceinline__ uint32_t wave_rank(uint32_t* count, uint32_t key, bool valid)
+__device__ __forceinline__ uint32_t wave_rank(gptr<uint32_t> count, uint32_t key, bool valid)
 {
     return wave_rank_finish(wave_rank_issue(count, key, valid));
 }
@@ -735,8 +736,11 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
     const int nmd = D.n_md;
     const T dt = (T)D.dt;
     const T Lt[3] = {(T)D.Ld[0], (T)D.Ld[1], (T)D.Ld[2]};
-    T* xs[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
-    T* vs[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
+    const gptr<T> xs[3] = {G(comp<T>(D.x[cur], n, 0)), G(comp<T>(D.x[cur], n, 1)), G(comp<T>(D.x[cur], n, 2))};
+    const gptr<T> vs[3] = {G(comp<T>(D.v[cur], n, 0)), G(comp<T>(D.v[cur], n, 1)), G(comp<T>(D.v[cur], n, 2))};
+    const gptr<const uint8_t> cflag = G(D.cflag);
+    const gptr<uint64_t> keyrank = G(D.keyrank);
+    const gptr<uint32_t> count = G(D.count);
     const int span = CHUNK / wg_per_chunk;
     const int64_t base = (int64_t)chunk * CHUNK + (int64_t)sub * span;
     if (D.flow) {
@@ -745,7 +749,7 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
         for (int j0 = 0; j0 < span; j0 += blockDim.x) {
             const int64_t i = base + j0 + threadIdx.x;
             bool valid = (j0 + (int)threadIdx.x < span) && (i < n);
-            if (valid) valid = D.cflag[i] == 0;
+            if (valid) valid = cflag[i] == 0;
             uint32_t key = 0;
             if (valid) {
                 T x[3], v[3];
@@ -756,8 +760,8 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
                 for (int d = 0; d < 3; ++d) { xs[d][i] = x[d]; vs[d][i] = v[d]; }
                 key = cell_key(D, (double)x[0], (double)x[1], (double)x[2], s);
             }
-            const uint32_t rank = wave_rank(D.count, key, valid);
-            if (valid) D.keyrank[i] = ((uint64_t)key << 32) | rank;
+            const uint32_t rank = wave_rank(count, key, valid);
+            if (valid) keyrank[i] = ((uint64_t)key << 32) | rank;
         }
         return;
     }
@@ -769,7 +773,7 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
     for (int u = 0; u < PPT; ++u) {
         ii[u] = base + u * bs + threadIdx.x;
         valid[u] = (u * bs + (int)threadIdx.x < span) && (ii[u] < n);
-        if (valid[u]) valid[u] = D.cflag[ii[u]] == 0;
+        if (valid[u]) valid[u] = cflag[ii[u]] == 0;
     }
 #pragma unroll
     for (int u = 0; u < PPT; ++u)
@@ -796,14 +800,14 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
     }
     RankIssue ri[PPT];
 #pragma unroll
-    for (int u = 0; u < PPT; ++u) ri[u] = wave_rank_issue(D.count, key[u], valid[u]);
+    for (int u = 0; u < PPT; ++u) ri[u] = wave_rank_issue(count, key[u], valid[u]);
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
         const uint32_t rank = wave_rank_finish(ri[u]);
         if (valid[u]) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) xs[d][ii[u]] = x[u][d];
-            D.keyrank[ii[u]] = ((uint64_t)key[u] << 32) | rank;
+            keyrank[ii[u]] = ((uint64_t)key[u] << 32) | rank;
         }
     }
 }
@@ -2394,23 +2398,24 @@ __device__ __forceinline__ void rec_put(Rec<float>* r, const float (&x)[3], cons
     q.idx_s = idx | ((uint32_t)(st & 1u) << 31);
     *r = q;
 }
-__device__ __forceinline__ void rec_get(const Rec<double>* r, double (&x)[3], double (&v)[3],
-                                        uint32_t& id, uint32_t& idx, uint8_t& st)
+template <class RP>
+__device__ __forceinline__ void rec_get(RP r, double (&x)[3], double (&v)[3], uint32_t& id, uint32_t& idx,
+                                        uint8_t& st)
 {
-    const Rec<double> q = *r;
-    x[0] = q.x[0]; x[1] = q.x[1]; x[2] = q.x[2];
-    v[0] = q.v[0]; v[1] = q.v[1]; v[2] = q.v[2];
-    id = q.id; idx = q.idx; st = (uint8_t)q.st;
+    x[0] = r->x[0]; x[1] = r->x[1]; x[2] = r->x[2];
+    v[0] = r->v[0]; v[1] = r->v[1]; v[2] = r->v[2];
+    id = r->id; idx = r->idx; st = (uint8_t)r->st;
 }
-__device__ __forceinline__ void rec_get(const Rec<float>* r, float (&x)[3], float (&v)[3],
-                                        uint32_t& id, uint32_t& idx, uint8_t& st)
+template <class RP>
+__device__ __forceinline__ void rec_get(RP r, float (&x)[3], float (&v)[3], uint32_t& id, uint32_t& idx,
+                                        uint8_t& st)
 {
-    const Rec<float> q = *r;
-    x[0] = q.x[0]; x[1] = q.x[1]; x[2] = q.x[2];
-    v[0] = q.v[0]; v[1] = q.v[1]; v[2] = q.v[2];
-    id = q.id_f & 0x7fffffffu;
-    idx = q.idx_s & 0x7fffffffu;
-    st = (uint8_t)(((q.idx_s >> 31) & 1u) | (((q.id_f >> 31) & 1u) << 1));
+    x[0] = r->x[0]; x[1] = r->x[1]; x[2] = r->x[2];
+    v[0] = r->v[0]; v[1] = r->v[1]; v[2] = r->v[2];
+    const uint32_t id_f = r->id_f, idx_s = r->idx_s;
+    id = id_f & 0x7fffffffu;
+    idx = idx_s & 0x7fffffffu;
+    st = (uint8_t)(((idx_s >> 31) & 1u) | (((id_f >> 31) & 1u) << 1));
 }
 
 // single fields of a record (the oversized-cell path reads them one by one)
@@ -2439,11 +2444,14 @@ __global__ __launch_bounds__(256) void k_scatter(Work w)
     if (!D.active) return;
     const int64_t n = D.n;
     const int cur = (int)(D.rs->coll_step & 1);
-    const T* xs[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
-    const T* vs[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
-    const uint32_t* ids = D.id[cur];
-    const uint8_t* sts = D.st[cur];
-    Rec<T>* stage = reinterpret_cast<Rec<T>*>(D.stage);
+    const gptr<const T> xs[3] = {G(comp<T>(D.x[cur], n, 0)), G(comp<T>(D.x[cur], n, 1)),
+                                 G(comp<T>(D.x[cur], n, 2))};
+    const gptr<const T> vs[3] = {G(comp<T>(D.v[cur], n, 0)), G(comp<T>(D.v[cur], n, 1)),
+                                 G(comp<T>(D.v[cur], n, 2))};
+    const gptr<const uint32_t> ids = G(D.id[cur]);
+    const gptr<const uint8_t> sts = G(D.st[cur]);
+    const gptr<const uint64_t> keyrank = G(D.keyrank);
+    const gptr<const uint32_t> start = G(D.start);
     const int64_t base = (int64_t)chunk * CHUNK;
     // the chunk's four particles per thread: every load before the stores
     constexpr int P = CHUNK / 256;
@@ -2453,13 +2461,13 @@ __global__ __launch_bounds__(256) void k_scatter(Work w)
 #pragma unroll
     for (int u = 0; u < P; ++u) {
         ii[u] = base + u * 256 + threadIdx.x;
-        const uint64_t kr = ii[u] < n ? D.keyrank[ii[u]] : 0ull;
+        const uint64_t kr = ii[u] < n ? keyrank[ii[u]] : 0ull;
         key[u] = (uint32_t)(kr >> 32);
         rank[u] = (uint32_t)kr;
     }
     int64_t slot[P];
 #pragma unroll
-    for (int u = 0; u < P; ++u) slot[u] = ii[u] < n ? (int64_t)D.start[key[u]] + rank[u] : n;
+    for (int u = 0; u < P; ++u) slot[u] = ii[u] < n ? (int64_t)start[key[u]] + rank[u] : n;
     T x[P][3], v[P][3];
     uint32_t idv[P];
     uint8_t stv[P];
@@ -2475,8 +2483,9 @@ __global__ __launch_bounds__(256) void k_scatter(Work w)
     // 16-byte word each), so a record leaves as one contiguous request
     __shared__ Rec<T> s_out[256];
     __shared__ int64_t s_slot[256];
-    const uint4* s_out4 = reinterpret_cast<const uint4*>(s_out);
-    uint4* stage4 = reinterpret_cast<uint4*>(stage);
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4* s_out4 = reinterpret_cast<const u32x4*>(s_out);
+    const gptr<u32x4> stage4 = G(reinterpret_cast<u32x4*>(D.stage));
 #pragma unroll
     for (int u = 0; u < P; ++u) {
         if (u) __syncthreads();
@@ -2499,14 +2508,14 @@ __global__ __launch_bounds__(256) void k_scatter(Work w)
 // The particles of one collision group occupy slots [q0, q0 + ns) with
 // ns <= CHUNK, so they span the chunks c_lo = q0 / CHUNK and c_lo + 1 at
 // most: one atomic per chunk and wave.  All 64 lanes must call it.
-__device__ __forceinline__ void count_flag(uint32_t* chunk_cnt, int64_t o, bool f, int64_t c_lo)
+__device__ __forceinline__ void count_flag(gptr<uint32_t> chunk_cnt, int64_t o, bool f, int64_t c_lo)
 {
     const int64_t ch = o / CHUNK;
     const uint32_t n_lo = (uint32_t)__popcll(__ballot(f && ch == c_lo));
     const uint32_t n_hi = (uint32_t)__popcll(__ballot(f && ch != c_lo));
     if ((threadIdx.x & 63) == 0) {
-        if (n_lo) atomicAdd(&chunk_cnt[c_lo], n_lo);
-        if (n_hi) atomicAdd(&chunk_cnt[c_lo + 1], n_hi);
+        if (n_lo) g_add(chunk_cnt + c_lo, n_lo);
+        if (n_hi) g_add(chunk_cnt + c_lo + 1, n_hi);
     }
 }
 
@@ -2654,7 +2663,7 @@ __device__ void collide_big_cell(const RepDesc& D, const ColloidParams* cp, int 
             D.cflag[o] = cnd ? 1 : 0;
         }
         // the wave's slots lie in [q0 + k0, q0 + k0 + NT): at most two chunks
-        count_flag(D.chunk_cnt, o, cnd, ((int64_t)q0 + k0) / CHUNK);
+        count_flag(G(D.chunk_cnt), o, cnd, ((int64_t)q0 + k0) / CHUNK);
     }
     __syncthreads();
 }
@@ -2740,13 +2749,13 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
     // ---- A: cell starts (and the counters zeroed for the next binning);
     //         per-cell random draws; colloid images
     for (int k = t; k <= ncl; k += NT) {
-        s_start[k] = D.start[c0 + k];
-        if (k < ncl) D.count[c0 + k] = 0;
+        s_start[k] = G(D.start)[c0 + k];
+        if (k < ncl) G(D.count)[c0 + k] = 0;
     }
     if (t >= NT - 128 && t < NT - 64) {
         if constexpr (RULE == 0) {
             for (int lc = t - (NT - 128); lc < ncl; lc += 64) {
-                const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : D.cell_of[c0 + lc];
+                const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : G(D.cell_of)[c0 + lc];
                 double nax[3];
                 marsaglia_axis(D.seed, (uint64_t)coll, (uint64_t)cell, nax);
                 s_n[lc][0] = nax[0]; s_n[lc][1] = nax[1]; s_n[lc][2] = nax[2];
@@ -2755,7 +2764,7 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
     } else if (t >= NT - 64) {
         if (D.bulk_on)
             for (int lc = t - (NT - 64); lc < ncl; lc += 64) {
-                const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : D.cell_of[c0 + lc];
+                const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : G(D.cell_of)[c0 + lc];
                 uint64_t wv[4];
                 philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
                 s_b[lc][0] = u01(wv[0]);
@@ -2767,7 +2776,7 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
             // every cell of the first and last layer, used if the cell turns
             // out to be cut and under-filled
             for (int lc = t - 64; lc < ncl; lc += 64) {
-                const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : D.cell_of[c0 + lc];
+                const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : G(D.cell_of)[c0 + lc];
                 const int64_t cz = cell / ((int64_t)D.L[0] * D.L[1]);
                 if (cz == 0 || cz == D.L[2] - 1) {
                     uint64_t wv[4]; double z[3];
@@ -2777,7 +2786,7 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
                 }
             }
         } else if (t < 64 + nc) {
-            for (int d = 0; d < 3; ++d) s_Xw[t - 64][d] = colloid_image(rs->X[t - 64][d], D.Ld[d]);
+            for (int d = 0; d < 3; ++d) s_Xw[t - 64][d] = colloid_image(G(rs)->X[t - 64][d], D.Ld[d]);
         }
     }
     if (cull && t < 64) {
@@ -2790,13 +2799,13 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
         int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
         int ref[3];
         {
-            const uint32_t lin = (uint32_t)(D.hbits == KEY_ROW ? c0 : D.cell_of[c0]);
+            const uint32_t lin = (uint32_t)(D.hbits == KEY_ROW ? c0 : G(D.cell_of)[c0]);
             ref[0] = (int)(lin % L0);
             ref[1] = (int)((lin / L0) % L1);
             ref[2] = (int)(lin / (L0 * L1));
         }
         if (lane < ncl) {
-            const uint32_t lin = (uint32_t)(D.hbits == KEY_ROW ? c0 + lane : D.cell_of[c0 + lane]);
+            const uint32_t lin = (uint32_t)(D.hbits == KEY_ROW ? c0 + lane : G(D.cell_of)[c0 + lane]);
             const int cc[3] = {(int)(lin % L0), (int)((lin / L0) % L1), (int)(lin / (L0 * L1))};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -2820,18 +2829,19 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
     if (t < 64 && lane < ncl) {
         // tile-local cell of each of the tile's first FILLCAP slots (the
         // cells' slot ranges are contiguous and in order)
-        const uint32_t base = D.start[c0], a = D.start[c0 + lane], b = D.start[c0 + lane + 1];
+        const uint32_t base = G(D.start)[c0], a = G(D.start)[c0 + lane], b = G(D.start)[c0 + lane + 1];
         const uint32_t e = b - base < (uint32_t)FILLCAP ? b - base : (uint32_t)FILLCAP;
         for (uint32_t r = a - base; r < e; ++r) s_cellof[r] = (uint8_t)lane;
     }
     if (t == 64) { s_vmax2 = 0ull; s_cmask = 0u; }
     __syncthreads();
 
-    const Rec<T>* stage = reinterpret_cast<const Rec<T>*>(D.stage);
-    T* xn[3] = {comp<T>(D.x[nxt], n, 0), comp<T>(D.x[nxt], n, 1), comp<T>(D.x[nxt], n, 2)};
-    T* vn[3] = {comp<T>(D.v[nxt], n, 0), comp<T>(D.v[nxt], n, 1), comp<T>(D.v[nxt], n, 2)};
-    uint32_t* idn = D.id[nxt];
-    uint8_t* stn = D.st[nxt];
+    const gptr<const Rec<T>> stage = G(reinterpret_cast<const Rec<T>*>(D.stage));
+    const gptr<T> xn[3] = {G(comp<T>(D.x[nxt], n, 0)), G(comp<T>(D.x[nxt], n, 1)), G(comp<T>(D.x[nxt], n, 2))};
+    const gptr<T> vn[3] = {G(comp<T>(D.v[nxt], n, 0)), G(comp<T>(D.v[nxt], n, 1)), G(comp<T>(D.v[nxt], n, 2))};
+    const gptr<uint32_t> idn = G(D.id[nxt]);
+    const gptr<uint8_t> stn = G(D.st[nxt]);
+    const gptr<uint8_t> cflag = G(D.cflag);
     const double ca = D.ca, sa = D.sa, oma = 1.0 - D.ca;
 
     double t_sum = 0.0, t_cells = 0.0, du_sum = 0.0, n_flip = 0.0;
@@ -2945,7 +2955,7 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
             // vector of variance (n0 - n) kT / m per component
             bool virt = false;
             if (D.walls && nn >= 1 && nn < D.wall_n0) {
-                const int64_t cell = D.hbits == KEY_ROW ? c0 + cl : D.cell_of[c0 + cl];
+                const int64_t cell = D.hbits == KEY_ROW ? c0 + cl : G(D.cell_of)[c0 + cl];
                 const int64_t cz = cell / ((int64_t)D.L[0] * D.L[1]);
                 virt = cz == 0 || cz == D.L[2] - 1;
             }
@@ -2995,7 +3005,7 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
                 nB = s_st[cb] & 1;
             }
             if (D.bulk_on && nB > 0) {
-                const double P = D.ptable[nB < RMP_PTABLE ? nB : RMP_PTABLE - 1];
+                const double P = G(D.ptable)[nB < RMP_PTABLE ? nB : RMP_PTABLE - 1];
                 if (s_b[cl][0] < P) {
                     int jb = (int)(s_b[cl][1] * (double)nB);
                     if (jb >= nB) jb = nB - 1;
@@ -3086,9 +3096,9 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
                 stn[o] = s;
                 cnd = is_candidate_masked(D, cp, cmask, s_Xw, s, (double)xo3[0], (double)xo3[1],
                                           (double)xo3[2], (double)vt[0], (double)vt[1], (double)vt[2]);
-                D.cflag[o] = cnd ? 1 : 0;
+                cflag[o] = cnd ? 1 : 0;
             }
-            count_flag(D.chunk_cnt, o, cnd, c_lo);
+            count_flag(G(D.chunk_cnt), o, cnd, c_lo);
         }
         ga = gb;
         if (ga < ncl) __syncthreads();   // the next group reuses the LDS
@@ -3118,9 +3128,9 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
             double a = 0.0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) a = a + sred[w * 4 + t];
-            D.tpart[(int64_t)tile * 4 + t] = a;
+            G(D.tpart)[(int64_t)tile * 4 + t] = a;
         }
-        if (t == 0) D.bigmask[tile] = big;
+        if (t == 0) G(D.bigmask)[tile] = big;
     }
 }
 
