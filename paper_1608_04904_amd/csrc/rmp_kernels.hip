@@ -1132,7 +1132,7 @@ struct ChainConst {
     uint64_t budgetv;          // longest wait for the other workgroups (ticks)
     __device__ double L(int d) const { return Lv[d]; }
     __device__ double h(int d) const { return hv[d]; }
-    __device__ uint64_t* part() const { return partv; }
+    __device__ gptr<uint64_t> part() const { return (gptr<uint64_t>)partv; }
     __device__ int G() const { return Gv; }
     __device__ int64_t stride() const { return stridev; }
     __device__ double cat_prob() const { return catv; }
@@ -1407,7 +1407,7 @@ __device__ __forceinline__ void chain_compute(ChainCtx<NT, NB>& S, const ChainCo
         nbar++;
         const uint32_t epoch = epoch0 + nbar;
         const int64_t Gs = cc.G();
-        uint64_t* P = cc.part() + (int64_t)(nbar & 1) * cc.stride();
+        const gptr<uint64_t> P = cc.part() + (int64_t)(nbar & 1) * cc.stride();
         uint32_t m = 0;
         if (t < nv || t == 0)
 #pragma unroll
@@ -1517,7 +1517,7 @@ __device__ __forceinline__ void exchange_master(ChainCtx<NT, NB>& S, const Chain
     constexpr int NW = NT / 64;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint32_t epoch = epoch0 + nbar;
-    const uint64_t* P = cc.part() + (int64_t)(nbar & 1) * cc.stride();
+    const gptr<const uint64_t> P = cc.part() + (int64_t)(nbar & 1) * cc.stride();
     const int nv = 3 * nc + 1;
     const uint64_t t_start = wall_clock64();
     // passes over chunks of XTAB_V values and of XTAB_R rows of the table
@@ -1577,7 +1577,7 @@ __device__ __forceinline__ void exchange_master(ChainCtx<NT, NB>& S, const Chain
                             }
                             rr[k] = lo;
                             ss[k] = i - (int)S.sOff[lo];
-                            const uint64_t* row = P + (int64_t)(r0 + lo) * ROWW;
+                            const gptr<const uint64_t> row = P + (int64_t)(r0 + lo) * ROWW;
                             hw[k] = __hip_atomic_load(&row[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             if (ss[k] > 0) {
                                 wl[k] = __hip_atomic_load(&row[2 * ss[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1654,7 +1654,7 @@ __device__ __forceinline__ void broadcast_images(ChainCtx<NT, NB>& S, const Chai
 {
     const int lane = threadIdx.x & 63;
     const uint32_t epoch = epoch0 + nbar;
-    uint64_t* B = cc.part() + (int64_t)(nbar & 1) * cc.stride() + cc.G() * (int64_t)ROWW;
+    const gptr<uint64_t> B = cc.part() + (int64_t)(nbar & 1) * cc.stride() + cc.G() * (int64_t)ROWW;
     for (int k = lane; k < 3 * nc; k += 64) {
         const double val = S.sXw[k / 3][k % 3];
         const uint64_t lo = ((uint64_t)(uint32_t)__double2loint(val) << 32) | epoch;
@@ -1676,7 +1676,7 @@ __device__ __forceinline__ void await_images(ChainCtx<NT, NB>& S, const ChainCon
 {
     const int lane = threadIdx.x & 63;
     const uint32_t epoch = epoch0 + nbar;
-    const uint64_t* B = cc.part() + (int64_t)(nbar & 1) * cc.stride() + cc.G() * (int64_t)ROWW;
+    const gptr<const uint64_t> B = cc.part() + (int64_t)(nbar & 1) * cc.stride() + cc.G() * (int64_t)ROWW;
     const uint64_t t_start = wall_clock64();
     int nap = 0;
     uint64_t fw = 0;
@@ -1723,7 +1723,7 @@ __device__ __forceinline__ void await_images(ChainCtx<NT, NB>& S, const ChainCon
 // that exist are loaded (wave-uniform guards): a co-resident workgroup that
 // is still computing must not be starved by polling traffic.
 template <int VB, int QM, class Ctx>
-__device__ __forceinline__ void poll_reduce(Ctx& S, const uint64_t* part, int64_t Gs, int v0, int vs, int nv,
+__device__ __forceinline__ void poll_reduce(Ctx& S, gptr<const uint64_t> part, int64_t Gs, int v0, int vs, int nv,
                                             int Gact, int Q, uint32_t epoch, uint64_t budget, double (&out)[VB])
 {
     const int lane = threadIdx.x & 63;
@@ -1834,7 +1834,7 @@ __device__ __forceinline__ void chain_collect(ChainCtx<NT, NB>& S, const ChainCo
     if (Gact > 1) {
         if (solo) {
             const uint32_t epoch = epoch0 + nbar;
-            const uint64_t* part = cc.part() + (int64_t)(nbar & 1) * cc.stride();
+            const gptr<const uint64_t> part = cc.part() + (int64_t)(nbar & 1) * cc.stride();
             double out[8];
             poll_reduce<8, 1>(S, part, cc.G(), 0, 1, nv, Gact, 1, epoch, cc.budget(), out);
             if (lane == 0)
@@ -2027,10 +2027,11 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
     const int64_t md0 = rs->md_step;
     const int nmd = D.n_md;
     const int64_t n = D.n;
-    T* xb[3] = {comp<T>(D.x[cur], n, 0), comp<T>(D.x[cur], n, 1), comp<T>(D.x[cur], n, 2)};
-    T* vb[3] = {comp<T>(D.v[cur], n, 0), comp<T>(D.v[cur], n, 1), comp<T>(D.v[cur], n, 2)};
-    uint8_t* stb = D.st[cur];
-    const uint32_t* idb = D.id[cur];
+    const gptr<T> xb[3] = {G(comp<T>(D.x[cur], n, 0)), G(comp<T>(D.x[cur], n, 1)), G(comp<T>(D.x[cur], n, 2))};
+    const gptr<T> vb[3] = {G(comp<T>(D.v[cur], n, 0)), G(comp<T>(D.v[cur], n, 1)), G(comp<T>(D.v[cur], n, 2))};
+    const gptr<uint8_t> stb = G(D.st[cur]);
+    const gptr<const uint32_t> idb = G(D.id[cur]);
+    const gptr<const uint32_t> cand = G(D.cand_idx);
 
     bool valid[K];
     int64_t idx[K];
@@ -2043,7 +2044,7 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
     for (int j = 0; j < K; ++j) {
         int64_t pos = (int64_t)g * B + (int64_t)t * K + j;
         valid[j] = pos < ncand;
-        idx[j] = valid[j] ? (int64_t)D.cand_idx[pos] : 0;
+        idx[j] = valid[j] ? (int64_t)cand[pos] : 0;
         for (int d = 0; d < 3; ++d) {
             x[j][d] = valid[j] ? xb[d][idx[j]] : (T)0;
             v[j][d] = valid[j] ? vb[d][idx[j]] : (T)0;
@@ -2233,16 +2234,16 @@ __device__ __forceinline__ void chain_body(Work w, int g, const RepDesc& D, cons
         }
         stb[i] = st[j];
         uint32_t key = cell_key(D, (double)x[j][0], (double)x[j][1], (double)x[j][2], s3);
-        uint32_t rank = atomicAdd(&D.count[key], 1u);
-        D.keyrank[i] = ((uint64_t)key << 32) | rank;
+        const uint32_t rank = __hip_atomic_fetch_add(G(D.count) + key, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        G(D.keyrank)[i] = ((uint64_t)key << 32) | rank;
     }
     // reaction bookkeeping of this workgroup (combined after the collision)
     __shared__ double sred[NT / 64 + 1];
     eu = block_sum<NT>(eu, sred);
     ef = block_sum<NT>(ef, sred);
     if (t == 0) {
-        D.epart[(int64_t)g * 2 + 0] = eu;
-        D.epart[(int64_t)g * 2 + 1] = ef;
+        G(D.epart)[(int64_t)g * 2 + 0] = eu;
+        G(D.epart)[(int64_t)g * 2 + 1] = ef;
         if (S.sflags) atomicOr(&rs->flags, S.sflags);
     }
     if (g == 0) {
