@@ -769,19 +769,23 @@ __global__ __launch_bounds__(256) void k_stream_bin(Work w, int wg_per_chunk)
     int64_t ii[PPT];
     T x[PPT][3], v[PPT][3];
     const int bs = (int)blockDim.x;
+    // the flag and the state are loaded side by side, so one memory latency
+    // precedes the drifts (a list entry's state, which the MD chain on the
+    // side stream may be writing meanwhile, is loaded and never used)
+    uint8_t fl[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
         ii[u] = base + u * bs + threadIdx.x;
         valid[u] = (u * bs + (int)threadIdx.x < span) && (ii[u] < n);
-        if (valid[u]) valid[u] = cflag[ii[u]] == 0;
-    }
-#pragma unroll
-    for (int u = 0; u < PPT; ++u)
+        fl[u] = valid[u] ? cflag[ii[u]] : (uint8_t)1;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             x[u][d] = valid[u] ? xs[d][ii[u]] : (T)0;
             v[u][d] = valid[u] ? vs[d][ii[u]] : (T)0;
         }
+    }
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) valid[u] = valid[u] && fl[u] == 0;
     uint32_t key[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
