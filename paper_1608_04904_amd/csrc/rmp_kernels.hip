@@ -1174,11 +1174,11 @@ struct ChainCtx {
     double sNode[NVAL_MAX];
     uint32_t sWhit[NT / 64];   // colloids that some entry of the wave is within cut-off of
     // master of the multi-workgroup exchange: the colloids each row listed
-    // at the last look, the rows' first slots, and a chunk of the values by
-    // value and row
+    // at the last look, a chunk of the values by row and value, and the
+    // trees' partial sums of each wave
     uint32_t sE[MAX_CHAIN_G];
-    uint32_t sOff[XTAB_R + 1];
-    double sTab[XTAB_V][XTAB_R];
+    double sTab[XTAB_R][XTAB_V];
+    double sPart[NT / 64][XTAB_V];
     uint32_t sPairMask[MAXC];  // colloid c: bit a set when the pair (c, a) interacts
     uint32_t sFull;            // a colloid left its interval-start reach margin: no cull
     // colloid-colloid pairs (a < b) of the current positions: force on the
@@ -1498,14 +1498,15 @@ __device__ __forceinline__ uint32_t reach_box(const ChainCtx<NT, NB>& S, const C
 // words tagged with the epoch.  The node value of an unlisted colloid is
 // exactly +0.0 (a tree of zeros), so it is not sent.  The master reads the
 // rows in slots of two words (slot 0 the header, 1 the potential, 2 + 3j + d
-// component d of the j-th listed colloid), expecting the colloids each row
-// listed at the last look (sE); a round is repeated until every header is
-// current and lists what was expected and every slot read is current.  The
-// values are then spread into a table by value and row, and each value is
-// summed over the rows with the wave tree of each group of 64 rows, the
-// groups pairwise (the same tree as over all rows at once).  The master
-// alone then updates the colloids and broadcasts their positions
-// (broadcast_images / await_images).
+// component d of the j-th listed colloid), a fixed group of NT / XTAB_R
+// threads per row, expecting the colloids each row listed at the last look
+// (sE); a round is repeated until every header is current and lists what
+// was expected and every slot read is current.  The values go into a table
+// by row and value; each value is then summed over the rows in the balanced
+// binary tree (the wave w of NW takes a block of rows, the blocks pairwise),
+// an entry the final round did not list counting as +0.0.  The master alone
+// then updates the colloids and broadcasts their positions (broadcast_images
+// / await_images).
 constexpr int XSLOTS = 4;      // slots per thread and batch of the master's reads
 
 __device__ __forceinline__ int nth_bit(uint32_t m, int j)
@@ -1514,105 +1515,97 @@ __device__ __forceinline__ int nth_bit(uint32_t m, int j)
     return __ffs(m) - 1;
 }
 
+// Balanced binary tree over N (a power of two) values get(0..N-1), formed
+// in one pass as a binary counter: the partial sum of each complete block of
+// 2^k values is kept until its sibling block is complete.
+template <int N, class F>
+__device__ __forceinline__ double tree_sum(F get)
+{
+    constexpr int LG = N <= 1 ? 0 : N <= 2 ? 1 : N <= 4 ? 2 : N <= 8 ? 3 : N <= 16 ? 4 : N <= 32 ? 5 : N <= 64 ? 6 : 7;
+    static_assert((1 << LG) == N, "a power of two up to 128");
+    double st[LG + 1];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double c = get(r);
+        int lvl = 0;
+#pragma unroll
+        for (int b = 1; b < N; b <<= 1) {
+            if (!(r & b)) break;
+            c = st[lvl] + c;
+            ++lvl;
+        }
+        st[lvl] = c;
+    }
+    return st[LG];
+}
+
 template <int NT, int NB>
 __device__ __forceinline__ void exchange_master(ChainCtx<NT, NB>& S, const ChainConst& cc, int nc, int Gact,
                                                 uint32_t nbar, uint32_t epoch0)
 {
     constexpr int NW = NT / 64;
+    constexpr int TPR = NT / XTAB_R;          // threads per row
+    constexpr int RB = XTAB_R / NW;           // rows per wave in the trees
+    static_assert(TPR >= 1 && (64 % TPR) == 0 && RB >= 1, "row groups within a wave");
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint32_t epoch = epoch0 + nbar;
     const gptr<const uint64_t> P = cc.part() + (int64_t)(nbar & 1) * cc.stride();
     const int nv = 3 * nc + 1;
     const uint64_t t_start = wall_clock64();
+    const int rt = t / TPR, sub = t - rt * TPR;   // this thread's row of the chunk, place in its group
     // passes over chunks of XTAB_V values and of XTAB_R rows of the table
     for (int v0 = 0; v0 < nv; v0 += XTAB_V)
         for (int r0 = 0; r0 < Gact; r0 += XTAB_R) {
             const int nr = Gact - r0 < XTAB_R ? Gact - r0 : XTAB_R;
+            const bool rv = rt < nr;
+            const gptr<const uint64_t> row = P + (int64_t)(r0 + (rv ? rt : 0)) * ROWW;
             int nap = 0;
             while (true) {
                 __asm__ __volatile__("" ::: "memory");
-                // slot offsets of the rows (2 + 3 m slots each), one lane per
-                // row, the exclusive scan over the rows in order
-                if (wave == 0) {
-                    constexpr int RPL = (XTAB_R + 63) / 64;     // rows per lane
-                    uint32_t cnt[RPL], sum = 0;
-#pragma unroll
-                    for (int q = 0; q < RPL; ++q) {
-                        const int r = lane * RPL + q;
-                        cnt[q] = r < nr ? 2u + 3u * (uint32_t)__popc(S.sE[r0 + r]) : 0u;
-                        sum += cnt[q];
-                    }
-                    uint32_t inc = sum;
-#pragma unroll
-                    for (int o = 1; o < 64; o <<= 1) {
-                        const uint32_t y = __shfl_up(inc, o, 64);
-                        if (lane >= o) inc += y;
-                    }
-                    uint32_t off = inc - sum;
-#pragma unroll
-                    for (int q = 0; q < RPL; ++q) {
-                        const int r = lane * RPL + q;
-                        if (r < nr) S.sOff[r] = off;
-                        off += cnt[q];
-                    }
-                    if (lane == 63) S.sOff[nr] = inc;
-                }
-                // the table of this chunk starts at +0.0 (unlisted values)
-                for (int k = t; k < XTAB_V * XTAB_R; k += NT) (&S.sTab[0][0])[k] = 0.0;
-                __syncthreads();
-                const int T = (int)S.sOff[nr];
+                const uint32_t e = rv ? S.sE[r0 + rt] : 0u;
+                const int ns = rv ? 2 + 3 * __popc(e) : 0;       // slots of the row
                 int ok = 1;
-                for (int base = 0; base < T; base += XSLOTS * NT) {
-                    uint64_t hw[XSLOTS], wl[XSLOTS], wh[XSLOTS];
-                    int rr[XSLOTS], ss[XSLOTS];
+                uint32_t mnew = e;
+                for (int s0 = sub; s0 < ns; s0 += XSLOTS * TPR) {
+                    uint64_t wl[XSLOTS], wh[XSLOTS];
 #pragma unroll
                     for (int k = 0; k < XSLOTS; ++k) {
-                        const int i = base + t + k * NT;
-                        rr[k] = -1;
-                        ss[k] = 0;
-                        hw[k] = wl[k] = wh[k] = 0ull;
-                        if (i < T) {
-                            // the row holding slot i: the last r with sOff[r] <= i
-                            int lo = 0, hi = nr - 1;
-                            while (lo < hi) {
-                                const int mid = (lo + hi + 1) >> 1;
-                                if ((int)S.sOff[mid] <= i) lo = mid;
-                                else hi = mid - 1;
-                            }
-                            rr[k] = lo;
-                            ss[k] = i - (int)S.sOff[lo];
-                            const gptr<const uint64_t> row = P + (int64_t)(r0 + lo) * ROWW;
-                            hw[k] = __hip_atomic_load(&row[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            if (ss[k] > 0) {
-                                wl[k] = __hip_atomic_load(&row[2 * ss[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                wh[k] = __hip_atomic_load(&row[2 * ss[k] + 1], __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                            }
+                        const int sl = s0 + k * TPR;
+                        wl[k] = wh[k] = 0ull;
+                        if (sl < ns) {
+                            // slot 0: the header word; slot s > 0: words 2s, 2s + 1
+                            wl[k] = __hip_atomic_load(&row[sl == 0 ? 0 : 2 * sl], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                            if (sl > 0)
+                                wh[k] = __hip_atomic_load(&row[2 * sl + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         }
                     }
 #pragma unroll
                     for (int k = 0; k < XSLOTS; ++k) {
-                        if (rr[k] < 0) continue;
-                        const int r = rr[k], s = ss[k];
-                        const bool cur = (uint32_t)hw[k] == epoch;
-                        const uint32_t m = (uint32_t)(hw[k] >> 32);
-                        const uint32_t e = S.sE[r0 + r];
-                        ok &= (cur && m == e) ? 1 : 0;
-                        if (s > 0) {
-                            ok &= ((uint32_t)wl[k] == epoch && (uint32_t)wh[k] == epoch) ? 1 : 0;
-                            // value index of the slot
-                            int v = 3 * nc;
-                            if (s >= 2) {
-                                const int j = (s - 2) / 3, d = (s - 2) - 3 * j;
-                                v = 3 * nth_bit(e, j) + d;
-                            }
-                            if (v >= v0 && v < v0 + XTAB_V)
-                                S.sTab[v - v0][r] = __hiloint2double((int)(wh[k] >> 32), (int)(wl[k] >> 32));
-                        } else if (cur && m != e) {
-                            S.sE[r0 + r] = m;      // look for the listed colloids next round
+                        const int sl = s0 + k * TPR;
+                        if (sl >= ns) continue;
+                        if (sl == 0) {
+                            const bool cur = (uint32_t)wl[k] == epoch;
+                            const uint32_t m = (uint32_t)(wl[k] >> 32);
+                            ok &= (cur && m == e) ? 1 : 0;
+                            if (cur) mnew = m;
+                            continue;
                         }
+                        ok &= ((uint32_t)wl[k] == epoch && (uint32_t)wh[k] == epoch) ? 1 : 0;
+                        // value index of the slot
+                        int v = 3 * nc;
+                        if (sl >= 2) {
+                            const int j = (sl - 2) / 3, d = (sl - 2) - 3 * j;
+                            v = 3 * nth_bit(e, j) + d;
+                        }
+                        if (v >= v0 && v < v0 + XTAB_V)
+                            S.sTab[rt][v - v0] = __hiloint2double((int)(wh[k] >> 32), (int)(wl[k] >> 32));
                     }
                 }
+                // the row's header thread: look for the listed colloids next
+                // round (the row's threads share a wave, so every one of them
+                // read e above)
+                if (rv && sub == 0 && mnew != e) S.sE[r0 + rt] = mnew;
                 if (__syncthreads_and(ok)) break;
                 // the time budget, decided for the workgroup by thread 0; once
                 // given up (RMP_FLAG_BARRIER) later barriers do not wait
@@ -1622,27 +1615,26 @@ __device__ __forceinline__ void exchange_master(ChainCtx<NT, NB>& S, const Chain
                 if (S.sflags & RMP_FLAG_BARRIER) break;
                 if (++nap > 16) __builtin_amdgcn_s_sleep(2);
             }
-            // trees: wave w takes the values v0 + w, v0 + w + NW, ...; lane l
-            // rows l and l + 64 of the chunk
-            for (int vb = wave; vb < XTAB_V && v0 + vb < nv; vb += 4 * NW) {
-                double a[4][2];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int vv = vb + i * NW;
-                    const bool use = vv < XTAB_V && v0 + vv < nv;
-                    a[i][0] = use ? S.sTab[use ? vv : 0][lane] : 0.0;
-                    a[i][1] = use ? S.sTab[use ? vv : 0][lane + 64] : 0.0;
-                }
-                wave_tree_sum_n<8>(reinterpret_cast<double(&)[8]>(a));
-                if (lane == 0)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int vv = vb + i * NW;
-                        if (vv < XTAB_V && v0 + vv < nv) {
-                            const double tot = a[i][0] + a[i][1];
-                            S.sNode[v0 + vv] = r0 == 0 ? tot : S.sNode[v0 + vv] + tot;
-                        }
-                    }
+            // trees: lane l the value v0 + l; wave w the rows [w RB, (w + 1) RB)
+            // of the chunk, then wave 0 the NW blocks pairwise.  An entry of a
+            // row past Gact, or of a colloid the row did not list, is +0.0.
+            const int nvc = nv - v0 < XTAB_V ? nv - v0 : XTAB_V;
+            if (lane < nvc) {
+                const int v = v0 + lane;
+                const bool isU = v == 3 * nc;
+                const int c = v / 3;
+                const int rb = wave * RB;
+                const double part = tree_sum<RB>([&](int q) {
+                    const int r = rb + q;
+                    const bool listed = r < nr && (isU || ((S.sE[r0 + r] >> c) & 1u) != 0u);
+                    return listed ? S.sTab[r][lane] : 0.0;
+                });
+                S.sPart[wave][lane] = part;
+            }
+            __syncthreads();
+            if (wave == 0 && lane < nvc) {
+                const double tot = tree_sum<NW>([&](int w) { return S.sPart[w][lane]; });
+                S.sNode[v0 + lane] = r0 == 0 ? tot : S.sNode[v0 + lane] + tot;
             }
             // the next chunk rewrites the table only after every wave has read it
             __syncthreads();
