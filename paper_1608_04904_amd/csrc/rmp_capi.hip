@@ -229,7 +229,8 @@ struct rmp_batch {
     RepDesc* d_desc = nullptr;
     int32_t* d_prefix[6] = {};
     uint32_t* d_tick = nullptr;     // chain work-list tickets (two counters)
-    int32_t chain_resident[5] = {}; // chain workgroups the device holds at once, per shape
+    int32_t chain_resident[2][5] = {}; // chain workgroups the device holds at once, per shape:
+                                       // generic variant, one- or two-colloid variant
     int32_t nc_common = -1;         // colloid count shared by every occupied slot, -1 if mixed
     std::vector<Replica> reps;
     std::vector<RepDesc> hdesc;
@@ -346,9 +347,38 @@ int chain_groups(const rmp_batch* b, int k, int nt)
     return (int)std::min<int64_t>(total, INT32_MAX);
 }
 
+// workgroups per compute unit of each MD-chain shape (per[0]: the generic
+// variant, per[1]: the fewer of the one- and two-colloid variants)
+template <class T>
+hipError_t occupancy_of(int (&per)[2][5])
+{
+    hipError_t e = hipSuccess;
+    int one[5] = {};
+#define RMP_OCC(DST, K, NT, NC)                                                                     \
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&(DST), k_chain<T, K, false, NC, NT>, NT, 0);
+    RMP_OCC(per[0][0], 1, 256, 0) RMP_OCC(per[0][1], 2, 256, 0) RMP_OCC(per[0][2], 4, 256, 0)
+    RMP_OCC(per[0][3], 1, 512, 0) RMP_OCC(per[0][4], 2, 512, 0)
+    RMP_OCC(per[1][0], 1, 256, 2) RMP_OCC(per[1][1], 2, 256, 2) RMP_OCC(per[1][2], 4, 256, 2)
+    RMP_OCC(per[1][3], 1, 512, 2) RMP_OCC(per[1][4], 2, 512, 2)
+    RMP_OCC(one[0], 1, 256, 1) RMP_OCC(one[1], 2, 256, 1) RMP_OCC(one[2], 4, 256, 1)
+    RMP_OCC(one[3], 1, 512, 1) RMP_OCC(one[4], 2, 512, 1)
+#undef RMP_OCC
+    for (int q = 0; q < 5; ++q) per[1][q] = std::min(per[1][q], one[q]);
+    return e;
+}
+
+// colloid count of the MD-chain variant: the one common to every occupied
+// slot when it is 1 or 2 (unrolled variants, with a smaller exchange table
+// and so more workgroups per compute unit), else 0 (the generic one, also
+// for a mix or an iterative RATTLE)
+int chain_nc(const rmp_batch* b)
+{
+    return !b->any_iterative && (b->nc_common == 1 || b->nc_common == 2) ? b->nc_common : 0;
+}
+
 int chain_resident_of(const rmp_batch* b, int q)
 {
-    return b->tun.chain_resident > 0 ? b->tun.chain_resident : b->chain_resident[q];
+    return b->tun.chain_resident > 0 ? b->tun.chain_resident : b->chain_resident[chain_nc(b) ? 1 : 0][q];
 }
 
 // 256-thread workgroups: the tuned entries per thread, raised until every
@@ -743,7 +773,9 @@ template <class T, int K, int NT>
 void launch_chain_shape(rmp_batch* b, hipStream_t s, dim3 g, bool ticket, int nc, const Work& w)
 {
     const dim3 blk(NT);
-    if (ticket) hipLaunchKernelGGL((k_chain<T, K, true, 0, NT>), g, blk, 0, s, w);
+    if (ticket && nc == 2) hipLaunchKernelGGL((k_chain<T, K, true, 2, NT>), g, blk, 0, s, w);
+    else if (ticket && nc == 1) hipLaunchKernelGGL((k_chain<T, K, true, 1, NT>), g, blk, 0, s, w);
+    else if (ticket) hipLaunchKernelGGL((k_chain<T, K, true, 0, NT>), g, blk, 0, s, w);
     else if (nc == 2) hipLaunchKernelGGL((k_chain<T, K, false, 2, NT>), g, blk, 0, s, w);
     else if (nc == 1) hipLaunchKernelGGL((k_chain<T, K, false, 1, NT>), g, blk, 0, s, w);
     else hipLaunchKernelGGL((k_chain<T, K, false, 0, NT>), g, blk, 0, s, w);
@@ -755,12 +787,9 @@ rmp_status launch_chain(rmp_batch* b, hipStream_t s)
     Timer tm(b, KN_CHAIN, s);
     const ChainShape cs = chain_shape_of(b);
     const dim3 g(b->totals[PF_CHAIN]);
+    const int nc = chain_nc(b);
     // more workgroups than the device holds at once: ticketed work list
-    const bool ticket = b->totals[PF_CHAIN] > b->chain_resident[cs.q];
-    // colloid count common to every occupied slot: 1 or 2 have unrolled
-    // variants, anything else (or a mix, or an iterative RATTLE) the
-    // generic one
-    const int nc = !b->any_iterative && (b->nc_common == 1 || b->nc_common == 2) ? b->nc_common : 0;
+    const bool ticket = b->totals[PF_CHAIN] > b->chain_resident[nc ? 1 : 0][cs.q];
     Work w = work(b, PF_CHAIN);
     // small launches: the chain's dependent steps are the whole critical
     // path, so its waves take issue priority over the streaming kernel that
@@ -1055,21 +1084,16 @@ rmp_status batch_init(rmp_batch* b, int32_t nslots, int32_t precision, void* ctl
         rmp_status sst = take_scratch_address(dev);
         if (sst != RMP_OK) return sst;
         HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        int per[5] = {0, 0, 0, 0, 0};
+        // per shape, for the generic and the one- or two-colloid variants
+        // (the ticketed instantiations use the same resources)
+        int per[2][5] = {};
         if (precision == 64) {
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<double, 1, false, 0, 256>, 256, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<double, 2, false, 0, 256>, 256, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<double, 4, false, 0, 256>, 256, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[3], k_chain<double, 1, false, 0, 512>, 512, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[4], k_chain<double, 2, false, 0, 512>, 512, 0));
+            HIPCHK(occupancy_of<double>(per));
         } else {
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_chain<float, 1, false, 0, 256>, 256, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_chain<float, 2, false, 0, 256>, 256, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_chain<float, 4, false, 0, 256>, 256, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[3], k_chain<float, 1, false, 0, 512>, 512, 0));
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[4], k_chain<float, 2, false, 0, 512>, 512, 0));
+            HIPCHK(occupancy_of<float>(per));
         }
-        for (int q = 0; q < 5; ++q) b->chain_resident[q] = std::max(1, per[q]) * std::max(1, ncu);
+        for (int v = 0; v < 2; ++v)
+            for (int q = 0; q < 5; ++q) b->chain_resident[v][q] = std::max(1, per[v][q]) * std::max(1, ncu);
     }
     b->reps.assign(nslots, Replica{});
     b->hdesc.assign(nslots, RepDesc{});

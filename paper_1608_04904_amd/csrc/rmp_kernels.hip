@@ -1174,11 +1174,13 @@ struct ChainCtx {
     double sNode[NVAL_MAX];
     uint32_t sWhit[NT / 64];   // colloids that some entry of the wave is within cut-off of
     // master of the multi-workgroup exchange: the colloids each row listed
-    // at the last look, a chunk of the values by row and value, and the
-    // trees' partial sums of each wave
+    // at the last look, a chunk of XV values by row and value, and the
+    // trees' partial sums of each wave (the variants for one or two colloids
+    // have at most 7 values)
+    static constexpr int XV = NB > 1 ? XTAB_V : 8;
     uint32_t sE[MAX_CHAIN_G];
-    double sTab[XTAB_R][XTAB_V];
-    double sPart[NT / 64][XTAB_V];
+    double sTab[XTAB_R][XV];
+    double sPart[NT / 64][XV];
     uint32_t sPairMask[MAXC];  // colloid c: bit a set when the pair (c, a) interacts
     uint32_t sFull;            // a colloid left its interval-start reach margin: no cull
     // colloid-colloid pairs (a < b) of the current positions: force on the
@@ -1546,6 +1548,7 @@ __device__ __forceinline__ void exchange_master(ChainCtx<NT, NB>& S, const Chain
     constexpr int NW = NT / 64;
     constexpr int TPR = NT / XTAB_R;          // threads per row
     constexpr int RB = XTAB_R / NW;           // rows per wave in the trees
+    constexpr int XV = ChainCtx<NT, NB>::XV;  // values per table chunk
     static_assert(TPR >= 1 && (64 % TPR) == 0 && RB >= 1, "row groups within a wave");
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint32_t epoch = epoch0 + nbar;
@@ -1553,8 +1556,8 @@ __device__ __forceinline__ void exchange_master(ChainCtx<NT, NB>& S, const Chain
     const int nv = 3 * nc + 1;
     const uint64_t t_start = wall_clock64();
     const int rt = t / TPR, sub = t - rt * TPR;   // this thread's row of the chunk, place in its group
-    // passes over chunks of XTAB_V values and of XTAB_R rows of the table
-    for (int v0 = 0; v0 < nv; v0 += XTAB_V)
+    // passes over chunks of XV values and of XTAB_R rows of the table
+    for (int v0 = 0; v0 < nv; v0 += XV)
         for (int r0 = 0; r0 < Gact; r0 += XTAB_R) {
             const int nr = Gact - r0 < XTAB_R ? Gact - r0 : XTAB_R;
             const bool rv = rt < nr;
@@ -1598,7 +1601,7 @@ __device__ __forceinline__ void exchange_master(ChainCtx<NT, NB>& S, const Chain
                             const int j = (sl - 2) / 3, d = (sl - 2) - 3 * j;
                             v = 3 * nth_bit(e, j) + d;
                         }
-                        if (v >= v0 && v < v0 + XTAB_V)
+                        if (v >= v0 && v < v0 + XV)
                             S.sTab[rt][v - v0] = __hiloint2double((int)(wh[k] >> 32), (int)(wl[k] >> 32));
                     }
                 }
@@ -1618,7 +1621,7 @@ __device__ __forceinline__ void exchange_master(ChainCtx<NT, NB>& S, const Chain
             // trees: lane l the value v0 + l; wave w the rows [w RB, (w + 1) RB)
             // of the chunk, then wave 0 the NW blocks pairwise.  An entry of a
             // row past Gact, or of a colloid the row did not list, is +0.0.
-            const int nvc = nv - v0 < XTAB_V ? nv - v0 : XTAB_V;
+            const int nvc = nv - v0 < XV ? nv - v0 : XV;
             if (lane < nvc) {
                 const int v = v0 + lane;
                 const bool isU = v == 3 * nc;
@@ -3421,7 +3424,9 @@ __global__ __launch_bounds__(256) void k_msd(Analysis* A, int32_t max_lag)
     template __global__ void k_chain<T, K, false, 0, NT>(Work);                  \
     template __global__ void k_chain<T, K, false, 1, NT>(Work);                  \
     template __global__ void k_chain<T, K, false, 2, NT>(Work);                  \
-    template __global__ void k_chain<T, K, true, 0, NT>(Work);
+    template __global__ void k_chain<T, K, true, 0, NT>(Work);                   \
+    template __global__ void k_chain<T, K, true, 1, NT>(Work);                   \
+    template __global__ void k_chain<T, K, true, 2, NT>(Work);
 
 #define RMP_INST(T)                                                              \
     template __global__ void k_init<T>(const RepDesc*);                          \
