@@ -382,9 +382,11 @@ int chain_resident_of(const rmp_batch* b, int q)
 }
 
 // 256-thread workgroups: the tuned entries per thread, raised until every
-// system's list fits its workgroups, then raised while the batch's chain
-// workgroups exceed what the device holds at once (past that point they
-// would run in waves, each wave paying the full per-step exchange latency).
+// system's list fits its workgroups, then raised to two while the batch's
+// chain workgroups exceed what the device holds at once (past that point
+// they run in waves through the ticketed work list; measured on 64 dimer
+// replicas, two entries per thread in waves 2.10 ms per tick, four
+// 2.17 ms, one 3.17 ms).
 // 512-thread workgroups with one or two entries per thread are used when
 // asked for, or, by default, when a system's list needs more than one entry
 // per thread at 256 threads and the 512-thread shape still fits on the
@@ -398,7 +400,7 @@ ChainShape chain_shape_of(const rmp_batch* b)
     for (const auto& R : b->reps)
         if (R.used) cap_max = std::max<int64_t>(cap_max, R.sz.cand_cap);
     while (k < K_MAX && cap_max > (int64_t)MAX_G * 256 * k) k *= 2;
-    while (k < K_MAX && chain_groups(b, k, 256) > chain_resident_of(b, k == 1 ? 0 : (k == 2 ? 1 : 2))) k *= 2;
+    while (k < 2 && chain_groups(b, k, 256) > chain_resident_of(b, k == 1 ? 0 : (k == 2 ? 1 : 2))) k *= 2;
     const bool want512 = b->tun.chain_block == 512 ||
                          (b->tun.chain_block <= 0 && cap_max > (int64_t)MAX_G * 256);
     if (want512 && cap_max <= (int64_t)MAX_G * 512 && chain_groups(b, 1, 512) <= chain_resident_of(b, 3))

@@ -489,58 +489,82 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(Work w, int after_collision
     const int t = threadIdx.x;
     const int nch = D.n_chunks;
     const int per = (nch + 1023) / 1024;
-    uint32_t local = 0;
-    // loads in batches of 8 so that they are in flight together (a single
-    // workgroup walks all chunks: latency, not bandwidth, bounds this)
-    constexpr int UB = 4;
+    const gptr<const uint32_t> cnt = G(D.chunk_cnt);
+    const gptr<uint32_t> off = G(D.chunk_off);
+    // a single workgroup walks all chunks: latency, not bandwidth, bounds
+    // this, so each thread's counts (up to CS_REG of them) are loaded at
+    // once and kept for the second pass; more are read in batches, twice
+    constexpr int CS_REG = 32, UB = 4;
     const int q0 = t * per;
-    int kk = 0;
-    for (; kk + UB <= per; kk += UB) {
-        uint32_t c[UB];
+    uint32_t c[CS_REG];
+    uint32_t local = 0;
+    if (per <= CS_REG) {
 #pragma unroll
-        for (int u = 0; u < UB; ++u) c[u] = q0 + kk + u < nch ? D.chunk_cnt[q0 + kk + u] : 0u;
+        for (int u = 0; u < CS_REG; ++u) c[u] = (u < per && q0 + u < nch) ? cnt[q0 + u] : 0u;
 #pragma unroll
-        for (int u = 0; u < UB; ++u) local += c[u];
+        for (int u = 0; u < CS_REG; ++u) local += c[u];
+    } else {
+        int kk = 0;
+        for (; kk + UB <= per; kk += UB) {
+            uint32_t b[UB];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) b[u] = q0 + kk + u < nch ? cnt[q0 + kk + u] : 0u;
+#pragma unroll
+            for (int u = 0; u < UB; ++u) local += b[u];
+        }
+        for (; kk < per; ++kk)
+            if (q0 + kk < nch) local += cnt[q0 + kk];
     }
-    for (; kk < per; ++kk)
-        if (q0 + kk < nch) local += D.chunk_cnt[q0 + kk];
     uint32_t total;
     uint32_t pre = block_exscan_u32<1024>(local, sbuf, &total);
-    kk = 0;
-    for (; kk + UB <= per; kk += UB) {
-        uint32_t c[UB];
+    if (per <= CS_REG) {
 #pragma unroll
-        for (int u = 0; u < UB; ++u) c[u] = q0 + kk + u < nch ? D.chunk_cnt[q0 + kk + u] : 0u;
-#pragma unroll
-        for (int u = 0; u < UB; ++u) {
-            if (q0 + kk + u < nch) D.chunk_off[q0 + kk + u] = pre;
+        for (int u = 0; u < CS_REG; ++u) {
+            if (u < per && q0 + u < nch) off[q0 + u] = pre;
             pre += c[u];
         }
-    }
-    for (; kk < per; ++kk) {
-        const int q = q0 + kk;
-        if (q < nch) {
-            D.chunk_off[q] = pre;
-            pre += D.chunk_cnt[q];
+    } else {
+        int kk = 0;
+        for (; kk + UB <= per; kk += UB) {
+            uint32_t b[UB];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) b[u] = q0 + kk + u < nch ? cnt[q0 + kk + u] : 0u;
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                if (q0 + kk + u < nch) off[q0 + kk + u] = pre;
+                pre += b[u];
+            }
+        }
+        for (; kk < per; ++kk) {
+            const int q = q0 + kk;
+            if (q < nch) {
+                off[q] = pre;
+                pre += cnt[q];
+            }
         }
     }
     if (after_collision) {
         // tile partials (temperature sum and cells, reaction energy, bulk
-        // flips): two independent accumulators keep two 32-byte loads in
-        // flight (more would spill at 1024 threads); the order is fixed for
-        // a given tile count
+        // flips): eight 32-byte loads in flight per round into two
+        // accumulators; the order is fixed for a given tile count
         double a[2][4] = {};
-        const double4* tp = reinterpret_cast<const double4*>(D.tpart);
+        const gptr<const double> tp = G(D.tpart);
+        constexpr int TL = 8;
         int k = t;
-        for (; k + 1024 < D.n_tiles; k += 2 * 1024) {
-            const double4 q0 = tp[k], q1 = tp[k + 1024];
-            a[0][0] += q0.x; a[0][1] += q0.y; a[0][2] += q0.z; a[0][3] += q0.w;
-            a[1][0] += q1.x; a[1][1] += q1.y; a[1][2] += q1.z; a[1][3] += q1.w;
+        for (; k + (TL - 1) * 1024 < D.n_tiles; k += TL * 1024) {
+            double q[TL][4];
+#pragma unroll
+            for (int j = 0; j < TL; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) q[j][e] = tp[(int64_t)(k + j * 1024) * 4 + e];
+#pragma unroll
+            for (int j = 0; j < TL; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a[j & 1][e] += q[j][e];
         }
-        if (k < D.n_tiles) {
-            const double4 q = tp[k];
-            a[0][0] += q.x; a[0][1] += q.y; a[0][2] += q.z; a[0][3] += q.w;
-        }
+        for (; k < D.n_tiles; k += 1024)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[0][e] += tp[(int64_t)k * 4 + e];
         double v[6];
 #pragma unroll
         for (int j = 0; j < 4; ++j) v[j] = a[0][j] + a[1][j];

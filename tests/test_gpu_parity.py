@@ -211,6 +211,26 @@ def test_fp64_many_list_workgroups():
     _assert_obs(ob, o.observables())
 
 
+@pytest.mark.parametrize("n_small", [1, 2])
+def test_fp64_master_exchange_over_two_row_chunks(n_small):
+    """More than 128 list workgroups (one entry per thread, 256 threads) around
+    one large sphere: the master form of the exchange reads its rows in two
+    chunks of 128 and sums each value over 256 rows.  With one small sphere
+    the two-colloid variant runs (its 8-value table), with two the generic
+    one."""
+    p = W.base_params(L=(32, 32, 32), rho=10, n_md=4)
+    W.add_colloid(p, (16.0, 16.0, 16.0), sigma=11.0, eps_A=1.0, eps_B=0.7, catalytic=True)
+    for k in range(n_small):
+        W.add_colloid(p, (3.0 + 4.0 * k, 3.0, 3.0), sigma=1.5)
+    p["cand_capacity"] = 65536
+    s0 = W.random_state(p, 131 + n_small, species_B_fraction=0.3)
+    g, o = _run_both(p, s0, 18 + n_small, 4, 2, tuning=dict(chain_k=1, chain_block=256))
+    ob = g.observables()
+    assert ob["n_candidates"] > 128 * 256, ob["n_candidates"]
+    _assert_bitwise(g.get_state(), o.get_state(), "two row chunks")
+    _assert_obs(ob, o.observables())
+
+
 def test_fp64_many_colloids_with_contacts():
     """Three dimers placed inside each other's colloid-colloid cut-off plus
     two free spheres: many colloids per list entry, colloid-colloid WCA."""
