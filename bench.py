@@ -422,18 +422,15 @@ def fp32_drift(intervals: int, every: int, oracle_intervals: int, with_oracle: b
 
 def tune_batch_classes(precision, intervals=4):
     """Autotuned launch shapes per box class of the ensemble (one seeded
-    system per class over the autotuner's grid), written to the run's output
-    folder when there is one."""
+    system per class over the autotuner's grid, measured afresh each run)."""
     from paper_1608_04904_amd import autotune
     import workloads as W
     reps = W.batch_replicas(n=64, precision=precision)
-    cache = os.path.join(ROOT, "gpurun_out", "autotune_bench.json") if os.path.isdir(
-        os.path.join(ROOT, "gpurun_out")) else None
     best = {}
     for p in reps:
         key = autotune.box_class(p)
         if key not in best:
-            best[key] = autotune.tune(p, seed=1, intervals=intervals, cache_path=cache, force=True)
+            best[key] = autotune.tune(p, seed=1, intervals=intervals, cache_path=None, force=True)
     return best
 
 
