@@ -178,6 +178,30 @@ def tuning_from_args(args) -> dict:
     return tun
 
 
+def copy_peak_gbps(mib=2048, reps=5):
+    """Best of `reps` plain device-to-device copies of `mib` MiB, read plus
+    write bytes over the copy's event time: what a pure streaming kernel
+    reaches on this device, reported beside the nominal 8 TB/s."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / (best * 1e-3) / 1e9
+
+
 def run_single(name, precision, steps, warmup, profile_steps, tun, keep=False):
     """Time `steps` intervals of one system, then a profiled pass.  Returns a
     dict with value, wall, per-kernel averages and the roofline objects."""
@@ -590,6 +614,10 @@ def main():
         return
 
     main_r = run_single(args.workload, args.precision, args.steps, args.warmup, args.profile_steps, tun)
+    copy = copy_peak_gbps()
+    _log(f"plain device copy: {copy:.1f} GB/s")
+    main_r["roofline"].update(measured_copy_GBps=round(copy, 1), frac_of_copy=main_r["roofline"]["achieved"] / copy)
+    main_r["interval"].update(frac_of_copy=main_r["interval"]["achieved_GBps"] / copy)
     extras = {}
     if not args.no_extras and args.workload == "large128":
         other = 32 if args.precision == 64 else 64
