@@ -614,7 +614,9 @@ def main():
         return
 
     main_r = run_single(args.workload, args.precision, args.steps, args.warmup, args.profile_steps, tun)
-    copy = copy_peak_gbps()
+    # with a calibration copy asked for, the same size, so that a counter
+    # run's largest copy dispatch is the calibration copy
+    copy = copy_peak_gbps(args.calibrate_copy if args.calibrate_copy > 0 else 2048)
     _log(f"plain device copy: {copy:.1f} GB/s")
     main_r["roofline"].update(measured_copy_GBps=round(copy, 1), frac_of_copy=main_r["roofline"]["achieved"] / copy)
     main_r["interval"].update(frac_of_copy=main_r["interval"]["achieved_GBps"] / copy)

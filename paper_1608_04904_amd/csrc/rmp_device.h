@@ -28,12 +28,15 @@ __device__ __forceinline__ void g_add(gptr<uint32_t> p, uint32_t v)
 }
 
 // Philox4x64-10 (Salmon et al., SC'11): counter (a, b, c, 0), key (seed, tag).
+// ROLL keeps the ten rounds as a loop: unrolled, the key schedule is hoisted
+// into scalar registers, which the collision kernels cannot spare; the
+// MD chain keeps the unrolled form (same values either way).
+template <bool ROLL = false>
 __device__ __forceinline__ void philox(uint64_t a, uint64_t b, uint64_t c,
                                        uint64_t seed, uint64_t tag, uint64_t w[4])
 {
     uint64_t c0 = a, c1 = b, c2 = c, c3 = 0, k0 = seed, k1 = tag;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    auto round = [&]() {
         const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
         uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
         uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
@@ -42,6 +45,13 @@ __device__ __forceinline__ void philox(uint64_t a, uint64_t b, uint64_t c,
         c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
         k0 += 0x9E3779B97F4A7C15ULL;
         k1 += 0xBB67AE8584CAA73BULL;
+    };
+    if constexpr (ROLL) {
+#pragma unroll 1
+        for (int r = 0; r < 10; ++r) round();
+    } else {
+#pragma unroll
+        for (int r = 0; r < 10; ++r) round();
     }
     w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
 }
@@ -104,11 +114,12 @@ __device__ __forceinline__ void wca(double r2, double sig2, double eps, double& 
 }
 
 // Marsaglia point on the unit sphere, two tries per Philox block.
+template <bool ROLL = false>
 __device__ __forceinline__ void marsaglia_axis(uint64_t seed, uint64_t coll, uint64_t cell, double n[3])
 {
     for (uint64_t sub = 0; sub < 64; ++sub) {
         uint64_t w[4];
-        philox(coll, cell, sub, seed, TAG_ROT, w);
+        philox<ROLL>(coll, cell, sub, seed, TAG_ROT, w);
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             double a = (2.0 * u01(w[2 * t])) - 1.0;

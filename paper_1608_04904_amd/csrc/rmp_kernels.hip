@@ -2617,7 +2617,7 @@ __device__ void collide_big_cell(const RepDesc& D, const ColloidParams* cp, int 
             nB += rec_st(q) & 1;
             if constexpr (RULE == 1) {
                 uint64_t wv[4]; double z[3];
-                philox((uint64_t)coll, rec_id(q), 0, D.seed, TAG_THERMO, wv);
+                philox<true>((uint64_t)coll, rec_id(q), 0, D.seed, TAG_THERMO, wv);
                 normals3(wv, z);
                 G0 = G0 + (D.vscale * z[0]);
                 G1 = G1 + (D.vscale * z[1]);
@@ -2634,7 +2634,7 @@ __device__ void collide_big_cell(const RepDesc& D, const ColloidParams* cp, int 
         int flipk = -1;
         if (D.bulk_on && nB > 0) {
             uint64_t wv[4];
-            philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
+            philox<true>((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
             double P = D.ptable[nB < RMP_PTABLE ? nB : RMP_PTABLE - 1];
             if (u01(wv[0]) < P) {
                 int jb = (int)(u01(wv[1]) * (double)nB);
@@ -2667,7 +2667,7 @@ __device__ void collide_big_cell(const RepDesc& D, const ColloidParams* cp, int 
                 v3[0] = u0 + rw[0]; v3[1] = u1 + rw[1]; v3[2] = u2 + rw[2];
             } else {
                 uint64_t wv[4]; double z[3];
-                philox((uint64_t)coll, idq, 0, D.seed, TAG_THERMO, wv);
+                philox<true>((uint64_t)coll, idq, 0, D.seed, TAG_THERMO, wv);
                 normals3(wv, z);
                 v3[0] = u0 + ((D.vscale * z[0]) - s_n[0]);
                 v3[1] = u1 + ((D.vscale * z[1]) - s_n[1]);
@@ -2781,7 +2781,7 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
             for (int lc = t - (NT - 128); lc < ncl; lc += 64) {
                 const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : G(D.cell_of)[c0 + lc];
                 double nax[3];
-                marsaglia_axis(D.seed, (uint64_t)coll, (uint64_t)cell, nax);
+                marsaglia_axis<true>(D.seed, (uint64_t)coll, (uint64_t)cell, nax);
                 s_n[lc][0] = nax[0]; s_n[lc][1] = nax[1]; s_n[lc][2] = nax[2];
             }
         }
@@ -2790,7 +2790,7 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
             for (int lc = t - (NT - 64); lc < ncl; lc += 64) {
                 const int64_t cell = D.hbits == KEY_ROW ? c0 + lc : G(D.cell_of)[c0 + lc];
                 uint64_t wv[4];
-                philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
+                philox<true>((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_BULK, wv);
                 s_b[lc][0] = u01(wv[0]);
                 s_b[lc][1] = u01(wv[1]);
             }
@@ -2804,7 +2804,7 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
                 const int64_t cz = cell / ((int64_t)D.L[0] * D.L[1]);
                 if (cz == 0 || cz == D.L[2] - 1) {
                     uint64_t wv[4]; double z[3];
-                    philox((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_VIRT, wv);
+                    philox<true>((uint64_t)coll, (uint64_t)cell, 0, D.seed, TAG_VIRT, wv);
                     normals3(wv, z);
                     s_z[lc][0] = z[0]; s_z[lc][1] = z[1]; s_z[lc][2] = z[2];
                 }
@@ -2944,7 +2944,7 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
                 s_st[sl] = sr[u];
                 if constexpr (RULE == 1) {
                     uint64_t wv[4]; double z[3];
-                    philox((uint64_t)coll, idq[u], 0, D.seed, TAG_THERMO, wv);
+                    philox<true>((uint64_t)coll, idq[u], 0, D.seed, TAG_THERMO, wv);
                     normals3(wv, z);
                     s_g[0][sl] = D.vscale * z[0];
                     s_g[1][sl] = D.vscale * z[1];
@@ -3079,9 +3079,11 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
         // without the cull every colloid is tested
         const uint32_t cmask = cull ? s_cmask : (nc >= 32 ? 0xffffffffu : ((1u << nc) - 1u));
         const int64_t c_lo = (int64_t)q0 / CHUNK;
+        bool fl[PPT];
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
             bool cnd = false;
+            fl[u] = false;
             int64_t o = (int64_t)q0;
             if (slot[u] >= 0) {
                 const int cl = lcj[u];
@@ -3103,14 +3105,14 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
                 o = (int64_t)q0 + slot[u];
                 const bool flip = s_flip[cl] == slot[u];
                 // the position (written to the output slot in C by this
-                // thread) is read back only for a flip or a colloid within
-                // reach of the tile
+                // thread) is read back only for a colloid within reach of
+                // the tile
                 T xo3[3] = {(T)0, (T)0, (T)0};
-                if (flip || cmask != 0u)
+                if (cmask != 0u)
 #pragma unroll
                     for (int d = 0; d < 3; ++d) xo3[d] = xn[d][o];
                 if (flip) {
-                    du_sum += species_dU(D, cp, nc, s_Xw, (double)xo3[0], (double)xo3[1], (double)xo3[2], 1, 0);
+                    fl[u] = true;
                     n_flip += 1.0;
                     s = 0;
                 }
@@ -3124,6 +3126,15 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
             }
             count_flag(G(D.chunk_cnt), o, cnd, c_lo);
         }
+        // the potential change of a flipped particle, in the same order per
+        // thread, after the writes: inside their loop its colloid loop
+        // raised the register peak beyond the budget (spills to scratch)
+#pragma unroll
+        for (int u = 0; u < PPT; ++u)
+            if (fl[u]) {
+                const int64_t o = (int64_t)q0 + slot[u];
+                du_sum += species_dU(D, cp, nc, s_Xw, (double)xn[0][o], (double)xn[1][o], (double)xn[2][o], 1, 0);
+            }
         ga = gb;
         if (ga < ncl) __syncthreads();   // the next group reuses the LDS
     }
@@ -3208,7 +3219,7 @@ __global__ __launch_bounds__(256) void k_collide_big(Work w, int n_items)
             const int64_t cell = D.hbits == KEY_ROW ? c0 + ga : D.cell_of[c0 + ga];
             const uint32_t q0 = D.start[c0 + ga];
             const int nn = (int)(D.start[c0 + ga + 1] - q0);
-            if (RULE == 0 && t == 0) marsaglia_axis(D.seed, (uint64_t)coll, (uint64_t)cell, s_n);
+            if (RULE == 0 && t == 0) marsaglia_axis<true>(D.seed, (uint64_t)coll, (uint64_t)cell, s_n);
             __syncthreads();
             collide_big_cell<T, RULE, NT>(D, cp, nc, s_Xw, coll, cell, q0, nn, s_u, s_n, &s_flip,
                                           t_sum, t_cells, du_sum, n_flip);

@@ -372,19 +372,27 @@ def test_fp32_full_size_large128_one_interval_close_to_fp64():
     cells involved and so the velocities of about 2 rho = 20 particles per
     such particle (measured: 0.4 %).  The 99th percentile of the velocity
     error is within 1e-5 of the velocity scale and the affected fraction
-    below 1 %."""
+    below 1 %.  One by one: outside the cells that such particles touch,
+    every particle that streamed freely and shares its cell with no particle
+    of the colloids' list is within 1e-5; the list particles, whose FP32
+    positions enter the steep colloid potential for 50 MD steps, and their
+    cell mates within 2e-3 (measured 4.7e-4 at most, 3 % of the list beyond
+    1e-5)."""
     rm = _rm()
     p = W.large128(precision=32)
     seed = W.BASE_SEED + 3
     print("[parity] large128 fp32 full size", flush=True)
     g = rm.System(p, seed)
     s0 = g.get_state()                      # FP32 values, exact in FP64
+    s0_coll = s0["coll_step"]
     g.step(50, 1)
     gs = g.get_state()
     g.close()
     del g
     o = oracle.Oracle(dict(p, precision=64), seed, init=False)
     o.set_state(s0)
+    o.build_list(50)                        # the interval below builds the same list
+    listed_ids = s0["id"][o.candidates()]
     del s0
     o.run(50, 1)
     os_ = o.get_state()
@@ -401,6 +409,52 @@ def test_fp32_full_size_large128_one_interval_close_to_fp64():
     print(f"[parity] large128 fp32: {int(off.sum())} velocities beyond 1e-5", flush=True)
     assert np.percentile(err, 99) <= 1e-5 * vs
     assert off.mean() < 1e-2
+    # One by one: the collision is the interval's last step, so the final
+    # positions fix each particle's cell on the shifted grid.  A particle
+    # whose shifted coordinate lies within 1e-4 of a face on either side
+    # (far beyond the FP32 rounding of a coordinate near 128, 7.6e-6) or
+    # whose cell differs between the two sides marks its cells on both
+    # sides; every particle outside the marked cells shares its cell's
+    # members with the oracle.  A key that differs has a face between the
+    # two positions, so the oracle's particle lies within its own position
+    # error of that face.
+    sh = o.shift(int(s0_coll))[:, None]
+    Li = np.array(p["L"], dtype=np.int64)
+    keys, cells, near = [], [], np.zeros(gi.size, dtype=bool)
+    for xs in (gs["x"][:, gi], os_["x"][:, oi]):
+        f = xs - sh
+        near |= (np.abs(f - np.round(f)) < 1e-4).any(axis=0)
+        c = np.floor(f).astype(np.int64) % Li[:, None]
+        cells.append(c)
+        keys.append(c[0] + Li[0] * (c[1] + Li[1] * c[2]))
+    flip = keys[0] != keys[1]
+    fo = os_["x"][:, oi[flip]] - sh
+    dx = np.abs(gs["x"][:, gi[flip]] - os_["x"][:, oi[flip]])
+    dx = np.minimum(dx, L - dx)
+    cross = (cells[0][:, flip] != cells[1][:, flip]) & (np.abs(fo - np.round(fo)) <= dx + 1e-9)
+    assert (cross == (cells[0][:, flip] != cells[1][:, flip])).all()
+    print(f"[parity] large128 fp32: {int(flip.sum())} cell-face flips, "
+          f"{int(near.sum())} particles within 1e-4 of a face", flush=True)
+
+    def cells_of(sel):
+        m = np.zeros(int(Li.prod()), dtype=bool)
+        m[keys[0][sel]] = True
+        m[keys[1][sel]] = True
+        return m[keys[0]] | m[keys[1]]
+
+    clean = ~cells_of(near | flip)
+    listed = np.zeros(gi.size, dtype=bool)
+    listed[listed_ids] = True               # ids are 0 .. N-1, gi sorts by id
+    free = clean & ~cells_of(listed)
+    mixed = clean & ~free
+    print(f"[parity] large128 fp32: {int((~clean).sum())} particles in marked cells; "
+          f"free {int(free.sum())}, max error {err[free].max() / vs:.2e}; list and cell mates "
+          f"{int(mixed.sum())}, max error {err[mixed].max() / vs:.2e}, "
+          f"{int((listed & off).sum())} of {int(listed.sum())} listed beyond 1e-5", flush=True)
+    assert free.mean() > 0.9
+    assert err[free].max() <= 1e-5 * vs
+    assert err[mixed].max() <= 2e-3 * vs
+    assert (listed & off).sum() <= 0.1 * listed.sum()
     assert np.allclose(gs["X"], os_["X"], rtol=1e-6, atol=1e-6)
 
 
