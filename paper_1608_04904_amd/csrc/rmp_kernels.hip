@@ -609,6 +609,10 @@ __global__ __launch_bounds__(256) void k_cand_write(Work w)
     const int chunk = item - w.prefix[rep];
     const RepDesc& D = w.desc[rep];
     if (!D.active) return;
+    // most chunks hold no list member (the list gathers around the
+    // colloids): their flags are not read at all, and their count is zero
+    // already
+    if (D.chunk_cnt[chunk] == 0u) return;
     __shared__ uint32_t sbuf[4];
     const int64_t n = D.n;
     const int64_t base = (int64_t)chunk * CHUNK;
