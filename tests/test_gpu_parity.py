@@ -479,6 +479,13 @@ def test_errors_are_reported():
     with pytest.raises(rm.RmpError) as e:
         h.observables()
     assert e.value.flags & 16
+    # the entries beyond the capacity stream freely: every particle is still
+    # binned exactly once
+    hs = h.get_state()
+    assert np.array_equal(np.sort(hs["id"]), np.arange(hs["id"].size))
+    L = np.array(q["L"], dtype=float)[:, None]
+    assert ((hs["x"] >= 0.0) & (hs["x"] < L)).all()
+    assert np.isfinite(hs["v"]).all()
 
 
 def test_set_state_rejects_invalid_states_and_nonfinite_cell_is_flagged():
