@@ -120,6 +120,8 @@ DESCS = {
                 "bonds, iterative RATTLE), tau 0.5 (50 MD steps/collision)"),
     "poiseuille": ("poiseuille: 64 x 64 x 32 cells between plates at z = 0 and 32, rho 10, N=1,310,720, "
                    "g = 0.001 along x, tau 0.1 (10 MD steps/collision), no colloid"),
+    "solvent128": ("solvent128: 128^3 cells, rho 10, N=20,971,520, no colloid (the streaming, sort and "
+                   "collision kernels alone), tau 0.5 (50 MD steps/collision)"),
 }
 
 
@@ -129,6 +131,10 @@ def workload(name: str, precision: int):
           "poiseuille": (W.poiseuille, 10, 5)}
     if name == "janus32":
         return W.janus_system(L=32, rho=10, n_md=50, precision=precision), 50, W.BASE_SEED + 6, DESCS[name]
+    if name == "solvent128":
+        p = W.base_params(L=(128, 128, 128), rho=10, dt=0.01, n_md=50, precision=precision)
+        p["name"] = name
+        return p, 50, W.BASE_SEED + 7, DESCS[name]
     if name not in mk:
         raise SystemExit(f"unknown workload {name}")
     f, n_md, k = mk[name]
@@ -552,7 +558,8 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="large128",
-                    choices=["large128", "dimer32", "sphere10", "poiseuille", "janus32", "batch", "serve"])
+                    choices=["large128", "dimer32", "sphere10", "poiseuille", "janus32", "solvent128", "batch",
+                             "serve"])
     ap.add_argument("--precision", type=int, default=64)
     ap.add_argument("--profile-steps", type=int, default=6)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
