@@ -3050,7 +3050,11 @@ __global__ __launch_bounds__(NT, (PPT == 1 || sizeof(T) == 4) ? 5 : 4) void k_co
             // sphere, widened by the largest speed times tau, meets the
             // tile's box (minimum image per axis, margin far above rounding)
             bool near = false;
-            const int c = t - 64;
+            // c is made opaque here so that the per-thread addresses below
+            // are formed inside the group loop: hoisted out of it, they were
+            // held across the whole tile and spilled to scratch (FP32 form)
+            int c = t - 64;
+            asm volatile("" : "+v"(c));
             if (c < nc) {
                 const double vmax2 = __longlong_as_double((long long)s_vmax2);
                 const double reach = ((3.0 * sqrt(vmax2)) * D.tau + cp->reachR[c]) * (1.0 + 1e-6) + 1e-6;
